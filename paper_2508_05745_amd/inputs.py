@@ -1,0 +1,211 @@
+"""Seeded synthetic inputs shared by the HIP path, the tests and the benchmark.
+
+This module only *describes problems*: random two-qubit gates, single-qubit channels given
+by their Kraus operators, brickwork circuit tables and random two-site states.  It holds
+none of the simulation method's arithmetic (no unravelling, no contraction, no sampling).
+
+Conventions (both the oracle and the HIP path read them from here):
+
+* qubit ``q`` of an ``n``-qubit chain is MPS site ``q``; in a dense state vector qubit 0 is
+  the most significant bit.
+* a two-qubit gate on the pair ``(q, q+1)`` is a 4x4 matrix on the basis index ``2*s + t``
+  with ``s`` the state of qubit ``q`` and ``t`` that of qubit ``q+1``.
+* brickwork layer ``l`` (0-based) acts on the pairs ``(p, p+1), (p+2, p+3), ...`` with
+  ``p = l % 2``; the first layer therefore starts at qubit 0.
+* a channel is a stack ``[r][2][2]`` of Kraus operators (r <= 4).  Noise events are listed
+  per ``(layer, qubit)`` as an index into the channel table, -1 meaning no noise.
+
+Channel parametrisations follow the paper's section on common unravelings (depolarizing
+with rate p, dephasing with rate p, amplitude damping with rate gamma).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+# ----------------------------------------------------------------------------- gates
+
+
+def haar_unitary(rng: np.random.Generator, d: int = 4) -> np.ndarray:
+    """Haar-random d x d unitary: QR of a complex Ginibre matrix with the phases of R's
+    diagonal moved into Q (Mezzadri's recipe)."""
+    z = (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    ph = np.diag(r) / np.abs(np.diag(r))
+    return (q * ph[None, :]).astype(np.complex128)
+
+
+# ----------------------------------------------------------------------------- channels
+
+_I = np.eye(2, dtype=np.complex128)
+_X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+_Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+_Z = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+
+
+def depolarizing(p: float) -> np.ndarray:
+    """rho -> (1-p) rho + p I/2 as the four rescaled Paulis."""
+    return np.stack([np.sqrt(1 - 3 * p / 4) * _I, np.sqrt(p) / 2 * _X,
+                     np.sqrt(p) / 2 * _Y, np.sqrt(p) / 2 * _Z])
+
+
+def dephasing(p: float) -> np.ndarray:
+    """rho -> (1-p/2) rho + (p/2) Z rho Z (mixed-unitary form)."""
+    return np.stack([np.sqrt(1 - p / 2) * _I, np.sqrt(p / 2) * _Z])
+
+
+def amplitude_damping(gamma: float) -> np.ndarray:
+    """The usual two-operator form diag(1, sqrt(1-gamma)), sqrt(gamma)|0><1|."""
+    k0 = np.array([[1, 0], [0, np.sqrt(1 - gamma)]], dtype=np.complex128)
+    k1 = np.array([[0, np.sqrt(gamma)], [0, 0]], dtype=np.complex128)
+    return np.stack([k0, k1])
+
+
+def compose(first: np.ndarray, second: np.ndarray) -> np.ndarray:
+    """Kraus set of ``second o first``: all products K2_j K1_i (j major)."""
+    return np.stack([k2 @ k1 for k2 in second for k1 in first])
+
+
+# ----------------------------------------------------------------------------- circuits
+
+
+def layer_pairs(n: int, layer: int) -> List[int]:
+    """Left qubits of the pairs acted on by brickwork layer ``layer``."""
+    p = layer % 2
+    return list(range(p, n - 1, 2))
+
+
+@dataclasses.dataclass
+class Circuit:
+    """A noisy brickwork circuit on an open chain.
+
+    gates:    [depth][max_pairs][4][4] complex128; slot i of layer l is the pair
+              (p + 2i, p + 2i + 1) with p = l % 2.
+    channels: [n_channels][4][2][2] complex128, Kraus stacks zero-padded to 4.
+    n_kraus:  [n_channels] number of meaningful Kraus operators per channel.
+    events:   [depth][n] int32 channel id of the noise applied to qubit q in layer l
+              (-1 = none).  Noise on a gate's qubits follows that gate; noise on an idle
+              qubit is applied when the sweep passes it.
+    """
+    n: int
+    depth: int
+    gates: np.ndarray
+    channels: np.ndarray
+    n_kraus: np.ndarray
+    events: np.ndarray
+    name: str = ""
+
+    def pairs(self, layer: int) -> List[int]:
+        return layer_pairs(self.n, layer)
+
+    def gate(self, layer: int, q: int) -> np.ndarray:
+        return self.gates[layer, (q - layer % 2) // 2]
+
+    def kraus(self, ch: int) -> np.ndarray:
+        return self.channels[ch, : self.n_kraus[ch]]
+
+    @property
+    def n_gates(self) -> int:
+        return sum(len(self.pairs(l)) for l in range(self.depth))
+
+
+def _pad_channels(chs: List[np.ndarray]):
+    tab = np.zeros((len(chs), 4, 2, 2), dtype=np.complex128)
+    nk = np.zeros(len(chs), dtype=np.int32)
+    for i, k in enumerate(chs):
+        if k.shape[0] > 4:
+            raise ValueError("at most 4 Kraus operators per channel")
+        tab[i, : k.shape[0]] = k
+        nk[i] = k.shape[0]
+    return tab, nk
+
+
+def brickwork(n: int, depth: int, seed: int, channel: np.ndarray, idle_noise: bool = False,
+              name: str = "") -> Circuit:
+    """Haar-random brickwork circuit; ``channel`` hits both qubits after every gate (and, if
+    ``idle_noise``, also every qubit left idle by a layer)."""
+    rng = np.random.default_rng(seed)
+    max_pairs = n // 2
+    gates = np.zeros((depth, max_pairs, 4, 4), dtype=np.complex128)
+    events = np.full((depth, n), -1, dtype=np.int32)
+    for l in range(depth):
+        for i, q in enumerate(layer_pairs(n, l)):
+            gates[l, i] = haar_unitary(rng, 4)
+            events[l, q] = 0
+            events[l, q + 1] = 0
+        if idle_noise:
+            events[l, :] = 0
+    tab, nk = _pad_channels([channel])
+    return Circuit(n=n, depth=depth, gates=gates, channels=tab, n_kraus=nk, events=events,
+                   name=name)
+
+
+def noiseless_copy(c: Circuit) -> Circuit:
+    """Same gates, no noise events."""
+    return dataclasses.replace(c, events=np.full_like(c.events, -1))
+
+
+# ----------------------------------------------------------------------------- configs
+
+
+@dataclasses.dataclass
+class Workload:
+    circuit: Circuit
+    chi: int
+    n_traj: int
+    seed: int          # trajectory seed (branch sampling)
+    name: str
+
+
+def config_small_exact() -> Workload:
+    """10-qubit chain, depth 10, depolarizing p=0.01 after each gate, chi=32 (exact),
+    1000 trajectories."""
+    c = brickwork(10, 10, seed=1001, channel=depolarizing(0.01), name="n10_d10_dep0.01")
+    return Workload(c, chi=32, n_traj=1000, seed=2001, name="n10-d10-dep0.01-chi32-1000traj")
+
+
+def config_ad_dephasing() -> Workload:
+    """32-qubit chain, depth 20, amplitude damping 0.005 then dephasing 0.005 on every
+    qubit in every layer, chi=64, 4096 trajectories."""
+    ch = compose(amplitude_damping(0.005), dephasing(0.005))
+    c = brickwork(32, 20, seed=1002, channel=ch, idle_noise=True, name="n32_d20_ad_df")
+    return Workload(c, chi=64, n_traj=4096, seed=2002, name="n32-d20-ad0.005-df0.005-chi64-4096traj")
+
+
+def config_wide(chi: int = 128, n_traj: int = 2048) -> Workload:
+    """100-qubit chain, depth 40, depolarizing p=0.02 after each gate (the chi=128 and
+    chi=256 workloads share this circuit)."""
+    c = brickwork(100, 40, seed=1005, channel=depolarizing(0.02), name="n100_d40_dep0.02")
+    return Workload(c, chi=chi, n_traj=n_traj, seed=2005,
+                    name=f"n100-d40-dep0.02-chi{chi}-{n_traj}traj")
+
+
+def random_two_site_states(count: int, chi_l: int, chi_r: int, seed: int,
+                           dtype=np.complex64) -> np.ndarray:
+    """``count`` complex Gaussian two-site tensors theta[a][s][t][b], each normalised to
+    unit Frobenius norm (layout chi_l x 2 x 2 x chi_r)."""
+    rng = np.random.default_rng(seed)
+    shape = (count, chi_l, 2, 2, chi_r)
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    x /= np.sqrt(np.sum(np.abs(x) ** 2, axis=(1, 2, 3, 4), keepdims=True))
+    return x.astype(dtype)
+
+
+def random_mixing_params(count: int, seed: int, scale: float = 0.1) -> np.ndarray:
+    """``count`` x 16 real parameters of a U(4) mixing, N(0, scale^2)."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, scale, size=(count, 16))
+
+
+def random_density_matrices(count: int, seed: int, rank: Optional[int] = None) -> np.ndarray:
+    """Random single-qubit density matrices (rank 1 or 2), for unravelling tests."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((count, 2, 2), dtype=np.complex128)
+    for i in range(count):
+        r = rank if rank is not None else 2
+        g = rng.standard_normal((2, r)) + 1j * rng.standard_normal((2, r))
+        m = g @ g.conj().T
+        out[i] = m / np.trace(m).real
+    return out

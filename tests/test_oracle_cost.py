@@ -1,0 +1,67 @@
+"""Pins of the unravelling cost and its reference gradient (no GPU)."""
+import numpy as np
+import pytest
+
+from oracle import cost as CO
+from oracle import unravel as U
+from paper_2508_05745_amd import inputs as I
+
+
+def _u_opt(rho, k):
+    w = U.optimal_mixing(rho, k)["W"]
+    return w.T.copy()     # K'_j = sum_i U_ji K_i  <=>  U = W^T
+
+
+def test_generators_are_a_hermitian_basis():
+    g = CO.generators()
+    assert np.allclose(g, np.conj(np.transpose(g, (0, 2, 1))))
+    m = g.reshape(16, 16)
+    assert np.linalg.matrix_rank(np.concatenate([m.real, m.imag], axis=1)) == 16
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_linear_cost_minimum_is_half_concurrence_squared(seed):
+    """At the Wootters mixing every branch has concurrence C, so f_lin = C^2 / 2; any other
+    mixing costs at least that (convexity of c^2/2 and sum_j p_j c_j >= C)."""
+    k = I.depolarizing(0.02 + 0.05 * seed)
+    rho = I.random_density_matrices(1, 40 + seed)[0]
+    out = U.optimal_mixing(rho, k)
+    uo = _u_opt(rho, k)
+    f = CO.cost(rho, k, uo, CO.KIND_LINEAR)
+    assert f == pytest.approx(out["C"] ** 2 / 2, abs=1e-12)
+    rng = np.random.default_rng(seed)
+    for _ in range(50):
+        assert CO.cost(rho, k, I.haar_unitary(rng, 4), CO.KIND_LINEAR) >= f - 1e-12
+
+
+@pytest.mark.parametrize("kind", [CO.KIND_LINEAR, CO.KIND_RENYI2])
+def test_gradient_vanishes_at_optimum(kind):
+    k = I.depolarizing(0.02)
+    rho = I.random_density_matrices(1, 7)[0]
+    uo = _u_opt(rho, k)
+    f, g = CO.grad_torch(rho, k, np.zeros(16), uo, kind)
+    assert np.abs(g).max() < 1e-8
+    assert np.abs(CO.grad_fd(rho, k, np.zeros(16), uo, kind)).max() < 1e-7
+
+
+@pytest.mark.parametrize("kind", [CO.KIND_LINEAR, CO.KIND_RENYI2])
+def test_autograd_matches_finite_differences(kind):
+    rng = np.random.default_rng(3)
+    k = I.depolarizing(0.02)
+    for t in range(4):
+        rho = I.random_density_matrices(1, 60 + t)[0]
+        params = rng.normal(0, 0.1, 16)
+        uref = I.haar_unitary(rng, 4)
+        f, g = CO.grad_torch(rho, k, params, uref, kind)
+        assert f == pytest.approx(CO.cost_params(rho, k, params, uref, kind), abs=1e-13)
+        gfd = CO.grad_fd(rho, k, params, uref, kind)
+        assert np.linalg.norm(g - gfd) <= 1e-6 * np.linalg.norm(g) + 1e-8
+
+
+def test_rho_from_theta_is_reduced_state():
+    th = I.random_two_site_states(3, 4, 5, seed=1, dtype=np.complex128)
+    for t in th:
+        r = CO.rho_from_theta(t)
+        psi = t.transpose(1, 0, 2, 3).reshape(2, -1)      # target index first
+        assert np.allclose(r, psi @ psi.conj().T, atol=1e-15)
+        assert abs(np.trace(r) - 1) < 1e-14

@@ -1,0 +1,101 @@
+"""Pins of the oracle's density-matrix, statevector and MPS trajectory code (no GPU)."""
+import numpy as np
+import pytest
+
+from oracle import dm, kraus_tree, mps, sv, unravel as U
+from paper_2508_05745_amd import inputs as I
+
+
+def test_density_matrix_is_a_state():
+    c = I.brickwork(5, 4, seed=3, channel=I.depolarizing(0.1), idle_noise=True)
+    rho = dm.run(c)
+    assert abs(np.trace(rho) - 1) < 1e-13
+    assert np.allclose(rho, rho.conj().T, atol=1e-14)
+    assert np.linalg.eigvalsh(rho).min() > -1e-13
+
+
+def test_density_matrix_two_qubit_hand_case():
+    """One gate then depolarizing on both qubits: (D x D)(G|00><00|G^dag) with the
+    depolarizing map D(X) = (1-p) X + p Tr_q(X) I/2 written out."""
+    p = 0.2
+    c = I.brickwork(2, 1, seed=4, channel=I.depolarizing(p))
+    g = c.gate(0, 0)
+    psi = g[:, 0]
+    r = np.outer(psi, psi.conj()).reshape(2, 2, 2, 2)
+    r = (1 - p) * r + p * np.einsum("ab,cxcy->axby", np.eye(2) / 2, r)
+    r = (1 - p) * r + p * np.einsum("xy,acbc->axby", np.eye(2) / 2, r)
+    assert np.allclose(dm.run(c), r.reshape(4, 4), atol=1e-14)
+
+
+@pytest.mark.parametrize("mode", [U.MODE_OPTIMAL, U.MODE_ORTHOGONAL, U.MODE_FIXED])
+def test_kraus_tree_average_is_exact_state(mode):
+    """Without approximation the Kraus-tree average equals rho for any unravelling."""
+    fixed = U.H4.real if mode == U.MODE_FIXED else None
+    c = I.brickwork(3, 2, seed=5, channel=I.depolarizing(0.1))
+    assert np.abs(kraus_tree.average_state(c, mode, fixed) - dm.run(c)).max() < 1e-13
+    c2 = I.brickwork(3, 2, seed=6, channel=I.compose(I.amplitude_damping(0.2),
+                                                    I.dephasing(0.3)), idle_noise=True)
+    if mode != U.MODE_FIXED:
+        assert np.abs(kraus_tree.average_state(c2, mode) - dm.run(c2)).max() < 1e-13
+
+
+@pytest.mark.parametrize("mode", [U.MODE_ORTHOGONAL, U.MODE_OPTIMAL])
+def test_untruncated_mps_equals_statevector(mode):
+    """Same seeds, no truncation: identical branch choices, fidelity 1 to 1e-12 and
+    equal observables (OPTIMAL: the statevector replays the MPS's mixings, which it checks
+    for optimality on its own reduced states)."""
+    c = I.brickwork(8, 6, seed=7, channel=I.compose(I.amplitude_damping(0.05),
+                                                   I.dephasing(0.05)), idle_noise=True)
+    for traj in range(3):
+        rec = []
+        m, eps = mps.trajectory(c, 16, traj, 99, mode=mode, record=rec)
+        rp = sv.Replay([r["W"] for r in rec]) if mode == U.MODE_OPTIMAL else None
+        rec2 = []
+        psi = sv.trajectory(c, traj, 99, mode=mode, record=rec2, replay=rp)
+        v = m.to_vector()
+        assert [a["j"] for a in rec] == [b["j"] for b in rec2]
+        assert 1 - abs(np.vdot(psi, v)) ** 2 < 1e-12
+        assert max(eps) < 1e-14
+        zi, zz = sv.z_expectations(psi, 8)
+        zi2, zz2 = mps.z_expectations(m)
+        assert np.abs(zi - zi2).max() < 1e-12 and np.abs(zz - zz2).max() < 1e-12
+        if rp is not None:
+            assert rp.max_gap < 1e-12 and rp.max_incomplete < 1e-12
+
+
+def test_norm_preserved_and_truncation_weight():
+    c = I.brickwork(10, 8, seed=8, channel=I.depolarizing(0.02))
+    m, eps = mps.trajectory(c, 4, 0, 5)
+    assert abs(np.linalg.norm(m.to_vector()) - 1) < 1e-12
+    assert max(eps) > 1e-6
+    assert max(m.bond_dims()) <= 4
+
+
+def test_single_bond_eckart_young():
+    """Truncating one bond: ||psi - P psi||^2 equals the discarded weight."""
+    rng = np.random.default_rng(9)
+    psi = rng.standard_normal(64) + 1j * rng.standard_normal(64)
+    psi /= np.linalg.norm(psi)
+    mat = psi.reshape(8, 8)
+    u, s, vh = np.linalg.svd(mat)
+    d = 3
+    proj = (u[:, :d] * s[:d]) @ vh[:d]
+    eps = np.sum(s[d:] ** 2)
+    assert np.linalg.norm(mat - proj) ** 2 == pytest.approx(eps, abs=1e-14)
+
+
+def test_trajectory_average_matches_density_matrix():
+    """Statistical agreement of 400 trajectories with the exact state (within 4 sigma
+    per observable)."""
+    c = I.brickwork(5, 4, seed=10, channel=I.depolarizing(0.2))
+    zi_ex, zz_ex = dm.z_expectations(dm.run(c), 5)
+    vals = []
+    for t in range(400):
+        m, _ = mps.trajectory(c, 8, t, 77)
+        zi, zz = mps.z_expectations(m)
+        vals.append(np.concatenate([zi, zz]))
+    vals = np.array(vals)
+    mean = vals.mean(0)
+    se = vals.std(0, ddof=1) / np.sqrt(len(vals)) + 1e-12
+    z = np.abs(mean - np.concatenate([zi_ex, zz_ex])) / se
+    assert z.max() < 4.5
