@@ -1,0 +1,191 @@
+/*
+ * mpsb: batched Monte Carlo simulation of noisy 1D brickwork circuits with matrix-product-
+ * state trajectories and locally entanglement-optimal unravelings (arXiv 2508.05745),
+ * native to AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  All functions return 0 (MPSB_OK) on success and a negative MPSB_E* code on
+ * failure; a thread-local message is available from mps_last_error().  Arguments are
+ * validated on the host before any device work is enqueued, so a failing call leaves its
+ * outputs untouched.  Errors raised by the device (asynchronous) surface at the next call
+ * on the same handle or at mps_batch_sync().
+ *
+ * Memory ownership: the library never allocates device memory.  The caller provides the
+ * state and work buffers (sizes from mps_batch_plan) and every input/output buffer; they
+ * must outlive the handle.  Pointers documented as "device" must be device-accessible
+ * (hipMalloc / torch CUDA tensors); "host" pointers are ordinary host memory.  All device
+ * work is enqueued on the stream given at creation (a hipStream_t passed as void*, NULL =
+ * the default stream); calls return without waiting for it unless stated otherwise.
+ *
+ * Complex numbers are stored interleaved (re, im).  "c128" = two doubles, "c64" = two
+ * floats.
+ */
+#ifndef MPSB_H
+#define MPSB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define MPSB_OK 0
+#define MPSB_EINVAL -1  /* bad shape or argument, non-unitary gate                     */
+#define MPSB_ENOMEM -2  /* caller buffer too small / sizes beyond the supported maxima  */
+#define MPSB_EHIP -3    /* a HIP runtime call failed                                   */
+#define MPSB_ENOTSUP -4 /* combination not supported by this build                      */
+#define MPSB_ENUM -5    /* non-finite value, or a forced branch with zero probability  */
+#define MPSB_EKRAUS -6  /* Kraus set not trace preserving (sum K^dag K != I)            */
+
+/* ------------------------------------------------------------------ enums */
+#define MPSB_FP32_BULK 0 /* site tensors c64, contractions FP32 (FP32 accumulation);
+                            eigen-solves, unravelling, probabilities, observables FP64 */
+#define MPSB_FP64 1      /* everything complex128 / FP64                                */
+
+/* Unravelling (choice of Kraus decomposition, eq. unitarity_kraus).  The mixed operators
+ * are K'_j = sum_i U[j][i] K_i, j = 0..3 (always four outputs, some possibly zero). */
+#define MPSB_ORTHOGONAL 0 /* the channel's own operators (U = identity, zero-padded)     */
+#define MPSB_FIXED 1      /* a caller-given, state-independent 4 x r mixing U           */
+#define MPSB_OPTIMAL 3    /* locally entanglement-optimal mixing (Thm. 2: Wootters'
+                             decomposition of the effective two-qubit state)            */
+
+#define MPSB_MAX_CHI 256      /* largest supported bond dimension                       */
+#define MPSB_MAX_QUBITS 4096
+#define MPSB_MAX_CHANNELS 16
+
+typedef struct mpsb_batch* mpsb_handle;
+
+/* Noisy brickwork circuit (the classical description D of the paper's truncated
+ * trajectory sampling task: qubit order = chain order, initial state |0...0>, a string
+ * of layers of two-qubit gates composed with single-qubit noise).  Host pointers; the
+ * library copies everything it needs during mps_batch_set_circuit.
+ *
+ *   layer l (0-based) acts on the pairs (p, p+1), (p+2, p+3), ... with p = l % 2;
+ *   gates  [depth][n_qubits/2][4][4] c128: slot i of layer l is the pair (p+2i, p+2i+1),
+ *          basis index 2*s + t with s the lower qubit of the pair;
+ *   kraus  [n_channels][4][2][2] c128, zero padded; n_kraus[c] in 1..4 operators used;
+ *   events [depth][n_qubits] int32: channel applied to qubit q in layer l, -1 = none.
+ *          Noise on a gate's qubits follows that gate (lower qubit first); noise on an
+ *          idle qubit is applied when the layer's sweep reaches it;
+ *   fixed_u [n_channels][4][4] c128 (row j = output operator), used with MPSB_FIXED.
+ */
+typedef struct {
+    int depth;
+    const double* gates;
+    int n_channels;
+    const double* kraus;
+    const int32_t* n_kraus;
+    const int32_t* events;
+    int unravel_mode;
+    const double* fixed_u; /* may be NULL unless unravel_mode == MPSB_FIXED */
+} mpsb_circuit;
+
+/* Sizes of the two caller buffers for n_traj trajectories of an n_qubits chain truncated
+ * to bond dimension chi (1..MPSB_MAX_CHI).  Bond k (between qubits k and k+1) has the fixed
+ * capacity min(chi, 2^(k+1), 2^(n-k-1)).  precision: MPSB_FP32_BULK or MPSB_FP64.
+ * Returns MPSB_EINVAL for bad arguments. */
+int mps_batch_plan(int n_traj, int n_qubits, int chi, int precision, size_t* state_bytes,
+                   size_t* work_bytes);
+
+/* Creates a batch in |0...0> with the orthogonality centre at qubit 0.  state_buf /
+ * work_buf: device buffers of at least the planned sizes (256-byte aligned); seed keys the
+ * counter-based branch sampler (SplitMix64 output number 1 + (traj<<32 | layer<<16 |
+ * qubit)).  The initial state is written asynchronously on `stream`. */
+int mps_batch_create(int n_traj, int n_qubits, int chi, int precision, uint64_t seed,
+                     void* state_buf, size_t state_bytes, void* work_buf, size_t work_bytes,
+                     void* stream, mpsb_handle* out);
+
+/* Copies and validates the circuit: every Kraus set must satisfy
+ * ||sum_i K_i^dag K_i - I||_max <= 1e-12 (else MPSB_EKRAUS), every gate
+ * ||G^dag G - I||_max <= 1e-12 (else MPSB_EINVAL), event ids must name a channel or be
+ * -1, FIXED mixings must be unitary on the used columns. */
+int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c);
+
+/* Applies brickwork layer `layer` (0 <= layer < depth) to every trajectory: for each pair
+ * in sweep order (left to right for even layers, right to left for odd layers) the two-
+ * site contraction with the gate, the noise events of the pair (unravel, draw, apply the
+ * sampled Kraus operator; Alg. 1), truncation of the pair's bond to its capacity with
+ * renormalisation, and the move of the orthogonality centre to the next pair; idle-qubit
+ * noise when the sweep reaches the qubit.  Layers must be applied in order 0, 1, 2, ...
+ * Optional device outputs (NULL to skip):
+ *   discarded [n_traj][n_qubits/2] FP64: discarded weight sum_{i>D} lambda_i / sum_i
+ *             lambda_i of each gate (slot i = pair p+2i; untouched slots are set to 0);
+ *   branch    [n_traj][n_qubits] int32: sampled branch of the event on each qubit (-1 =
+ *             no event);
+ *   w_record  [n_traj][n_qubits][4][4] c128: the mixing U used by each event (K'_j =
+ *             sum_i U[j][i] K_i), rows j, columns i (unused columns zero). */
+int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch,
+                double* w_record);
+
+/* Channel-unravelling subprocedure (Alg. 1) for one noise event per trajectory on qubit
+ * qubit[t] (host array [n_traj], the centre is moved there first) with channel
+ * `channel`, mode `unravel_mode` (MPSB_FIXED uses the circuit's fixed_u).  forced: host
+ * array [n_traj] of branch indices, -1 = draw with the sampler keyed by (traj,
+ * rng_layer, qubit[t]); a forced branch of zero probability fails with MPSB_ENUM before
+ * the state is changed.  Device outputs (NULL to skip): branch [n_traj] int32,
+ * p [n_traj][4] FP64. */
+int sample_kraus(mpsb_handle h, const int32_t* qubit, int channel, int unravel_mode,
+                 int rng_layer, const int32_t* forced, int32_t* branch, double* p);
+
+/* Approximation subprocedure on demand (Sec. "Class of Truncated Trajectory Sampling
+ * Algorithms"): truncates every bond to min(chi, capacity) with a full left-to-right sweep
+ * (discarding the smallest Schmidt values, renormalising), then moves the centre back to
+ * qubit 0; discarded [n_traj] FP64 device (or NULL) receives the summed discarded weight
+ * of the sweep.  1 <= chi <= the batch's chi.  (Named mps_truncate rather than truncate so
+ * that it does not collide with the POSIX truncate(2) declaration.) */
+int mps_truncate(mpsb_handle h, int chi, double* discarded);
+
+/* Host-only validation of a circuit for an n_qubits chain: the checks of
+ * mps_batch_set_circuit, without a handle or a device. */
+int mps_circuit_validate(int n_qubits, const mpsb_circuit* c);
+
+/* Observables of every trajectory: <Z_i> (i = 0..n-1) then <Z_i Z_{i+1}> (i = 0..n-2),
+ * computed in FP64 with left/right environments (normalised by <psi|psi>).  Device
+ * outputs: mean [2n-1] and m2 [2n-1] (sum of squared deviations) over trajectories,
+ * reduced in a fixed order (bitwise reproducible); per_traj [n_traj][2n-1] (or NULL). */
+int expect(mpsb_handle h, double* mean, double* m2, double* per_traj);
+
+/* Blocks until all work of the handle is done; reports asynchronous device errors. */
+int mps_batch_sync(mpsb_handle h);
+int mps_batch_destroy(mpsb_handle h);
+const char* mps_last_error(void);
+
+/* Batched locally entanglement-optimal unravelling (Sec. "Locally entanglement-optimal
+ * unraveling"; appendix "Practical/closed-form version" of Wootters' decomposition): for
+ * each of `batch` qubits with normalised reduced state rho_q [batch][2][2] c128 and the
+ * channel kraus [n_k][r][2][2] c128 (channel of item b = kraus_id[b], or 0 if kraus_id is
+ * NULL; r in 1..4), returns U [batch][4][r] c128 (K'_j = sum_i U[j][i] K_i; rows
+ * orthonormal so the K'_j are a complete Kraus set), the branch weights p [batch][4]
+ * (FP64) and the entanglement of formation eof [batch] reached by the decomposition.
+ * All pointers are device pointers; n_k <= MPSB_MAX_CHANNELS. */
+int unravel_opt(int batch, const double* rho_q, const double* kraus, int n_k,
+                const int32_t* kraus_id, int r, double* U, double* p, double* eof,
+                void* stream);
+
+/* Expected entanglement of an unravelling, as a function of the mixing (differentiable
+ * cost): for `batch` two-site tensors theta [batch][chi_l][2][2][chi_r] (c64 when prec ==
+ * MPSB_FP32_BULK, c128 when MPSB_FP64; noise on the first physical index) the reduced
+ * state rho_q = sum_{a,t,b} theta[a,s,t,b] conj(theta[a,s',t,b]) is formed (FP64
+ * accumulation) and written to rho_out [batch][2][2] c128, then
+ *   kind 0: f = sum_j p_j (1 - Tr sigma_j^2)   (linear entropy)
+ *   kind 1: f = sum_j p_j (-log2 Tr sigma_j^2) (Renyi-2)
+ * with sigma_j = K'_j rho_q K'_j^dag / p_j, K'_j = sum_i U_ji K_i, U = exp(i sum_k
+ * params[k] L_k) U_ref, the 16 generators L_k being E_kk (k<4), then for the pairs
+ * (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) the symmetric E_jk + E_kj and the antisymmetric
+ * i(E_kj - E_jk).  kraus [4][2][2] c128 (zero padded), params [batch][16] FP64, u_ref
+ * [batch][4][4] c128, f_out [batch] FP64.  Device pointers. */
+int unravel_cost(int batch, const void* theta, int chi_l, int chi_r, int prec,
+                 const double* kraus, const double* params, const double* u_ref, int kind,
+                 double* f_out, double* rho_out, void* stream);
+
+/* Adjoint of unravel_cost with respect to the 16 mixing parameters (theta is not
+ * re-read): grad_out [batch][16] = grad_f[b] * d f_b / d params_b.  Device pointers. */
+int unravel_cost_grad(int batch, const double* rho_q, const double* kraus,
+                      const double* params, const double* u_ref, int kind,
+                      const double* grad_f, double* grad_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPSB_H */

@@ -1,0 +1,427 @@
+// Batched complex contractions of the gate-step: the generic strided GEMM used for the
+// Gram matrices, recomposition, centre hops and environments, the two-site theta
+// contraction with the gate and two-site reduced density matrix fused in its epilogue, the
+// in-place application of the sampled Kraus pair, and small cast/scale helpers.
+#include "common.h"
+#include "kernels.h"
+
+namespace mpsb {
+
+// ============================================================================ generic GEMM
+// C[b] = alpha[b] * op(A[b]) * op(B[b]);  op = N (row-major M x K, ld) or
+// C (conjugate transpose of a row-major K x M matrix).  64x64 tiles, BK = 16, 256 threads,
+// 4x4 complex accumulators per thread, LDS staging as separate re/im planes.
+constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+
+template <typename T> struct Ld;
+template <> struct Ld<float> { using C = c32; };
+template <> struct Ld<double> { using C = c64d; };
+
+template <typename TA, typename TB, typename TACC, typename TC, bool CA, bool CB>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const cplx<TA>* __restrict__ A,
+                                              int lda, long long sA, const cplx<TB>* __restrict__ B,
+                                              int ldb, long long sB, cplx<TC>* __restrict__ C, int ldc,
+                                              long long sC, const double* __restrict__ alpha) {
+  __shared__ TACC As_re[GB_K][GB_M + 4], As_im[GB_K][GB_M + 4];
+  __shared__ TACC Bs_re[GB_K][GB_N + 4], Bs_im[GB_K][GB_N + 4];
+  const int bz = blockIdx.z;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  TACC acc_re[4][4], acc_im[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc_re[i][j] = acc_im[i][j] = 0;
+
+  for (int k0 = 0; k0 < K; k0 += GB_K) {
+    // ---- stage A tile: op(A)[m][k], m in [m0, m0+64), k in [k0, k0+16)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int e = tid + 256 * r;
+      int mm, kk;
+      if (!CA) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
+      int m = m0 + mm, k = k0 + kk;
+      cplx<TA> v = {0, 0};
+      if (m < M && k < K) {
+        if (!CA) v = A[(long long)m * lda + k];
+        else { v = A[(long long)k * lda + m]; v.im = -v.im; }
+      }
+      As_re[kk][mm] = (TACC)v.re;
+      As_im[kk][mm] = (TACC)v.im;
+    }
+    // ---- stage B tile: op(B)[k][n]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int e = tid + 256 * r;
+      int nn, kk;
+      if (!CB) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
+      int n = n0 + nn, k = k0 + kk;
+      cplx<TB> v = {0, 0};
+      if (n < N && k < K) {
+        if (!CB) v = B[(long long)k * ldb + n];
+        else { v = B[(long long)n * ldb + k]; v.im = -v.im; }
+      }
+      Bs_re[kk][nn] = (TACC)v.re;
+      Bs_im[kk][nn] = (TACC)v.im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GB_K; ++kk) {
+      TACC ar[4], ai[4], br[4], bi[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { ar[i] = As_re[kk][ty + 16 * i]; ai[i] = As_im[kk][ty + 16 * i]; }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) { br[j] = Bs_re[kk][tx + 16 * j]; bi[j] = Bs_im[kk][tx + 16 * j]; }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc_re[i][j] += ar[i] * br[j] - ai[i] * bi[j];
+          acc_im[i][j] += ar[i] * bi[j] + ai[i] * br[j];
+        }
+    }
+    __syncthreads();
+  }
+  const double al = alpha ? alpha[bz] : 1.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int m = m0 + ty + 16 * i;
+    if (m >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int n = n0 + tx + 16 * j;
+      if (n >= N) continue;
+      cplx<TC> o;
+      o.re = (TC)(al * (double)acc_re[i][j]);
+      o.im = (TC)(al * (double)acc_im[i][j]);
+      C[(long long)m * ldc + n] = o;
+    }
+  }
+}
+
+template <typename TA, typename TB, typename TACC, typename TC>
+static hipError_t gemm_dispatch(bool ca, bool cb, int M, int N, int K, const void* A, int lda,
+                                long long sA, const void* B, int ldb, long long sB, void* C,
+                                int ldc, long long sC, const double* alpha, int batch,
+                                hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch);
+  auto a = (const cplx<TA>*)A;
+  auto b = (const cplx<TB>*)B;
+  auto c = (cplx<TC>*)C;
+  if (!ca && !cb) hipLaunchKernelGGL((k_gemm<TA, TB, TACC, TC, false, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
+  else if (ca && !cb) hipLaunchKernelGGL((k_gemm<TA, TB, TACC, TC, true, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
+  else if (!ca && cb) hipLaunchKernelGGL((k_gemm<TA, TB, TACC, TC, false, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
+  else hipLaunchKernelGGL((k_gemm<TA, TB, TACC, TC, true, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
+  return hipGetLastError();
+}
+
+hipError_t gemm(int prec_in, int prec_out, bool ca, bool cb, int M, int N, int K, const void* A,
+                int lda, long long sA, const void* B, int ldb, long long sB, void* C, int ldc,
+                long long sC, const double* alpha, int batch, hipStream_t st) {
+  if (prec_in == 0 && prec_out == 0)
+    return gemm_dispatch<float, float, float, float>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
+  if (prec_in == 0 && prec_out == 1)
+    return gemm_dispatch<float, float, float, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
+  return gemm_dispatch<double, double, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
+}
+
+// ============================================================================ theta
+// theta[(a,s),(t,b)] = sum_c C[a][s][c] B[c][t][b]; then per (a,b) the 4 values over (s,t)
+// are mixed by the gate G[s't'][st] and written in place of theta (row 2a+s', column
+// t' chi_r + b), and the two-site reduced density matrix
+//   rho[x][y] = sum_{a,b} thetaG[x][a,b] conj(thetaG[y][a,b]),  x = 2s'+t'
+// is accumulated per tile (FP64) into partial[traj][tile][16] c128.
+// Tile: 32 values of a (64 rows) x 32 values of b for both t (64 columns); 256 threads,
+// each 2 a x 2 b x 4 (s,t) accumulators.
+template <typename T>
+__global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, const cplx<T>* __restrict__ Cs,
+                                               const cplx<T>* __restrict__ Bs, long long s_traj,
+                                               cplx<T>* __restrict__ out, long long s_out, Mat4 gate,
+                                               double* __restrict__ partial, int n_tiles) {
+  __shared__ T A_re[GB_K][64 + 4], A_im[GB_K][64 + 4];   // [k][row = 2*(a-a0)+s]
+  __shared__ T B_re[GB_K][64 + 4], B_im[GB_K][64 + 4];   // [k][col = t*32 + (b-b0)]
+  __shared__ double red[256 / 64][32];
+  const int traj = blockIdx.z;
+  const cplx<T>* Cp = Cs + traj * s_traj;
+  const cplx<T>* Bp = Bs + traj * s_traj;
+  cplx<T>* O = out + traj * s_out;
+  const int a0 = blockIdx.y * 32, b0 = blockIdx.x * 32;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int ldc = 2 * chi_m;   // C as (a,s) x c row-major: row stride chi_m, (a,s) -> 2a+s
+  const int ldb = 2 * chi_r;   // B as c x (t,b)
+  T acc_re[2][2][2][2], acc_im[2][2][2][2];   // [ai][s][bj][t]
+#pragma unroll
+  for (int i = 0; i < 16; ++i) { (&acc_re[0][0][0][0])[i] = 0; (&acc_im[0][0][0][0])[i] = 0; }
+  for (int k0 = 0; k0 < chi_m; k0 += GB_K) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int e = tid + 256 * r;
+      int kk = e & 15, row = e >> 4;               // row = 2*(a-a0)+s
+      int a = a0 + (row >> 1), s = row & 1, k = k0 + kk;
+      cplx<T> v = {0, 0};
+      if (a < chi_l && k < chi_m) v = Cp[(long long)(2 * a + s) * chi_m + k];
+      A_re[kk][row] = v.re;
+      A_im[kk][row] = v.im;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int e = tid + 256 * r;
+      int col = e & 63, kk = e >> 6;               // col = t*32 + (b-b0)
+      int t = col >> 5, b = b0 + (col & 31), k = k0 + kk;
+      cplx<T> v = {0, 0};
+      if (b < chi_r && k < chi_m) v = Bp[(long long)k * ldb + t * chi_r + b];
+      B_re[kk][col] = v.re;
+      B_im[kk][col] = v.im;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < GB_K; ++kk) {
+      T ar[2][2], ai[2][2], br[2][2], bi[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          int row = 2 * (ty + 16 * i) + s;
+          ar[i][s] = A_re[kk][row];
+          ai[i][s] = A_im[kk][row];
+        }
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          int col = t * 32 + tx + 16 * j;
+          br[j][t] = B_re[kk][col];
+          bi[j][t] = B_im[kk][col];
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              acc_re[i][s][j][t] += ar[i][s] * br[j][t] - ai[i][s] * bi[j][t];
+              acc_im[i][s][j][t] += ar[i][s] * bi[j][t] + ai[i][s] * br[j][t];
+            }
+    }
+    __syncthreads();
+  }
+  // ---- epilogue: gate mix, store, RDM partial sums in FP64
+  double rr[16], ri[16];
+#pragma unroll
+  for (int x = 0; x < 16; ++x) rr[x] = ri[x] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      int a = a0 + ty + 16 * i, b = b0 + tx + 16 * j;
+      if (a >= chi_l || b >= chi_r) continue;
+      double vr[4], vi[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        double sr = 0, si = 0;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          double gr = gate.v[2 * (4 * x + y)], gi = gate.v[2 * (4 * x + y) + 1];
+          double tr = (double)acc_re[i][y >> 1][j][y & 1], tim = (double)acc_im[i][y >> 1][j][y & 1];
+          sr += gr * tr - gi * tim;
+          si += gr * tim + gi * tr;
+        }
+        cplx<T> o;
+        o.re = (T)sr;
+        o.im = (T)si;
+        O[(long long)(2 * a + (x >> 1)) * ldb + (x & 1) * chi_r + b] = o;
+        vr[x] = (double)o.re;   // RDM of the stored (rounded) values
+        vi[x] = (double)o.im;
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          rr[4 * x + y] += vr[x] * vr[y] + vi[x] * vi[y];
+          ri[4 * x + y] += vi[x] * vr[y] - vr[x] * vi[y];
+        }
+    }
+  // block reduction of the 32 doubles, fixed order (wave shuffles then LDS)
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int x = 0; x < 32; ++x) {
+    double v = (x < 16) ? rr[x] : ri[x - 16];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][x] = v;
+  }
+  __syncthreads();
+  if (tid < 32) {
+    double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    int tile = blockIdx.y * gridDim.x + blockIdx.x;
+    int x = tid & 15;
+    double* p = partial + ((long long)traj * n_tiles + tile) * 32;
+    if (tid < 16) p[2 * x] = v; else p[2 * x + 1] = v;
+  }
+}
+
+hipError_t theta(int prec, int chi_l, int chi_m, int chi_r, const void* Cs, const void* Bs,
+                 long long s_traj, void* out, long long s_out, const Mat4& gate, double* partial,
+                 int n_traj, hipStream_t st) {
+  dim3 grid((chi_r + 31) / 32, (chi_l + 31) / 32, n_traj);
+  int nt = grid.x * grid.y;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_theta<float>, grid, dim3(256), 0, st, chi_l, chi_m, chi_r, (const c32*)Cs, (const c32*)Bs, s_traj, (c32*)out, s_out, gate, partial, nt);
+  else
+    hipLaunchKernelGGL(k_theta<double>, grid, dim3(256), 0, st, chi_l, chi_m, chi_r, (const c64d*)Cs, (const c64d*)Bs, s_traj, (c64d*)out, s_out, gate, partial, nt);
+  return hipGetLastError();
+}
+
+int theta_tiles(int chi_l, int chi_r) { return ((chi_r + 31) / 32) * ((chi_l + 31) / 32); }
+
+// ============================================================================ Kraus pair
+// X[(a,s),(t,b)] <- sum_{s0,t0} Ks[s][s0] Kt[t][t0] X[(a,s0),(t0,b)] in place, with the
+// per-trajectory 2x2 operators ks/kt [traj][2][2] c128 (identity when flagged off).
+template <typename T>
+__global__ void k_kraus_pair(int chi_l, int chi_r, cplx<T>* X, long long s_traj, const double* __restrict__ kops,
+                             int n_traj) {
+  long long total = (long long)n_traj * chi_l * chi_r;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    int b = e % chi_r;
+    long long r = e / chi_r;
+    int a = r % chi_l;
+    int traj = r / chi_l;
+    const double* k = kops + traj * 16;   // Ks then Kt, each 2x2 c128
+    cplx<T>* x = X + traj * s_traj;
+    const int ld = 2 * chi_r;
+    double vr[2][2], vi[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        cplx<T> v = x[(long long)(2 * a + s) * ld + t * chi_r + b];
+        vr[s][t] = v.re;
+        vi[s][t] = v.im;
+      }
+    // apply Kt on t
+    double wr[2][2], wi[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        double sr = 0, si = 0;
+#pragma unroll
+        for (int t0 = 0; t0 < 2; ++t0) {
+          double kr = k[8 + 2 * (2 * t + t0)], ki = k[8 + 2 * (2 * t + t0) + 1];
+          sr += kr * vr[s][t0] - ki * vi[s][t0];
+          si += kr * vi[s][t0] + ki * vr[s][t0];
+        }
+        wr[s][t] = sr;
+        wi[s][t] = si;
+      }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        double sr = 0, si = 0;
+#pragma unroll
+        for (int s0 = 0; s0 < 2; ++s0) {
+          double kr = k[2 * (2 * s + s0)], ki = k[2 * (2 * s + s0) + 1];
+          sr += kr * wr[s0][t] - ki * wi[s0][t];
+          si += kr * wi[s0][t] + ki * wr[s0][t];
+        }
+        cplx<T> o;
+        o.re = (T)sr;
+        o.im = (T)si;
+        x[(long long)(2 * a + s) * ld + t * chi_r + b] = o;
+      }
+  }
+}
+
+hipError_t kraus_pair(int prec, int chi_l, int chi_r, void* X, long long s_traj, const double* kops,
+                      int n_traj, hipStream_t st) {
+  long long total = (long long)n_traj * chi_l * chi_r;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 65536) blocks = 65536;
+  if (prec == 0) hipLaunchKernelGGL(k_kraus_pair<float>, dim3(blocks), dim3(256), 0, st, chi_l, chi_r, (c32*)X, s_traj, kops, n_traj);
+  else hipLaunchKernelGGL(k_kraus_pair<double>, dim3(blocks), dim3(256), 0, st, chi_l, chi_r, (c64d*)X, s_traj, kops, n_traj);
+  return hipGetLastError();
+}
+
+// ============================================================================ scale + cast
+// out[i][j] = in[i][j] * col_scale[j]   (conj_t: out[j][i] = conj(in[i][j]) * col_scale[j])
+// in: c128 rows x cols (ld_in); out: T (ld_out).  col_scale per trajectory or NULL.
+template <typename T>
+__global__ void k_scale_cast(int rows, int cols, const c64d* __restrict__ in, int ld_in, long long s_in,
+                             const double* __restrict__ col_scale, long long s_scale, bool conj_t,
+                             cplx<T>* __restrict__ out, int ld_out, long long s_out, int n_traj) {
+  long long total = (long long)n_traj * rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    int j = e % cols;
+    long long r = e / cols;
+    int i = r % rows;
+    int traj = r / rows;
+    c64d v = in[traj * s_in + (long long)i * ld_in + j];
+    double sc = col_scale ? col_scale[traj * s_scale + j] : 1.0;
+    cplx<T> o;
+    if (!conj_t) {
+      o.re = (T)(v.re * sc);
+      o.im = (T)(v.im * sc);
+      out[traj * s_out + (long long)i * ld_out + j] = o;
+    } else {
+      o.re = (T)(v.re * sc);
+      o.im = (T)(-v.im * sc);
+      out[traj * s_out + (long long)j * ld_out + i] = o;
+    }
+  }
+}
+
+hipError_t scale_cast(int prec, int rows, int cols, const void* in, int ld_in, long long s_in,
+                      const double* col_scale, long long s_scale, bool conj_t, void* out, int ld_out,
+                      long long s_out, int n_traj, hipStream_t st) {
+  long long total = (long long)n_traj * rows * cols;
+  if (total <= 0) return hipSuccess;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 65536) blocks = 65536;
+  if (prec == 0) hipLaunchKernelGGL(k_scale_cast<float>, dim3(blocks), dim3(256), 0, st, rows, cols, (const c64d*)in, ld_in, s_in, col_scale, s_scale, conj_t, (c32*)out, ld_out, s_out, n_traj);
+  else hipLaunchKernelGGL(k_scale_cast<double>, dim3(blocks), dim3(256), 0, st, rows, cols, (const c64d*)in, ld_in, s_in, col_scale, s_scale, conj_t, (c64d*)out, ld_out, s_out, n_traj);
+  return hipGetLastError();
+}
+
+// ============================================================================ fill
+template <typename T>
+__global__ void k_init_sites(cplx<T>* state, const long long* __restrict__ site_off, const int* __restrict__ site_len,
+                             int n_sites, long long s_traj, int n_traj) {
+  // zero every site tensor, then A[0][0][0] = 1 (|0> with bond index 0)
+  long long per = s_traj;
+  long long total = per * n_traj;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    state[e] = cplx<T>{0, 0};
+  }
+}
+
+template <typename T>
+__global__ void k_set_one(cplx<T>* state, const long long* __restrict__ site_off, int n_sites, long long s_traj,
+                          int n_traj) {
+  int traj = blockIdx.x * blockDim.x + threadIdx.x;
+  if (traj >= n_traj) return;
+  for (int k = 0; k < n_sites; ++k) state[traj * s_traj + site_off[k]] = cplx<T>{(T)1, (T)0};
+}
+
+hipError_t init_state(int prec, void* state, const long long* d_site_off, int n_sites, long long s_traj,
+                      int n_traj, hipStream_t st) {
+  long long total = s_traj * n_traj;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 65536) blocks = 65536;
+  if (prec == 0) {
+    hipLaunchKernelGGL(k_init_sites<float>, dim3(blocks), dim3(256), 0, st, (c32*)state, d_site_off, nullptr, n_sites, s_traj, n_traj);
+    hipLaunchKernelGGL(k_set_one<float>, dim3((n_traj + 255) / 256), dim3(256), 0, st, (c32*)state, d_site_off, n_sites, s_traj, n_traj);
+  } else {
+    hipLaunchKernelGGL(k_init_sites<double>, dim3(blocks), dim3(256), 0, st, (c64d*)state, d_site_off, nullptr, n_sites, s_traj, n_traj);
+    hipLaunchKernelGGL(k_set_one<double>, dim3((n_traj + 255) / 256), dim3(256), 0, st, (c64d*)state, d_site_off, n_sites, s_traj, n_traj);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mpsb

@@ -1,0 +1,83 @@
+// Launch wrappers of the mpsb HIP kernels (host-side declarations).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mpsb {
+
+// Arguments of the noise-event kernels.  Channel data of at most two channels (slot 0: the
+// lower / single qubit of the launch, slot 1: the upper qubit of a gate) travel by value.
+struct EventArgs {
+  int n_traj, n_qubits, layer, mode;
+  int rec_stride, rec_qbase;   // record index = traj * rec_stride + (qubit - rec_qbase)
+  uint64_t seed;
+  int32_t* branch_out;   // [n_traj][n_qubits] or NULL
+  double* w_out;         // [n_traj][n_qubits][4][4] c128 or NULL
+  int n_kraus[2];
+  double kraus[2][32];
+  double fixed_u[2][32];
+};
+
+// prec: 0 = complex64 storage / FP32 arithmetic, 1 = complex128 / FP64
+hipError_t gemm(int prec_in, int prec_out, bool conj_a, bool conj_b, int M, int N, int K, const void* A, int lda,
+                long long sA, const void* B, int ldb, long long sB, void* C, int ldc, long long sC,
+                const double* alpha, int batch, hipStream_t st);
+hipError_t theta(int prec, int chi_l, int chi_m, int chi_r, const void* Cs, const void* Bs, long long s_traj,
+                 void* out, long long s_out, const Mat4& gate, double* partial, int n_traj, hipStream_t st);
+int theta_tiles(int chi_l, int chi_r);
+hipError_t kraus_pair(int prec, int chi_l, int chi_r, void* X, long long s_traj, const double* kops, int n_traj,
+                      hipStream_t st);
+hipError_t scale_cast(int prec, int rows, int cols, const void* in, int ld_in, long long s_in,
+                      const double* col_scale, long long s_scale, bool conj_t, void* out, int ld_out,
+                      long long s_out, int n_traj, hipStream_t st);
+hipError_t init_state(int prec, void* state, const long long* d_site_off, int n_sites, long long s_traj,
+                      int n_traj, hipStream_t st);
+
+size_t heev_ws_doubles(int n, int keep);
+size_t heev_gws_doubles(int keep);
+hipError_t heev(int n, int keep, double zero_tol, void* A, long long sA, double* ws, long long sW, double* gws,
+                long long sG, double* evals, long long sE, double* kept_sum, void* Z, long long sZ, int batch,
+                hipStream_t st);
+
+hipError_t launch_gate_events(const EventArgs& ea, const double* partial, int n_tiles, int q, int has_s, int has_t,
+                              double* kops, int* status, hipStream_t st);
+hipError_t launch_site_event(const EventArgs& ea, const double* rho1, int q, int slot, const int* forced,
+                             double* kops, double* p_out, int* status, hipStream_t st);
+hipError_t launch_site_event_check(const EventArgs& ea, const double* rho1, int slot, const int* forced, int* status,
+                                   hipStream_t st);
+hipError_t launch_unravel_opt(int batch, const double* rho_q, const double* kraus, const int* kraus_id, int r,
+                              double* U, double* p, double* eof, hipStream_t st);
+
+// single-site reduced state of a site tensor [a][s][b]: rho1[traj][s][s'] (unnormalised)
+hipError_t site_rdm(int prec, int chi_l, int chi_r, const void* site, long long s_traj, double* rho1, int n_traj,
+                    hipStream_t st);
+// apply the per-trajectory 2x2 operator (first block of kops) to the physical index of a site
+hipError_t site_apply(int prec, int chi_l, int chi_r, void* site, long long s_traj, const double* kops, int n_traj,
+                      hipStream_t st);
+// renormalisation factors 1/sqrt(kept) and discarded weight (kept / trace)
+hipError_t trunc_factors(const double* kept, const double* ws, long long sW, int n, double* alpha,
+                         double* discarded, int disc_stride, int accumulate, int n_traj, hipStream_t st);
+// inverse square roots / square roots of hop eigenvalues (0 for dropped)
+hipError_t hop_scales(const double* evals, long long sE, int n, double* inv_sqrt, double* sqrt_, int n_traj,
+                      hipStream_t st);
+
+// observables
+hipError_t env_init(double* env, long long s_env, int n_traj, hipStream_t st);
+hipError_t widen(const void* in, long long s_in, void* out, long long s_out, long long len, int n_traj, hipStream_t st);
+hipError_t neg_cols(void* X, long long sX, int rows, int ld, int c0, int w, int n_traj, hipStream_t st);
+hipError_t zero_cols(int prec, void* X, long long sX, int rows, int ld, int c0, int w, int n_traj, hipStream_t st);
+hipError_t obs_trace(int chi, const double* X, long long s_env, const double* R, long long s_R, double* out,
+                     int out_stride, int n_traj, hipStream_t st);
+hipError_t obs_normalise(double* per_traj, int n_obs, const double* norms, int n_traj, hipStream_t st);
+hipError_t obs_reduce(const double* per_traj, int n_obs, int n_traj, double* mean, double* m2, hipStream_t st);
+
+// unravelling cost
+hipError_t cost_rho(int batch, const void* theta, int chi_l, int chi_r, int prec, double* rho, hipStream_t st);
+hipError_t cost_eval(int batch, const double* rho, const double* kraus, const double* params, const double* u_ref,
+                     int kind, double* f, hipStream_t st);
+hipError_t cost_grad(int batch, const double* rho, const double* kraus, const double* params, const double* u_ref,
+                     int kind, const double* grad_f, double* grad, hipStream_t st);
+
+}  // namespace mpsb

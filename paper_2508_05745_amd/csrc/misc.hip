@@ -1,0 +1,267 @@
+// Small kernels of the sweep: single-site reduced states and operator application for idle-
+// qubit events, truncation / hop scale factors, precision widening, and the observable
+// traces and the fixed-order reduction over trajectories.
+#include "common.h"
+#include "kernels.h"
+
+namespace mpsb {
+
+static inline int nblocks(long long total, int bs = 256) {
+  long long b = (total + bs - 1) / bs;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// rho1[traj][s][s'] = sum_{a,b} A[a][s][b] conj(A[a][s'][b])  (one workgroup per trajectory)
+template <typename T>
+__global__ void k_site_rdm(int chi_l, int chi_r, const cplx<T>* __restrict__ site, long long s_traj, double* rho1) {
+  __shared__ double red[4][8];
+  const cplx<T>* A = site + blockIdx.x * s_traj;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const long long tot = (long long)chi_l * chi_r;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+    int a = (int)(e / chi_r), b = (int)(e % chi_r);
+    cplx<T> v0 = A[(long long)a * 2 * chi_r + b], v1 = A[(long long)a * 2 * chi_r + chi_r + b];
+    double r0 = v0.re, i0 = v0.im, r1 = v1.re, i1 = v1.im;
+    acc[0] += r0 * r0 + i0 * i0;          // [0][0]
+    acc[2] += r0 * r1 + i0 * i1;          // [0][1] re
+    acc[3] += i0 * r1 - r0 * i1;          // [0][1] im
+    acc[6] += r1 * r1 + i1 * i1;          // [1][1]
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int x = 0; x < 8; ++x) {
+    double v = acc[x];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][x] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s[8];
+    for (int x = 0; x < 8; ++x) s[x] = red[0][x] + red[1][x] + red[2][x] + red[3][x];
+    double* o = rho1 + blockIdx.x * 8;
+    o[0] = s[0]; o[1] = 0.0;
+    o[2] = s[2]; o[3] = s[3];
+    o[4] = s[2]; o[5] = -s[3];
+    o[6] = s[6]; o[7] = 0.0;
+  }
+}
+
+hipError_t site_rdm(int prec, int chi_l, int chi_r, const void* site, long long s_traj, double* rho1, int n_traj,
+                    hipStream_t st) {
+  if (prec == 0) hipLaunchKernelGGL(k_site_rdm<float>, dim3(n_traj), dim3(256), 0, st, chi_l, chi_r, (const c32*)site, s_traj, rho1);
+  else hipLaunchKernelGGL(k_site_rdm<double>, dim3(n_traj), dim3(256), 0, st, chi_l, chi_r, (const c64d*)site, s_traj, rho1);
+  return hipGetLastError();
+}
+
+// A[a][s][b] <- sum_s0 K[s][s0] A[a][s0][b]
+template <typename T>
+__global__ void k_site_apply(int chi_l, int chi_r, cplx<T>* site, long long s_traj, const double* __restrict__ kops,
+                             int n_traj) {
+  const long long per = (long long)chi_l * chi_r, total = per * n_traj;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    int traj = (int)(e / per);
+    long long r = e % per;
+    int a = (int)(r / chi_r), b = (int)(r % chi_r);
+    cplx<T>* A = site + traj * s_traj;
+    const double* k = kops + (long long)traj * 16;
+    cplx<T> v0 = A[(long long)a * 2 * chi_r + b], v1 = A[(long long)a * 2 * chi_r + chi_r + b];
+    double o[2][2];
+    for (int s = 0; s < 2; ++s) {
+      double k0r = k[2 * (2 * s)], k0i = k[2 * (2 * s) + 1], k1r = k[2 * (2 * s + 1)], k1i = k[2 * (2 * s + 1) + 1];
+      o[s][0] = k0r * v0.re - k0i * v0.im + k1r * v1.re - k1i * v1.im;
+      o[s][1] = k0r * v0.im + k0i * v0.re + k1r * v1.im + k1i * v1.re;
+    }
+    A[(long long)a * 2 * chi_r + b] = cplx<T>{(T)o[0][0], (T)o[0][1]};
+    A[(long long)a * 2 * chi_r + chi_r + b] = cplx<T>{(T)o[1][0], (T)o[1][1]};
+  }
+}
+
+hipError_t site_apply(int prec, int chi_l, int chi_r, void* site, long long s_traj, const double* kops, int n_traj,
+                      hipStream_t st) {
+  int nb = nblocks((long long)chi_l * chi_r * n_traj);
+  if (prec == 0) hipLaunchKernelGGL(k_site_apply<float>, dim3(nb), dim3(256), 0, st, chi_l, chi_r, (c32*)site, s_traj, kops, n_traj);
+  else hipLaunchKernelGGL(k_site_apply<double>, dim3(nb), dim3(256), 0, st, chi_l, chi_r, (c64d*)site, s_traj, kops, n_traj);
+  return hipGetLastError();
+}
+
+// alpha = 1/sqrt(kept); discarded = (trace - kept) / trace (trace kept by the eigensolver at
+// ws[3n] of each matrix)
+__global__ void k_trunc_factors(const double* kept, const double* ws, long long sW, int n, double* alpha,
+                                double* discarded, int disc_stride, int accumulate, int n_traj) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_traj) return;
+  double k = kept[t], tr = ws[t * sW + 3 * n];
+  alpha[t] = k > 0 ? 1.0 / sqrt(k) : 0.0;
+  double eps = tr > 0 ? fmax(tr - k, 0.0) / tr : 0.0;
+  if (discarded) {
+    double* d = discarded + (long long)t * disc_stride;
+    *d = accumulate ? *d + eps : eps;
+  }
+}
+
+hipError_t trunc_factors(const double* kept, const double* ws, long long sW, int n, double* alpha, double* discarded,
+                         int disc_stride, int accumulate, int n_traj, hipStream_t st) {
+  hipLaunchKernelGGL(k_trunc_factors, dim3((n_traj + 255) / 256), dim3(256), 0, st, kept, ws, sW, n, alpha, discarded,
+                     disc_stride, accumulate, n_traj);
+  return hipGetLastError();
+}
+
+// zero columns [c0, c0+w) of rows x ld matrices (prec)
+template <typename T>
+__global__ void k_zero_cols(cplx<T>* X, long long sX, int rows, int ld, int c0, int w, int n_traj) {
+  long long per = (long long)rows * w, total = per * n_traj;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    int t = (int)(e / per);
+    long long r = e % per;
+    int i = (int)(r / w), j = (int)(r % w);
+    X[t * sX + (long long)i * ld + c0 + j] = cplx<T>{(T)0, (T)0};
+  }
+}
+
+hipError_t zero_cols(int prec, void* X, long long sX, int rows, int ld, int c0, int w, int n_traj, hipStream_t st) {
+  int nb = nblocks((long long)rows * w * n_traj);
+  if (prec == 0) hipLaunchKernelGGL(k_zero_cols<float>, dim3(nb), dim3(256), 0, st, (c32*)X, sX, rows, ld, c0, w, n_traj);
+  else hipLaunchKernelGGL(k_zero_cols<double>, dim3(nb), dim3(256), 0, st, (c64d*)X, sX, rows, ld, c0, w, n_traj);
+  return hipGetLastError();
+}
+
+__global__ void k_hop_scales(const double* evals, long long sE, int n, double* inv_sqrt, double* sqrt_, int n_traj) {
+  long long total = (long long)n * n_traj;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    int t = (int)(e / n), k = (int)(e % n);
+    double l = evals[t * sE + k];
+    inv_sqrt[e] = l > 0 ? 1.0 / sqrt(l) : 0.0;
+    sqrt_[e] = l > 0 ? sqrt(l) : 0.0;
+  }
+}
+
+hipError_t hop_scales(const double* evals, long long sE, int n, double* inv_sqrt, double* sqrt_, int n_traj,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_hop_scales, dim3(nblocks((long long)n * n_traj)), dim3(256), 0, st, evals, sE, n, inv_sqrt, sqrt_, n_traj);
+  return hipGetLastError();
+}
+
+// c64 -> c128 copy of a batch of contiguous blocks
+__global__ void k_widen(const c32* __restrict__ in, long long s_in, c64d* __restrict__ out, long long s_out, long long len,
+                        int n_traj) {
+  long long total = len * n_traj;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    int t = (int)(e / len);
+    long long i = e % len;
+    c32 v = in[t * s_in + i];
+    out[t * s_out + i] = c64d{(double)v.re, (double)v.im};
+  }
+}
+
+hipError_t widen(const void* in, long long s_in, void* out, long long s_out, long long len, int n_traj, hipStream_t st) {
+  hipLaunchKernelGGL(k_widen, dim3(nblocks(len * n_traj)), dim3(256), 0, st, (const c32*)in, s_in, (c64d*)out, s_out, len, n_traj);
+  return hipGetLastError();
+}
+
+// negate columns [c0, c0+w) of rows x ld matrices (c128)
+__global__ void k_neg_cols(c64d* X, long long sX, int rows, int ld, int c0, int w, int n_traj) {
+  long long per = (long long)rows * w, total = per * n_traj;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    int t = (int)(e / per);
+    long long r = e % per;
+    int i = (int)(r / w), j = (int)(r % w);
+    c64d& v = X[t * sX + (long long)i * ld + c0 + j];
+    v.re = -v.re;
+    v.im = -v.im;
+  }
+}
+
+hipError_t neg_cols(void* X, long long sX, int rows, int ld, int c0, int w, int n_traj, hipStream_t st) {
+  hipLaunchKernelGGL(k_neg_cols, dim3(nblocks((long long)rows * w * n_traj)), dim3(256), 0, st, (c64d*)X, sX, rows, ld, c0, w, n_traj);
+  return hipGetLastError();
+}
+
+__global__ void k_env_one(c64d* env, long long s_env, int n_traj) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_traj) env[t * s_env] = c64d{1.0, 0.0};
+}
+
+hipError_t env_init(double* env, long long s_env_c, int n_traj, hipStream_t st) {
+  hipLaunchKernelGGL(k_env_one, dim3((n_traj + 255) / 256), dim3(256), 0, st, (c64d*)env, s_env_c, n_traj);
+  return hipGetLastError();
+}
+
+// out[t * stride] = Re Tr(X R) for chi x chi c128 matrices (one workgroup per trajectory)
+__global__ void k_trace_prod(int chi, const c64d* __restrict__ X, long long sX, const c64d* __restrict__ R, long long sR,
+                             double* out, int stride) {
+  __shared__ double red[4];
+  const c64d* x = X + blockIdx.x * sX;
+  const c64d* r = R + blockIdx.x * sR;
+  double acc = 0;
+  const long long tot = (long long)chi * chi;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+    int i = (int)(e / chi), j = (int)(e % chi);
+    c64d a = x[(long long)i * chi + j], b = r[(long long)j * chi + i];
+    acc += a.re * b.re - a.im * b.im;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[(long long)blockIdx.x * stride] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t obs_trace(int chi, const double* X, long long s_env, const double* R, long long s_R, double* out,
+                     int out_stride, int n_traj, hipStream_t st) {
+  hipLaunchKernelGGL(k_trace_prod, dim3(n_traj), dim3(256), 0, st, chi, (const c64d*)X, s_env, (const c64d*)R, s_R, out, out_stride);
+  return hipGetLastError();
+}
+
+__global__ void k_obs_normalise(double* per_traj, int n_obs, const double* norms, int n_traj) {
+  long long total = (long long)n_obs * n_traj;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    int t = (int)(e / n_obs);
+    per_traj[e] /= norms[t];
+  }
+}
+
+hipError_t obs_normalise(double* per_traj, int n_obs, const double* norms, int n_traj, hipStream_t st) {
+  hipLaunchKernelGGL(k_obs_normalise, dim3(nblocks((long long)n_obs * n_traj)), dim3(256), 0, st, per_traj, n_obs, norms, n_traj);
+  return hipGetLastError();
+}
+
+// mean and M2 over trajectories, one workgroup per observable, fixed-order pairwise merge
+// (Chan et al.) of per-thread Welford accumulators
+__global__ void k_obs_reduce(const double* __restrict__ per_traj, int n_obs, int n_traj, double* mean, double* m2) {
+  __shared__ double sn[256], sm[256], sq[256];
+  const int o = blockIdx.x, tid = threadIdx.x;
+  double n = 0, mu = 0, q = 0;
+  for (int t = tid; t < n_traj; t += 256) {
+    double x = per_traj[(long long)t * n_obs + o];
+    n += 1;
+    double d = x - mu;
+    mu += d / n;
+    q += d * (x - mu);
+  }
+  sn[tid] = n; sm[tid] = mu; sq[tid] = q;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      double na = sn[tid], nb = sn[tid + s];
+      double nn = na + nb;
+      if (nb > 0) {
+        double d = sm[tid + s] - sm[tid];
+        sm[tid] = nn > 0 ? sm[tid] + d * nb / nn : 0.0;
+        sq[tid] = sq[tid] + sq[tid + s] + d * d * na * nb / nn;
+        sn[tid] = nn;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    mean[o] = sm[0];
+    m2[o] = sq[0];
+  }
+}
+
+hipError_t obs_reduce(const double* per_traj, int n_obs, int n_traj, double* mean, double* m2, hipStream_t st) {
+  hipLaunchKernelGGL(k_obs_reduce, dim3(n_obs), dim3(256), 0, st, per_traj, n_obs, n_traj, mean, m2);
+  return hipGetLastError();
+}
+
+}  // namespace mpsb

@@ -1,0 +1,273 @@
+"""ctypes binding of the mpsb HIP library (argument marshalling only).
+
+Every step of the simulation runs in the library's HIP kernels; torch provides device
+memory (uint8 / complex / float64 CUDA tensors) and the current stream.  There is no CPU
+fallback: if the library is missing or no device is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpsb.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSUP, ENUM, EKRAUS = 0, -1, -2, -3, -4, -5, -6
+FP32_BULK, FP64 = 0, 1
+ORTHOGONAL, FIXED, OPTIMAL = 0, 1, 3
+MAX_CHI = 256
+
+_lib = None
+
+
+class MpsbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mpsb error {code}: {msg}")
+        self.code = code
+
+
+class _Circuit(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int), ("gates", ctypes.c_void_p), ("n_channels", ctypes.c_int),
+                ("kraus", ctypes.c_void_p), ("n_kraus", ctypes.c_void_p), ("events", ctypes.c_void_p),
+                ("unravel_mode", ctypes.c_int), ("fixed_u", ctypes.c_void_p)]
+
+
+def lib():
+    """Loads libmpsb.so (built in-tree by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not found: build the HIP library first "
+                               "(python -m paper_2508_05745_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
+        L.mps_last_error.restype = ctypes.c_char_p
+        L.mps_batch_plan.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.mps_batch_create.argtypes = [i32, i32, i32, i32, u64, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
+        L.mps_batch_set_circuit.argtypes = [vp, ctypes.POINTER(_Circuit)]
+        L.mps_circuit_validate.argtypes = [i32, ctypes.POINTER(_Circuit)]
+        L.apply_layer.argtypes = [vp, i32, vp, vp, vp]
+        L.sample_kraus.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
+        L.mps_truncate.argtypes = [vp, i32, vp]
+        L.expect.argtypes = [vp, vp, vp, vp]
+        L.mps_batch_sync.argtypes = [vp]
+        L.mps_batch_destroy.argtypes = [vp]
+        L.unravel_opt.argtypes = [i32, vp, vp, i32, vp, i32, vp, vp, vp, vp]
+        L.unravel_cost.argtypes = [i32, vp, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp]
+        L.unravel_cost_grad.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise MpsbError(code, lib().mps_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype).contiguous()
+
+
+# ------------------------------------------------------------------------- circuits
+
+
+class CircuitArrays:
+    """Host arrays of an inputs.Circuit in the layout the C ABI expects."""
+
+    def __init__(self, circuit, mode: int = OPTIMAL, fixed_u: Optional[np.ndarray] = None):
+        self.n = circuit.n
+        self.gates = np.ascontiguousarray(circuit.gates.astype(np.complex128)).view(np.float64)
+        self.kraus = np.ascontiguousarray(circuit.channels.astype(np.complex128)).view(np.float64)
+        self.n_kraus = np.ascontiguousarray(circuit.n_kraus.astype(np.int32))
+        self.events = np.ascontiguousarray(circuit.events.astype(np.int32))
+        self.depth = circuit.depth
+        self.mode = mode
+        if fixed_u is not None:
+            fu = np.zeros((circuit.channels.shape[0], 4, 4), dtype=np.complex128)
+            fu[:] = fixed_u
+            self.fixed_u = np.ascontiguousarray(fu).view(np.float64)
+        else:
+            self.fixed_u = None
+
+    def struct(self) -> _Circuit:
+        c = _Circuit()
+        c.depth = self.depth
+        c.gates = self.gates.ctypes.data
+        c.n_channels = self.n_kraus.shape[0]
+        c.kraus = self.kraus.ctypes.data
+        c.n_kraus = self.n_kraus.ctypes.data
+        c.events = self.events.ctypes.data
+        c.unravel_mode = self.mode
+        c.fixed_u = self.fixed_u.ctypes.data if self.fixed_u is not None else None
+        return c
+
+
+def plan(n_traj: int, n_qubits: int, chi: int, precision: int):
+    s, w = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().mps_batch_plan(n_traj, n_qubits, chi, precision, ctypes.byref(s), ctypes.byref(w)))
+    return s.value, w.value
+
+
+def validate_circuit(circuit, mode: int = OPTIMAL, fixed_u=None):
+    ca = CircuitArrays(circuit, mode, fixed_u)
+    st = ca.struct()
+    _check(lib().mps_circuit_validate(circuit.n, ctypes.byref(st)))
+
+
+class Batch:
+    """A batch of MPS trajectories living in caller (torch) device buffers."""
+
+    def __init__(self, n_traj: int, n_qubits: int, chi: int, precision: int = FP64, seed: int = 0):
+        import torch
+        self.n_traj, self.n, self.chi, self.precision = n_traj, n_qubits, chi, precision
+        sb, wb = plan(n_traj, n_qubits, chi, precision)
+        self.state = torch.empty(sb, dtype=torch.uint8, device="cuda")
+        self.work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        _check(lib().mps_batch_create(n_traj, n_qubits, chi, precision, ctypes.c_uint64(seed),
+                                      _ptr(self.state), sb, _ptr(self.work), wb, _stream(),
+                                      ctypes.byref(h)))
+        self.h = h
+        self._circ = None
+
+    def set_circuit(self, circuit, mode: int = OPTIMAL, fixed_u=None):
+        self._circ = CircuitArrays(circuit, mode, fixed_u)
+        st = self._circ.struct()
+        _check(lib().mps_batch_set_circuit(self.h, ctypes.byref(st)))
+
+    def apply_layer(self, layer: int, discarded=None, branch=None, w_record=None):
+        _check(lib().apply_layer(self.h, layer, _ptr(discarded), _ptr(branch), _ptr(w_record)))
+
+    def sample_kraus(self, qubit: int, channel: int, mode: int, rng_layer: int, forced=None,
+                     branch=None, p=None):
+        q = np.full(self.n_traj, qubit, dtype=np.int32)
+        f = None if forced is None else np.ascontiguousarray(np.asarray(forced, dtype=np.int32))
+        _check(lib().sample_kraus(self.h, q.ctypes.data, channel, mode, rng_layer,
+                                  None if f is None else f.ctypes.data, _ptr(branch), _ptr(p)))
+
+    def truncate(self, chi: int, discarded=None):
+        _check(lib().mps_truncate(self.h, chi, _ptr(discarded)))
+
+    def expect(self, per_traj: bool = True):
+        """(mean, m2, per_traj) of <Z_i> (n) then <Z_i Z_i+1> (n-1), float64 CUDA tensors."""
+        import torch
+        nobs = 2 * self.n - 1
+        mean = torch.empty(nobs, dtype=torch.float64, device="cuda")
+        m2 = torch.empty(nobs, dtype=torch.float64, device="cuda")
+        pt = torch.empty((self.n_traj, nobs), dtype=torch.float64, device="cuda") if per_traj else None
+        _check(lib().expect(self.h, _ptr(mean), _ptr(m2), _ptr(pt)))
+        return mean, m2, pt
+
+    def sync(self):
+        _check(lib().mps_batch_sync(self.h))
+
+    def close(self):
+        if self.h is not None:
+            lib().mps_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------------- unravelling
+
+
+def unravel_opt(rho_q, kraus, kraus_id=None):
+    """Batched optimal unravelling.  rho_q: [B,2,2] complex; kraus: [n_k, r, 2, 2] (or
+    [r,2,2]) complex.  Returns (U [B,4,r] complex128, p [B,4], eof [B]) CUDA tensors."""
+    import torch
+    rho = torch.as_tensor(rho_q).to(device="cuda", dtype=torch.complex128).contiguous()
+    k = torch.as_tensor(kraus).to(device="cuda", dtype=torch.complex128)
+    if k.dim() == 3:
+        k = k.unsqueeze(0)
+    k = k.contiguous()
+    B, nk, r = rho.shape[0], k.shape[0], k.shape[1]
+    kid = None if kraus_id is None else torch.as_tensor(kraus_id).to(device="cuda", dtype=torch.int32).contiguous()
+    U = torch.empty((B, 4, r), dtype=torch.complex128, device="cuda")
+    p = torch.empty((B, 4), dtype=torch.float64, device="cuda")
+    eof = torch.empty((B,), dtype=torch.float64, device="cuda")
+    _check(lib().unravel_opt(B, _ptr(rho), _ptr(k), nk, _ptr(kid), r, _ptr(U), _ptr(p),
+                             _ptr(eof), _stream()))
+    return U, p, eof
+
+
+def unravel_cost(theta, kraus, params, u_ref, kind: int = 0):
+    """theta: [B, chi_l, 2, 2, chi_r] complex64/complex128 CUDA tensor.  Returns (f [B],
+    rho_q [B,2,2])."""
+    import torch
+    prec = FP32_BULK if theta.dtype == torch.complex64 else FP64
+    B, cl, cr = theta.shape[0], theta.shape[1], theta.shape[4]
+    k = torch.zeros((4, 2, 2), dtype=torch.complex128, device="cuda")
+    kk = torch.as_tensor(kraus).to(device="cuda", dtype=torch.complex128)
+    k[: kk.shape[0]] = kk
+    f = torch.empty((B,), dtype=torch.float64, device="cuda")
+    rho = torch.empty((B, 2, 2), dtype=torch.complex128, device="cuda")
+    params = params.contiguous()
+    u_ref = u_ref.to(torch.complex128).contiguous()
+    _check(lib().unravel_cost(B, _ptr(theta.contiguous()), cl, cr, prec, _ptr(k), _ptr(params),
+                              _ptr(u_ref), kind, _ptr(f), _ptr(rho), _stream()))
+    return f, rho, k
+
+
+def unravel_cost_grad(rho, kraus4, params, u_ref, kind: int, grad_f):
+    import torch
+    B = rho.shape[0]
+    g = torch.empty((B, 16), dtype=torch.float64, device="cuda")
+    _check(lib().unravel_cost_grad(B, _ptr(rho.contiguous()), _ptr(kraus4.contiguous()),
+                                   _ptr(params.contiguous()), _ptr(u_ref.contiguous()), kind,
+                                   _ptr(None if grad_f is None else grad_f.contiguous()),
+                                   _ptr(g), _stream()))
+    return g
+
+
+def _autograd_function():
+    import torch
+
+    class UnravelCost(torch.autograd.Function):
+        """f(params) = expected linear (kind 0) / Renyi-2 (kind 1) entropy of the unravelling
+        of `kraus` on the reduced states of `theta`; differentiable w.r.t. params only (the
+        adjoint is the library's unravel_cost_grad, theta is not re-read)."""
+
+        @staticmethod
+        def forward(ctx, params, theta, kraus, u_ref, kind):
+            f, rho, k4 = unravel_cost(theta, kraus, params, u_ref, kind)
+            ctx.save_for_backward(rho, k4, params, u_ref.to(torch.complex128))
+            ctx.kind = kind
+            return f
+
+        @staticmethod
+        def backward(ctx, grad_f):
+            rho, k4, params, u_ref = ctx.saved_tensors
+            g = unravel_cost_grad(rho, k4, params, u_ref, ctx.kind, grad_f.to(torch.float64))
+            return g, None, None, None, None
+
+    return UnravelCost
+
+
+_UC = None
+
+
+def UnravelCost():
+    global _UC
+    if _UC is None:
+        _UC = _autograd_function()
+    return _UC

@@ -1,0 +1,41 @@
+"""GPU parity of unravel_opt (the batched locally entanglement-optimal unravelling) with
+the oracle.  The optimum is not unique (degenerate Takagi / M_R spectra for depolarizing,
+dephasing and amplitude damping), so the decomposition is checked through what is unique:
+the entanglement of formation, the optimality E_av(U) = EoF of the returned mixing on the
+oracle's side, completeness, and the branch weights of the returned mixing."""
+import numpy as np
+import pytest
+
+from oracle import unravel as OU
+from paper_2508_05745_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+CHANNELS = {
+    "depolarizing": I.depolarizing(0.02),
+    "depolarizing_sep": I.depolarizing(0.8),
+    "amplitude_damping": I.amplitude_damping(0.3),
+    "dephasing": I.dephasing(0.2),
+    "ad_dephasing": I.compose(I.amplitude_damping(0.005), I.dephasing(0.005)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CHANNELS))
+def test_unravel_opt_matches_oracle(name):
+    from paper_2508_05745_amd import mpsb as M
+    k = CHANNELS[name]
+    B = 300
+    rho = np.stack([I.random_density_matrices(1, 1000 + t, rank=1 if t % 11 == 0 else 2)[0]
+                    for t in range(B)])
+    rho[0] = np.eye(2) / 2                      # Choi-state input
+    U, p, eof = M.unravel_opt(rho, k)
+    U, p, eof = U.cpu().numpy(), p.cpu().numpy(), eof.cpu().numpy()
+    for b in range(B):
+        ref = OU.optimal_mixing(rho[b], k)
+        assert abs(eof[b] - ref["eof"]) < 1e-12, (b, eof[b], ref["eof"])
+        kp = np.einsum("ji,iab->jab", U[b], k)
+        assert np.abs(sum(x.conj().T @ x for x in kp) - np.eye(2)).max() < 1e-12
+        pj, eav = OU.average_entanglement(rho[b], kp)
+        assert abs(eav - ref["eof"]) < 1e-11, (b, eav, ref["eof"])
+        assert np.abs(pj - p[b]).max() < 1e-13
+        assert abs(p[b].sum() - 1) < 1e-13
