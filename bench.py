@@ -1,0 +1,207 @@
+"""Throughput benchmark: trajectory gate-steps/s of the MPS trajectory simulator with
+locally entanglement-optimal unravelling.
+
+Workload: 100-qubit open chain, brickwork depth 40 of Haar-random two-qubit gates,
+depolarizing p = 0.02 on both qubits after every gate, optimal unravelling of every noise
+event, bond dimension chi = 128, 2048 trajectories (synthetic, seeded).  One "step" is one
+brickwork layer applied to all trajectories (gate, two noise events, truncation and centre
+move for every pair).  Bond capacities are fixed from the first layer on, so every step does
+the work of the saturated bond dimension.
+
+The FP32-bulk path (c64 contractions, FP64 eigen-solves / unravelling / probabilities /
+observables) gives `value`; the full-FP64 path is timed on the same steps and the paired
+difference of the per-trajectory observables is reported.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--chi 128] [--traj 2048]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PROF_NAMES = ["theta", "events", "kraus_pair", "gram", "tridiag", "tri_eig", "cholqr", "backtransform",
+              "recompose", "hop", "idle", "expect"]
+PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
+
+
+def caps(n, chi):
+    return [min(chi, 2 ** (k + 1), 2 ** (n - k - 1)) for k in range(n - 1)]
+
+
+def algorithmic_work(n, chi, layers, n_traj):
+    """Algorithmic flops of the timed launches, per kernel class (see the design notes):
+    theta 32*cl*cm*cr, Gram 64*c^2*c' (full Hermitian product), tridiagonalisation
+    16/3 m^3 per matrix (m = Gram dimension; the hop matrices included), back-transformation
+    8 m^2 k, recomposition 32 D cl cr, hop contractions 8 c^2 2c (Gram) + 2 x 16 c^2 cl."""
+    cp = caps(n, chi)
+    dl = lambda k: 1 if k == 0 else cp[k - 1]
+    dr = lambda k: 1 if k == n - 1 else cp[k]
+    w = {k: 0.0 for k in PROF_NAMES}
+    centre = None
+    for l in layers:
+        par = l % 2
+        pairs = list(range(par, n - 1, 2))
+        if par == 1:
+            pairs = pairs[::-1]
+        for q in pairs:
+            cl, cm, cr = dl(q), dr(q), dr(q + 1)
+            D = cm
+            w["theta"] += 32.0 * cl * cm * cr
+            m = 2 * cl if par == 0 else 2 * cr
+            w["gram"] += 8.0 * m * m * (4 * cl * cr) / m
+            w["tridiag"] += 16.0 / 3.0 * m ** 3
+            w["backtransform"] += 8.0 * m * m * D
+            w["recompose"] += 32.0 * D * cl * cr
+    return {k: v * n_traj for k, v in w.items()}
+
+
+def run_gpu(workload, layers_warm, layers_timed, precision, profile=True):
+    import torch
+
+    from paper_2508_05745_amd import mpsb as M
+    c = workload.circuit
+    b = M.Batch(workload.n_traj, c.n, workload.chi, precision, workload.seed)
+    b.set_circuit(c, M.OPTIMAL)
+    for l in layers_warm:
+        b.apply_layer(l)
+    b.sync()
+    lib = M.lib()
+    if profile:
+        lib.mps_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        lib.mps_profile(b.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for l in layers_timed:
+        b.apply_layer(l)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b.sync()
+    prof = None
+    if profile:
+        ms = (ctypes.c_double * 16)()
+        cnt = (ctypes.c_longlong * 16)()
+        lib.mps_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        nc = lib.mps_profile_read(b.h, ms, cnt, 16)
+        prof = {PROF_NAMES[i]: (ms[i], cnt[i]) for i in range(min(nc, len(PROF_NAMES)))}
+        lib.mps_profile(b.h, 0)
+    _, _, pt = b.expect()
+    b.sync()
+    obs = pt.cpu().numpy()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return t1 - t0, prof, obs
+
+
+def cpu_baseline(workload, budget_s=25.0):
+    """The oracle MPS (NumPy, FP64) on one trajectory of the same circuit and chi: untimed
+    layers until the bond dimension saturates (or half the budget), then timed layers."""
+    from oracle import mps as omps
+    from oracle import sv as osv
+    c = workload.circuit
+    m = omps.MPS(c.n)
+    t_start = time.perf_counter()
+    l = 0
+    while l < c.depth and time.perf_counter() - t_start < 0.5 * budget_s:
+        omps.trajectory(c, workload.chi, 0, workload.seed, layer_range=[l], m=m)
+        l += 1
+        if max(m.bond_dims()) >= workload.chi and l >= 14:
+            break
+    warm = l
+    t0 = time.perf_counter()
+    steps = 0
+    while l < c.depth and (time.perf_counter() - t0 < 0.4 * budget_s or steps == 0):
+        omps.trajectory(c, workload.chi, 0, workload.seed, layer_range=[l], m=m)
+        steps += len(c.pairs(l))
+        l += 1
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return dict(value=steps / dt, unit="trajectory gate-steps/s", cores=int(cores), kind="oracle",
+                sample=f"1 trajectory, layers {warm}..{l - 1} (after {warm} untimed layers, max bond "
+                       f"{max(m.bond_dims())}) of the same chi={workload.chi} circuit, "
+                       f"NumPy/LAPACK complex128")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--chi", type=int, default=128)
+    ap.add_argument("--traj", type=int, default=2048)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding (disjoint "
+                                   "trajectory ranges) is designed but not implemented",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    from paper_2508_05745_amd import inputs as I
+    from paper_2508_05745_amd import mpsb as M
+    wl = I.config_wide(chi=args.chi, n_traj=args.traj)
+    c = wl.circuit
+    W, K = args.warmup, args.steps
+    if W + K > c.depth:
+        raise SystemExit("warmup + steps exceeds the circuit depth (40)")
+    warm, timed = list(range(W)), list(range(W, W + K))
+    gate_steps = wl.n_traj * sum(len(c.pairs(l)) for l in timed)
+    print(f"# fp32-bulk: {W} warmup + {K} timed layers, {gate_steps} gate-steps", file=sys.stderr, flush=True)
+    dt32, prof, obs32 = run_gpu(wl, warm, timed, M.FP32_BULK)
+    value = gate_steps / dt32
+    print(f"# fp32-bulk: {dt32:.3f} s -> {value:.1f} gate-steps/s", file=sys.stderr, flush=True)
+    fp64 = None
+    if not args.no_fp64:
+        dt64, prof64, obs64 = run_gpu(wl, warm, timed, M.FP64, profile=False)
+        d = np.abs(obs32 - obs64)
+        fp64 = dict(value=gate_steps / dt64, ms_per_step=1e3 * dt64 / K,
+                    obs_abs_diff_max=float(d.max()), obs_abs_diff_mean=float(d.mean()),
+                    mean_obs_abs_diff_max=float(np.abs(obs32.mean(0) - obs64.mean(0)).max()))
+        print(f"# fp64: {dt64:.3f} s, max |dO| fp32 vs fp64 {d.max():.2e}", file=sys.stderr, flush=True)
+    # roofline of the dominant kernel class
+    work = algorithmic_work(c.n, wl.chi, timed, wl.n_traj)
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, cnt = prof[dom]
+    fl = work.get(dom, 0.0)
+    if dom in ("theta", "gram", "recompose"):
+        peak, unit, bound = PEAK["fp32"], "TFLOP/s", "mfma"
+    else:
+        peak, unit, bound = PEAK["fp64"], "TFLOP/s", "alu"
+    achieved = fl / (ms * 1e-3) if ms > 0 else 0.0
+    roof = dict(kernel=dom, bound=bound, achieved=achieved / 1e12, peak=peak / 1e12, unit=unit,
+                frac=achieved / peak, traffic=None, launches=int(cnt), avg_launch_ms=ms / max(cnt, 1))
+    kern = {k: dict(ms=v[0], launches=int(v[1])) for k, v in prof.items()}
+    th = prof.get("theta", (0, 1))
+    theta_rate = work["theta"] / (th[0] * 1e-3) if th[0] > 0 else 0.0
+    cpu = None if args.no_cpu else cpu_baseline(wl)
+    line = {
+        "metric": "trajectory gate-steps/s at chi=128 (FP32-bulk vs FP64) + <O> error vs oracle",
+        "value": value, "unit": "trajectory gate-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": 1e3 * dt32 / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 contractions (fp32) + fp64 eig/unravel",
+        "data": "synthetic (seeded Haar brickwork, depolarizing p=0.02)",
+        "config": {"workload": wl.name, "n_qubits": c.n, "depth": c.depth, "chi": wl.chi,
+                   "n_traj": wl.n_traj, "unravel": "optimal", "parallelism": "trajectories (1 GPU)"},
+        "roofline": roof, "theta_roofline": dict(achieved=theta_rate / 1e12, peak=PEAK["fp32"] / 1e12,
+                                                 unit="TFLOP/s", frac=theta_rate / PEAK["fp32"]),
+        "kernels_ms": kern, "fp64": fp64, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -146,6 +146,17 @@ int mps_circuit_validate(int n_qubits, const mpsb_circuit* c);
  * reduced in a fixed order (bitwise reproducible); per_traj [n_traj][2n-1] (or NULL). */
 int expect(mpsb_handle h, double* mean, double* m2, double* per_traj);
 
+/* Optional per-kernel-class timing with HIP events recorded on the batch stream (for
+ * roofline reports).  mps_profile(h, 1) resets and starts, (h, 0) stops.  mps_profile_read
+ * synchronises and returns, per class, the summed milliseconds and the number of timed
+ * launches (host arrays of n entries); the return value is the number of classes.  Class
+ * order: 0 theta contraction + gate + two-site RDM, 1 noise events (unravel + sample),
+ * 2 Kraus-pair application, 3 truncation Gram matrix, 4 tridiagonalisation, 5 tridiagonal
+ * eigenvalues + inverse iteration, 6 CholeskyQR2, 7 eigenvector back-transformation,
+ * 8 recomposition, 9 centre-hop contractions, 10 idle-qubit events, 11 observables. */
+int mps_profile(mpsb_handle h, int enable);
+int mps_profile_read(mpsb_handle h, double* ms, long long* count, int n);
+
 /* Blocks until all work of the handle is done; reports asynchronous device errors. */
 int mps_batch_sync(mpsb_handle h);
 int mps_batch_destroy(mpsb_handle h);

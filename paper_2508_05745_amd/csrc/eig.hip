@@ -446,14 +446,16 @@ __global__ __launch_bounds__(ET) void k_backtransform(int n, int keep, const c64
 size_t heev_ws_doubles(int n, int keep) { return (size_t)6 * n + (size_t)6 * n * keep + 64; }
 size_t heev_gws_doubles(int keep) { return (size_t)keep * keep + 64; }
 
-hipError_t heev(int n, int keep, double zero_tol, void* A, long long sA, double* ws, long long sW, double* gws,
-                long long sG, double* evals, long long sE, double* kept_sum, void* Z, long long sZ, int batch,
-                hipStream_t st) {
+hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long long sA, double* ws, long long sW,
+                      double* gws, long long sG, double* evals, long long sE, double* kept_sum, void* Z, long long sZ,
+                      int batch, hipStream_t st) {
   if (n > EMAX || keep > n || keep > EMAX / 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_tridiag, dim3(batch), dim3(ET), 0, st, n, (c64d*)A, sA, ws, sW);
-  hipLaunchKernelGGL(k_tri_eig, dim3(batch), dim3(ET), 0, st, n, keep, zero_tol, ws, sW, evals, sE, kept_sum);
-  hipLaunchKernelGGL(k_cholqr, dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, gws, sG);
-  hipLaunchKernelGGL(k_backtransform, dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
+  switch (phase) {
+    case 0: hipLaunchKernelGGL(k_tridiag, dim3(batch), dim3(ET), 0, st, n, (c64d*)A, sA, ws, sW); break;
+    case 1: hipLaunchKernelGGL(k_tri_eig, dim3(batch), dim3(ET), 0, st, n, keep, zero_tol, ws, sW, evals, sE, kept_sum); break;
+    case 2: hipLaunchKernelGGL(k_cholqr, dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, gws, sG); break;
+    default: hipLaunchKernelGGL(k_backtransform, dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ); break;
+  }
   return hipGetLastError();
 }
 

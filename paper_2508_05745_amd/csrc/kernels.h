@@ -37,9 +37,11 @@ hipError_t init_state(int prec, void* state, const long long* d_site_off, int n_
 
 size_t heev_ws_doubles(int n, int keep);
 size_t heev_gws_doubles(int keep);
-hipError_t heev(int n, int keep, double zero_tol, void* A, long long sA, double* ws, long long sW, double* gws,
-                long long sG, double* evals, long long sE, double* kept_sum, void* Z, long long sZ, int batch,
-                hipStream_t st);
+// phase 0: tridiagonalisation, 1: eigenvalues + inverse iteration, 2: CholeskyQR2,
+// 3: back-transformation
+hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long long sA, double* ws, long long sW,
+                      double* gws, long long sG, double* evals, long long sE, double* kept_sum, void* Z, long long sZ,
+                      int batch, hipStream_t st);
 
 hipError_t launch_gate_events(const EventArgs& ea, const double* partial, int n_tiles, int q, int has_s, int has_t,
                               double* kops, int* status, hipStream_t st);

@@ -137,7 +137,23 @@ int make_layout(int n_traj, int n, int chi, int prec, Layout& L) {
 
 }  // namespace
 
+// kernel classes timed by the optional profiler
+enum ProfClass {
+  PC_THETA = 0, PC_EVENTS, PC_KRAUS, PC_GRAM, PC_TRIDIAG, PC_TRIEIG, PC_CHOLQR, PC_BACK, PC_RECOMPOSE, PC_HOPGEMM,
+  PC_SMALL, PC_EXPECT, PC_COUNT
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<int> cls;                 // class of each recorded pair
+  double ms[PC_COUNT] = {0};
+  long long count[PC_COUNT] = {0};
+};
+
 struct mpsb_batch {
+  Prof prof;
   Layout L;
   uint64_t seed;
   char* state;
@@ -160,6 +176,61 @@ struct mpsb_batch {
 namespace {
 
 template <typename T> T* W(mpsb_batch* h, size_t off) { return (T*)(h->work + off); }
+
+void prof_collect(mpsb_batch* h);
+
+// RAII section: records a start / end event pair on the batch stream when profiling.
+struct ProfSec {
+  mpsb_batch* h;
+  bool active;
+  ProfSec(mpsb_batch* h_, int c) : h(h_), active(h_->prof.on) {
+    if (!active) return;
+    Prof& P = h->prof;
+    if (P.used >= 16384) prof_collect(h);
+    if (P.used + 2 > P.pool.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { active = false; return; }
+        P.pool.push_back(e);
+      }
+    }
+    P.cls.push_back(c);
+    (void)hipEventRecord(P.pool[P.used], h->st);
+    P.used++;
+  }
+  ~ProfSec() {
+    if (!active) return;
+    Prof& P = h->prof;
+    (void)hipEventRecord(P.pool[P.used], h->st);
+    P.used++;
+  }
+};
+
+void prof_collect(mpsb_batch* h) {
+  Prof& P = h->prof;
+  if (P.used == 0) return;
+  (void)hipStreamSynchronize(h->st);
+  for (size_t i = 0; i + 1 < P.used; i += 2) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, P.pool[i], P.pool[i + 1]) == hipSuccess) {
+      P.ms[P.cls[i / 2]] += ms;
+      P.count[P.cls[i / 2]] += 1;
+    }
+  }
+  P.used = 0;
+  P.cls.clear();
+}
+
+hipError_t heev_all(mpsb_batch* h, int n, int keep, double zt, void* A, long long sA, double* ws, long long sW,
+                    double* gws, long long sG, double* ev, long long sE, double* kept, void* Z, long long sZ, int batch) {
+  const int cls[4] = {PC_TRIDIAG, PC_TRIEIG, PC_CHOLQR, PC_BACK};
+  for (int ph = 0; ph < 4; ++ph) {
+    ProfSec s(h, cls[ph]);
+    hipError_t e = heev_phase(ph, n, keep, zt, A, sA, ws, sW, gws, sG, ev, sE, kept, Z, sZ, batch, h->st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 char* site_ptr(mpsb_batch* h, int k) { return h->state + (size_t)h->L.off[k] * h->L.esz; }
 int* status_ptr(mpsb_batch* h) { return W<int>(h, h->L.o_status); }
 
@@ -192,9 +263,13 @@ int hop_right(mpsb_batch* h, int j) {
   char* Cj = site_ptr(h, j);
   char* Bn = site_ptr(h, j + 1);
   double* gram = W<double>(h, L.o_gram);
-  HIPCHK(gemm(p, 1, true, false, cr, cr, 2 * cl, Cj, cr, L.s_traj, Cj, cr, L.s_traj, gram, cr, L.s_gram, nullptr, T, h->st));
-  HIPCHK(heev(cr, cr, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
-              W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), W<double>(h, L.o_z), L.s_z, T, h->st));
+  {
+    ProfSec s(h, PC_HOPGEMM);
+    HIPCHK(gemm(p, 1, true, false, cr, cr, 2 * cl, Cj, cr, L.s_traj, Cj, cr, L.s_traj, gram, cr, L.s_gram, nullptr, T, h->st));
+  }
+  HIPCHK(heev_all(h, cr, cr, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
+              W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), W<double>(h, L.o_z), L.s_z, T));
+  ProfSec shop(h, PC_HOPGEMM);
   double* invs = W<double>(h, L.o_invs);
   double* sq = W<double>(h, L.o_sqrt);
   HIPCHK(hop_scales(W<double>(h, L.o_evals), L.s_evals, cr, invs, sq, T, h->st));
@@ -220,9 +295,13 @@ int hop_left(mpsb_batch* h, int j) {
   char* Cj = site_ptr(h, j);
   char* Ap = site_ptr(h, j - 1);
   double* gram = W<double>(h, L.o_gram);
-  HIPCHK(gemm(p, 1, false, true, cl, cl, 2 * cr, Cj, 2 * cr, L.s_traj, Cj, 2 * cr, L.s_traj, gram, cl, L.s_gram, nullptr, T, h->st));
-  HIPCHK(heev(cl, cl, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
-              W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), W<double>(h, L.o_z), L.s_z, T, h->st));
+  {
+    ProfSec s(h, PC_HOPGEMM);
+    HIPCHK(gemm(p, 1, false, true, cl, cl, 2 * cr, Cj, 2 * cr, L.s_traj, Cj, 2 * cr, L.s_traj, gram, cl, L.s_gram, nullptr, T, h->st));
+  }
+  HIPCHK(heev_all(h, cl, cl, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
+              W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), W<double>(h, L.o_z), L.s_z, T));
+  ProfSec shop(h, PC_HOPGEMM);
   double* invs = W<double>(h, L.o_invs);
   double* sq = W<double>(h, L.o_sqrt);
   HIPCHK(hop_scales(W<double>(h, L.o_evals), L.s_evals, cl, invs, sq, T, h->st));
@@ -291,27 +370,38 @@ int two_site_step(mpsb_batch* h, int layer, int q, const Mat4& gate, int ch_s, i
   char* X = W<char>(h, L.o_x);
   double* partial = W<double>(h, L.o_partial);
   double* kops = W<double>(h, L.o_kops);
-  HIPCHK(theta(p, cl, cm, cr, Sq, Sn, L.s_traj, X, L.s_x, gate, partial, T, h->st));
+  {
+    ProfSec s(h, PC_THETA);
+    HIPCHK(theta(p, cl, cm, cr, Sq, Sn, L.s_traj, X, L.s_x, gate, partial, T, h->st));
+  }
   const int nt = theta_tiles(cl, cr);
   if (ch_s >= 0 || ch_t >= 0) {
     EventArgs ea = base_event_args(h, layer, branch, w_record, h->mode);
     if (ch_s >= 0) fill_channel_slot(h, ea, 0, ch_s);
     if (ch_t >= 0) fill_channel_slot(h, ea, 1, ch_t);
-    HIPCHK(launch_gate_events(ea, partial, nt, q, ch_s >= 0, ch_t >= 0, kops, status_ptr(h), h->st));
+    {
+      ProfSec s(h, PC_EVENTS);
+      HIPCHK(launch_gate_events(ea, partial, nt, q, ch_s >= 0, ch_t >= 0, kops, status_ptr(h), h->st));
+    }
+    ProfSec s(h, PC_KRAUS);
     HIPCHK(kraus_pair(p, cl, cr, X, L.s_x, kops, T, h->st));
   }
   double* gram = W<double>(h, L.o_gram);
   double* Z = W<double>(h, L.o_z);
   double* alpha = W<double>(h, L.o_alpha);
   const int n = left_to_right ? 2 * cl : 2 * cr;
-  if (left_to_right)
-    HIPCHK(gemm(p, 1, false, true, 2 * cl, 2 * cl, 2 * cr, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cl, L.s_gram, nullptr, T, h->st));
-  else
-    HIPCHK(gemm(p, 1, true, false, 2 * cr, 2 * cr, 2 * cl, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cr, L.s_gram, nullptr, T, h->st));
+  {
+    ProfSec s(h, PC_GRAM);
+    if (left_to_right)
+      HIPCHK(gemm(p, 1, false, true, 2 * cl, 2 * cl, 2 * cr, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cl, L.s_gram, nullptr, T, h->st));
+    else
+      HIPCHK(gemm(p, 1, true, false, 2 * cr, 2 * cr, 2 * cl, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cr, L.s_gram, nullptr, T, h->st));
+  }
   const int kk = std::min(keep, D);
-  HIPCHK(heev(n, kk, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
-              W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), Z, L.s_z, T, h->st));
+  HIPCHK(heev_all(h, n, kk, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
+              W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), Z, L.s_z, T));
   HIPCHK(trunc_factors(W<double>(h, L.o_kept), W<double>(h, L.o_ews), L.s_ews, n, alpha, discarded, disc_stride, accumulate, T, h->st));
+  ProfSec srec(h, PC_RECOMPOSE);
   if (left_to_right) {
     // A_q = U (2cl x D), columns >= kk zero; C_{q+1} = alpha A_q^dag X
     HIPCHK(scale_cast(p, 2 * cl, kk, Z, kk, L.s_z, nullptr, 0, false, Sq, D, L.s_traj, T, h->st));
@@ -337,6 +427,7 @@ int idle_step(mpsb_batch* h, int layer, int q, int ch, int mode, const int* d_fo
   char* S = site_ptr(h, q);
   double* rho1 = W<double>(h, L.o_rho1);
   double* kops = W<double>(h, L.o_kops);
+  ProfSec sidle(h, PC_SMALL);
   HIPCHK(site_rdm(p, dl(L, q), dr(L, q), S, L.s_traj, rho1, T, h->st));
   EventArgs ea = base_event_args(h, layer, branch, w_record, mode);
   if (per_call_record) {
@@ -596,6 +687,7 @@ int expect(mpsb_handle h, double* mean, double* m2, double* per_traj) {
   const long long se = L.s_env;   // c128 elements per slot
   char* ex = W<char>(h, L.o_exp);
   const int chunk = L.exp_chunk;
+  ProfSec sexp(h, PC_EXPECT);
   for (int t0 = 0; t0 < T; t0 += chunk) {
     const int ct = std::min(chunk, T - t0);
     // per trajectory of the chunk: [R_0 .. R_n][L][Lz][Lzp][Y][Tm][site]
@@ -672,6 +764,21 @@ int expect(mpsb_handle h, double* mean, double* m2, double* per_traj) {
   return MPSB_OK;
 }
 
+int mps_profile(mpsb_handle h, int enable) {
+  if (!h) return fail(MPSB_EINVAL, "null handle");
+  prof_collect(h);
+  for (int c = 0; c < PC_COUNT; ++c) { h->prof.ms[c] = 0; h->prof.count[c] = 0; }
+  h->prof.on = enable != 0;
+  return MPSB_OK;
+}
+
+int mps_profile_read(mpsb_handle h, double* ms, long long* count, int n) {
+  if (!h || !ms || !count) return fail(MPSB_EINVAL, "null argument");
+  prof_collect(h);
+  for (int c = 0; c < n && c < PC_COUNT; ++c) { ms[c] = h->prof.ms[c]; count[c] = h->prof.count[c]; }
+  return PC_COUNT;
+}
+
 int mps_batch_sync(mpsb_handle h) {
   if (!h) return fail(MPSB_EINVAL, "null handle");
   HIPCHK(hipStreamSynchronize(h->st));
@@ -680,6 +787,8 @@ int mps_batch_sync(mpsb_handle h) {
 
 int mps_batch_destroy(mpsb_handle h) {
   if (!h) return fail(MPSB_EINVAL, "null handle");
+  (void)hipStreamSynchronize(h->st);
+  for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
   delete h;
   return MPSB_OK;
 }
