@@ -140,10 +140,9 @@ __device__ void cost_setup(const double* rho_in, const double* kraus, const doub
       for (int j = 0; j < 4; ++j) H[i][j] = H[i][j] + params[k] * g[i][j];
   }
   for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
-      X[i][j] = cd{-H[i][j].im, H[i][j].re};                 // iH
-      Xh[i][j] = cd{H[j][i].im, -H[j][i].re};                // (iH)^dag = -i H^dag
-    }
+    for (int j = 0; j < 4; ++j) X[i][j] = cd{-H[i][j].im, H[i][j].re};   // iH
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) Xh[i][j] = conj(X[j][i]);                // (iH)^dag
   expm<4>(X, E);
   mm<4>(E, Ur, cs.U);
   for (int j = 0; j < 4; ++j) {

@@ -1,16 +1,16 @@
 // Batched FP64 Hermitian eigensolver for the truncation Gram matrices and the centre hops.
 //
 // For each matrix (one workgroup per matrix and phase):
-//   E1  Householder reduction to tridiagonal form, A = Q T Q^dag, Q = H_0 H_1 ... H_{n-3},
-//       H_j = I - 2 u_j u_j^dag; the reflector vectors overwrite the strict upper triangle;
+//   E1  blocked Householder reduction to tridiagonal form, A = Q T Q^dag,
+//       Q = H_0 H_1 ... H_{n-3}, H_j = I - 2 u_j u_j^dag, only the lower triangle of A is read
+//       or written; the reflector vectors overwrite the strict lower triangle;
 //   E2  a diagonal phase similarity makes T real symmetric; the `keep` largest
 //       eigenvalues by Sturm-count bisection (one thread per eigenvalue); eigenvectors of
 //       the real tridiagonal by inverse iteration with partial-pivoting LU (one thread
 //       per eigenvalue); eigenvalues <= zero_tol * lambda_max are dropped (value 0, vector
 //       0: such directions carry no weight of the state);
-//   E3  CholeskyQR2 orthonormalisation of the kept vectors (restores orthogonality inside
-//       clusters of close eigenvalues);
-//   E4  back-transformation evec = Q diag(omega) X with blocked compact-WY reflectors.
+//       clusters of relatively close eigenvalues are reorthogonalised inside the iteration;
+//   E3  back-transformation evec = Q diag(omega) X with blocked compact-WY reflectors.
 // Outputs: eigenvalues (descending), eigenvectors n x keep (row-major, ld keep) c128,
 // the trace of the input and the sum of the kept eigenvalues.
 #include <float.h>
@@ -36,95 +36,217 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------- E1
+// Blocked Householder tridiagonalisation reading and writing only the lower triangle.
+// Panels of NB columns are reduced with the trailing matrix kept in the deferred form
+// A - 2 (V W^dag + W V^dag); each column needs one pass over the lower triangle of the
+// trailing matrix (the matrix-vector product), and the panel's rank-2NB update is applied
+// once at the end of the panel.  The panel vectors live in LDS (column-major by vector, so
+// that lanes read consecutive rows).  u_j is kept in column j below the diagonal.
+template <int NMAX, int NB, int RB>
 __global__ __launch_bounds__(ET) void k_tridiag(int n, c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
                                                 long long sW) {
-  __shared__ c64d su[EMAX], sp[EMAX];
+  __shared__ c64d Vt[NB][NMAX], Wt[NB][NMAX];
+  __shared__ c64d su[NMAX], sp[NMAX];
+  __shared__ c64d part[ET / 64][NMAX];
+  __shared__ c64d cdot[2 * NB];
   __shared__ double red[ET / 64];
-  __shared__ double s_scal[4];
   c64d* A = Ag + blockIdx.x * sA;
   double* W = ws + blockIdx.x * sW;
   double* d = W;                          // [n]
-  c64d* ec = (c64d*)(W + n);              // [n]   subdiagonal T[j+1][j] (complex)
+  c64d* ec = (c64d*)(W + n);              // [n]   subdiagonal T[j+1][j]
   double* tr = W + 3 * n;                 // [1]   trace
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int SLOTS = NMAX / 64;
 
-  // trace of the input
   double t = 0;
   for (int i = tid; i < n; i += ET) t += A[(long long)i * n + i].re;
   t = block_sum(t, red);
   if (tid == 0) tr[0] = t;
 
-  for (int j = 0; j + 2 < n; ++j) {
-    const int m = n - j - 1;
-    const c64d* row = A + (long long)j * n + (j + 1);
-    // alpha = ||x||, x_i = conj(A[j][j+1+i])
-    double s2 = 0;
-    for (int i = tid; i < m; i += ET) s2 += norm2(row[i]);
-    s2 = block_sum(s2, red);
-    const double alpha = sqrt(s2);
-    const c64d x0 = conj(row[0]);
-    const double ax0 = sqrt(norm2(x0));
-    if (alpha <= 1e-300) {
-      // nothing to annihilate: H = I
-      for (int i = tid; i < m; i += ET) A[(long long)j * n + j + 1 + i] = c64d{0, 0};
-      if (tid == 0) ec[j] = x0;
+  for (int j0 = 0; j0 + 2 < n; j0 += NB) {
+    const int jb = min(NB, n - 2 - j0);
+    for (int k = 0; k < jb; ++k) {
+      const int j = j0 + k;
+      const int m = n - j - 1;
+      // corrected column j (rows j..n-1) -> su (rows j+1..) and the diagonal
+      for (int r = j + tid; r < n; r += ET) {
+        c64d a = A[(long long)r * n + j];
+        for (int kk = 0; kk < k; ++kk) {
+          c64d corr = Vt[kk][r] * conj(Wt[kk][j]) + Wt[kk][r] * conj(Vt[kk][j]);
+          a = a - 2.0 * corr;
+        }
+        if (r == j) d[j] = a.re;
+        else su[r - j - 1] = a;
+      }
       __syncthreads();
-      continue;
-    }
-    const c64d ph = ax0 > 0 ? c64d{x0.re / ax0, x0.im / ax0} : c64d{1.0, 0.0};
-    const double vn = sqrt(2.0 * alpha * (alpha + ax0));
-    __syncthreads();
-    for (int i = tid; i < m; i += ET) {
-      c64d xi = conj(row[i]);
-      if (i == 0) xi = xi + alpha * ph;
-      su[i] = c64d{xi.re / vn, xi.im / vn};
-    }
-    __syncthreads();
-    // p = A22 u, one wave per row
-    for (int i = wv; i < m; i += ET / 64) {
-      const c64d* r = A + (long long)(j + 1 + i) * n + (j + 1);
-      double pr = 0, pi = 0;
-      for (int k = lane; k < m; k += 64) {
-        c64d a = r[k], u = su[k];
-        pr += a.re * u.re - a.im * u.im;
-        pi += a.re * u.im + a.im * u.re;
+      double s2 = 0;
+      for (int i = tid; i < m; i += ET) s2 += norm2(su[i]);
+      s2 = block_sum(s2, red);
+      const double alpha = sqrt(s2);
+      const c64d x0 = su[0];
+      const double ax0 = sqrt(norm2(x0));
+      const bool skip = !(alpha > 1e-300);
+      const c64d ph = ax0 > 0 ? c64d{x0.re / ax0, x0.im / ax0} : c64d{1.0, 0.0};
+      const double vn = skip ? 1.0 : sqrt(2.0 * alpha * (alpha + ax0));
+      __syncthreads();
+      for (int i = tid; i < m; i += ET) {
+        c64d xi = su[i];
+        if (i == 0) xi = xi + alpha * ph;
+        c64d u = skip ? c64d{0, 0} : c64d{xi.re / vn, xi.im / vn};
+        su[i] = u;
+        A[(long long)(j + 1 + i) * n + j] = u;
+      }
+      for (int r = tid; r <= j; r += ET) Vt[k][r] = c64d{0, 0};
+      if (tid == 0) ec[j] = skip ? x0 : c64d{-ph.re * alpha, -ph.im * alpha};
+      __syncthreads();
+      for (int i = tid; i < m; i += ET) Vt[k][j + 1 + i] = su[i];
+      // p = (lower-stored Hermitian A22) u: row parts by waves (RB rows at a time, loads
+      // issued together), column parts accumulated in registers (lane owns columns
+      // lane + 64 s)
+      c64d colacc[SLOTS];
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) colacc[s] = c64d{0, 0};
+      for (int i0 = wv * RB; i0 < m; i0 += (ET / 64) * RB) {
+        c64d av[RB][SLOTS];
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+          const int i = i0 + rr;
+          const c64d* row = A + (long long)(j + 1 + i) * n + (j + 1);
+#pragma unroll
+          for (int s = 0; s < SLOTS; ++s) {
+            const int kk = lane + 64 * s;
+            av[rr][s] = (i < m && kk <= i) ? row[kk] : c64d{0, 0};
+          }
+        }
+        double pr[RB], pim[RB];
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+          const int i = i0 + rr;
+          const c64d ui = i < m ? su[i] : c64d{0, 0};
+          pr[rr] = 0;
+          pim[rr] = 0;
+#pragma unroll
+          for (int s = 0; s < SLOTS; ++s) {
+            const int kk = lane + 64 * s;
+            const c64d a = av[rr][s];
+            const c64d uk = su[kk < m ? kk : 0];
+            pr[rr] += a.re * uk.re - a.im * uk.im;
+            pim[rr] += a.re * uk.im + a.im * uk.re;
+            if (kk < i) {
+              colacc[s].re += a.re * ui.re + a.im * ui.im;
+              colacc[s].im += a.re * ui.im - a.im * ui.re;
+            }
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+          for (int rr = 0; rr < RB; ++rr) {
+            pr[rr] += __shfl_down(pr[rr], off, 64);
+            pim[rr] += __shfl_down(pim[rr], off, 64);
+          }
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int rr = 0; rr < RB; ++rr)
+            if (i0 + rr < m) sp[i0 + rr] = c64d{pr[rr], pim[rr]};
+        }
       }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        pr += __shfl_down(pr, off, 64);
-        pi += __shfl_down(pi, off, 64);
+      for (int s = 0; s < SLOTS; ++s) {
+        const int kk = lane + 64 * s;
+        if (kk < m) part[wv][kk] = colacc[s];
       }
-      if (lane == 0) sp[i] = c64d{pr, pi};
+      // dot products of the panel vectors with u (rows j+1..n-1)
+      for (int dd = wv; dd < 2 * k; dd += ET / 64) {
+        const int kk = dd >> 1;
+        const bool isw = dd & 1;
+        double cr = 0, ci = 0;
+        for (int i = lane; i < m; i += 64) {
+          c64d v = isw ? Wt[kk][j + 1 + i] : Vt[kk][j + 1 + i];
+          c64d u = su[i];
+          cr += v.re * u.re + v.im * u.im;
+          ci += v.re * u.im - v.im * u.re;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          cr += __shfl_down(cr, off, 64);
+          ci += __shfl_down(ci, off, 64);
+        }
+        if (lane == 0) cdot[dd] = c64d{cr, ci};   // even: V^dag u, odd: W^dag u
+      }
+      __syncthreads();
+      for (int i = tid; i < m; i += ET) {
+        c64d p = sp[i];
+#pragma unroll
+        for (int w = 0; w < ET / 64; ++w) p = p + part[w][i];
+        const int r = j + 1 + i;
+        for (int kk = 0; kk < k; ++kk) {
+          c64d corr = Vt[kk][r] * cdot[2 * kk + 1] + Wt[kk][r] * cdot[2 * kk];
+          p = p - 2.0 * corr;
+        }
+        sp[i] = p;
+      }
+      __syncthreads();
+      double kq = 0;
+      for (int i = tid; i < m; i += ET) kq += su[i].re * sp[i].re + su[i].im * sp[i].im;
+      kq = block_sum(kq, red);
+      for (int r = tid; r <= j; r += ET) Wt[k][r] = c64d{0, 0};
+      for (int i = tid; i < m; i += ET) Wt[k][j + 1 + i] = sp[i] - kq * su[i];
+      __syncthreads();
+    }
+    // trailing update of the lower triangle, rows/cols >= t0:
+    // A[r][c] -= 2 sum_k (V[r][k] conj(W[c][k]) + W[r][k] conj(V[c][k])), RB rows per wave and
+    // SLOTS columns per lane register-blocked
+    const int t0 = j0 + jb;
+    for (int r0 = t0 + wv * RB; r0 < n; r0 += (ET / 64) * RB) {
+      c64d acc[RB][SLOTS];
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) acc[rr][s] = c64d{0, 0};
+      for (int kk = 0; kk < jb; ++kk) {
+        c64d vr[RB], wr[RB], vc[SLOTS], wc[SLOTS];
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+          const int r = min(r0 + rr, n - 1);
+          vr[rr] = Vt[kk][r];
+          wr[rr] = Wt[kk][r];
+        }
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+          const int c = min(t0 + lane + 64 * s, n - 1);
+          vc[s] = conj(Vt[kk][c]);
+          wc[s] = conj(Wt[kk][c]);
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+          for (int s = 0; s < SLOTS; ++s) acc[rr][s] = acc[rr][s] + vr[rr] * wc[s] + wr[rr] * vc[s];
+      }
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const int r = r0 + rr;
+        if (r >= n) continue;
+        c64d* row = A + (long long)r * n;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+          const int c = t0 + lane + 64 * s;
+          if (c <= r) row[c] = row[c] - 2.0 * acc[rr][s];
+        }
+      }
     }
     __syncthreads();
-    // K = Re(u^dag p); w = p - K u (kept in sp)
-    double kk = 0;
-    for (int i = tid; i < m; i += ET) kk += su[i].re * sp[i].re + su[i].im * sp[i].im;
-    kk = block_sum(kk, red);
-    for (int i = tid; i < m; i += ET) sp[i] = sp[i] - kk * su[i];
-    __syncthreads();
-    // A22 -= 2 (u w^dag + w u^dag)
-    for (int i = wv; i < m; i += ET / 64) {
-      const c64d ui = su[i], wi = sp[i];
-      c64d* r = A + (long long)(j + 1 + i) * n + (j + 1);
-      for (int k = lane; k < m; k += 64) {
-        c64d uk = su[k], wk = sp[k];
-        c64d upd = ui * conj(wk) + wi * conj(uk);
-        r[k] = r[k] - 2.0 * upd;
-      }
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      d[n - 2] = A[(long long)(n - 2) * n + (n - 2)].re;
+      d[n - 1] = A[(long long)(n - 1) * n + (n - 1)].re;
+      ec[n - 2] = A[(long long)(n - 1) * n + (n - 2)];
+    } else {
+      d[0] = A[0].re;
     }
-    // keep u in row j, the subdiagonal element in ec
-    for (int i = tid; i < m; i += ET) A[(long long)j * n + j + 1 + i] = su[i];
-    if (tid == 0) ec[j] = c64d{-ph.re * alpha, -ph.im * alpha};
-    __syncthreads();
   }
-  if (n >= 2 && tid == 0) ec[n - 2] = conj(A[(long long)(n - 2) * n + (n - 1)]);
-  if (tid == 0 && n >= 2) {
-    // the last reflector slot (row n-2) holds no reflector
-    A[(long long)(n - 2) * n + (n - 1)] = c64d{0, 0};
-  }
-  __syncthreads();
-  for (int i = tid; i < n; i += ET) d[i] = A[(long long)i * n + i].re;
 }
 
 // ---------------------------------------------------------------------------- E2
@@ -218,80 +340,99 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
   const double lmax = ev[0];
   const double cut = fmax(zero_tol * fmax(lmax, 0.0), 1e-300);
 
-  // ---- inverse iteration, one thread per kept eigenvalue
-  for (int k = tid; k < keep; k += ET) {
-    const double lam = ev[k];
-    const bool drop = !(lam > cut);
-    if (drop) {
-      for (int i = 0; i < n; ++i) X[(long long)i * keep + k] = 0.0;
-      continue;
+  // ---- clusters of relatively close kept eigenvalues (gap < 1e-3 of the eigenvalue):
+  // their vectors are computed by one thread, each orthogonalised against the previous
+  // members of its cluster after every solve.  Other eigenvalues are isolated relative to
+  // their size, so inverse iteration alone yields vectors accurate to eps * lambda_max / gap.
+  __shared__ short cl_end[EMAX];
+  if (tid == 0) {
+    int k = 0;
+    while (k < keep) {
+      int e = k + 1;
+      while (e < keep && ev[e - 1] > cut && ev[e] > cut && (ev[e - 1] - ev[e]) < 1e-3 * ev[e - 1]) ++e;
+      for (int q = k; q < e; ++q) cl_end[q] = (short)(q == k ? e : -1);
+      k = e;
     }
-    // perturb the shift by a relative eps so that the factorisation is never exactly singular
-    const double sig = lam + 4.0 * DBL_EPSILON * tnorm * (1.0 + 0.37 * (k & 7));
-    const double tiny = DBL_EPSILON * tnorm + 1e-300;
-    // LU with partial pivoting of T - sig I
-    double cd = sd[0] - sig, cs = (n > 1) ? se[0] : 0.0;
-    for (int i = 0; i + 1 < n; ++i) {
-      const double sub = se[i], nd = sd[i + 1] - sig, ns = (i + 2 < n) ? se[i + 1] : 0.0;
-      const long long o = (long long)i * keep + k;
-      if (fabs(cd) >= fabs(sub)) {
-        double l = (cd != 0.0) ? sub / cd : 0.0;
-        U0[o] = (cd != 0.0) ? cd : tiny;
-        U1[o] = cs;
-        U2[o] = 0.0;
-        L[o] = l;
-        PV[o] = 0.0;
-        cd = nd - l * cs;
-        cs = ns;
-      } else {
-        double l = cd / sub;
-        U0[o] = sub;
-        U1[o] = nd;
-        U2[o] = ns;
-        L[o] = l;
-        PV[o] = 1.0;
-        cd = cs - l * nd;
-        cs = -l * ns;
+  }
+  __syncthreads();
+  for (int k0 = tid; k0 < keep; k0 += ET) {
+    const int kend = cl_end[k0];
+    if (kend < 0) continue;
+    for (int k = k0; k < kend; ++k) {
+      const double lam = ev[k];
+      if (!(lam > cut)) {
+        for (int i = 0; i < n; ++i) X[(long long)i * keep + k] = 0.0;
+        continue;
       }
-    }
-    U0[(long long)(n - 1) * keep + k] = (cd != 0.0) ? cd : tiny;
-    // start vector: deterministic pseudo-random in [0.5, 1.5)
-    for (int i = 0; i < n; ++i)
-      X[(long long)i * keep + k] = 0.5 + (hash32((uint32_t)(i * 7919 + k * 104729 + 17)) >> 8) * (1.0 / 16777216.0);
-    for (int itr = 0; itr < 3; ++itr) {
-      if (itr > 0) {
-        // apply P and L^{-1}
-        for (int i = 0; i + 1 < n; ++i) {
-          const long long o = (long long)i * keep + k;
-          double xi = X[o], xn = X[o + keep];
-          if (PV[o] != 0.0) { double tmp = xi; xi = xn; xn = tmp; }
-          xn -= L[o] * xi;
-          X[o] = xi;
-          X[o + keep] = xn;
+      // perturbed shift so that the factorisation is never exactly singular
+      const double sig = lam + 4.0 * DBL_EPSILON * tnorm * (1.0 + 0.37 * (k & 7));
+      const double tiny = DBL_EPSILON * tnorm + 1e-300;
+      double cd = sd[0] - sig, cs = (n > 1) ? se[0] : 0.0;
+      for (int i = 0; i + 1 < n; ++i) {
+        const double sub = se[i], nd = sd[i + 1] - sig, ns = (i + 2 < n) ? se[i + 1] : 0.0;
+        const long long o = (long long)i * keep + k;
+        if (fabs(cd) >= fabs(sub)) {
+          double l = (cd != 0.0) ? sub / cd : 0.0;
+          U0[o] = (cd != 0.0) ? cd : tiny;
+          U1[o] = cs;
+          U2[o] = 0.0;
+          L[o] = l;
+          PV[o] = 0.0;
+          cd = nd - l * cs;
+          cs = ns;
+        } else {
+          double l = cd / sub;
+          U0[o] = sub;
+          U1[o] = nd;
+          U2[o] = ns;
+          L[o] = l;
+          PV[o] = 1.0;
+          cd = cs - l * nd;
+          cs = -l * ns;
         }
       }
-      // U^{-1}
-      double y1 = 0.0, y2 = 0.0, mx = 0.0;
-      for (int i = n - 1; i >= 0; --i) {
-        const long long o = (long long)i * keep + k;
-        double y = (X[o] - U1[o] * y1 - U2[o] * y2) / U0[o];
-        if (i == n - 1) y = X[o] / U0[o];
-        else if (i == n - 2) y = (X[o] - U1[o] * y1) / U0[o];
-        X[o] = y;
-        y2 = y1;
-        y1 = y;
-        mx = fmax(mx, fabs(y));
+      U0[(long long)(n - 1) * keep + k] = (cd != 0.0) ? cd : tiny;
+      for (int i = 0; i < n; ++i)
+        X[(long long)i * keep + k] = 0.5 + (hash32((uint32_t)(i * 7919 + k * 104729 + 17)) >> 8) * (1.0 / 16777216.0);
+      for (int itr = 0; itr < 2; ++itr) {
+        if (itr > 0) {
+          for (int i = 0; i + 1 < n; ++i) {
+            const long long o = (long long)i * keep + k;
+            double xi = X[o], xn = X[o + keep];
+            if (PV[o] != 0.0) { double tmp = xi; xi = xn; xn = tmp; }
+            xn -= L[o] * xi;
+            X[o] = xi;
+            X[o + keep] = xn;
+          }
+        }
+        double y1 = 0.0, y2 = 0.0, mx = 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+          const long long o = (long long)i * keep + k;
+          double v = X[o];
+          if (i + 1 < n) v -= U1[o] * y1;
+          if (i + 2 < n) v -= U2[o] * y2;
+          const double y = v / U0[o];
+          X[o] = y;
+          y2 = y1;
+          y1 = y;
+          mx = fmax(mx, fabs(y));
+        }
+        const double sc = (mx > 0) ? 1.0 / mx : 1.0;
+        for (int i = 0; i < n; ++i) X[(long long)i * keep + k] *= sc;
+        // orthogonalise against the previous members of the cluster
+        for (int p = k0; p < k; ++p) {
+          double dot = 0;
+          for (int i = 0; i < n; ++i) dot += X[(long long)i * keep + p] * X[(long long)i * keep + k];
+          for (int i = 0; i < n; ++i) X[(long long)i * keep + k] -= dot * X[(long long)i * keep + p];
+        }
+        double nn = 0;
+        for (int i = 0; i < n; ++i) {
+          const double y = X[(long long)i * keep + k];
+          nn += y * y;
+        }
+        const double inv = nn > 0 ? 1.0 / sqrt(nn) : 0.0;
+        for (int i = 0; i < n; ++i) X[(long long)i * keep + k] *= inv;
       }
-      double sc = (mx > 0) ? 1.0 / mx : 1.0;
-      double nn = 0;
-      for (int i = 0; i < n; ++i) {
-        const long long o = (long long)i * keep + k;
-        double y = X[o] * sc;
-        X[o] = y;
-        nn += y * y;
-      }
-      double inv = 1.0 / sqrt(nn);
-      for (int i = 0; i < n; ++i) X[(long long)i * keep + k] *= inv;
     }
   }
   __syncthreads();
@@ -307,135 +448,124 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
 }
 
 // ---------------------------------------------------------------------------- E3
-// CholeskyQR2 of the n x keep real matrix X (component-major), zero columns left alone.
-__global__ __launch_bounds__(ET) void k_cholqr(int n, int keep, double* __restrict__ ws, long long sW,
-                                               double* __restrict__ gws, long long sG) {
-  double* W = ws + blockIdx.x * sW;
-  double* X = W + 6 * n;
-  double* G = gws + blockIdx.x * sG;     // keep x keep
-  const int tid = threadIdx.x;
-  __shared__ double piv[EMAX];
-  for (int pass = 0; pass < 2; ++pass) {
-    // G = X^T X (lower + diag)
-    const int kk = keep * keep;
-    for (int e = tid; e < kk; e += ET) {
-      int a = e / keep, b = e % keep;
-      if (b > a) continue;
-      double s = 0;
-      for (int i = 0; i < n; ++i) s += X[(long long)i * keep + a] * X[(long long)i * keep + b];
-      G[(long long)a * keep + b] = s;
-    }
-    __syncthreads();
-    // right-looking Cholesky of the lower triangle; zero / dependent pivots -> column dropped
-    for (int c = 0; c < keep; ++c) {
-      double g = G[(long long)c * keep + c];
-      __syncthreads();
-      bool ok = g > 1e-28;
-      double r = ok ? sqrt(g) : 0.0;
-      if (tid == 0) piv[c] = r;
-      for (int i = c + 1 + tid; i < keep; i += ET) G[(long long)i * keep + c] = ok ? G[(long long)i * keep + c] / r : 0.0;
-      __syncthreads();
-      const int m = keep - c - 1;
-      const int mm = m * m;
-      for (int e = tid; e < mm; e += ET) {
-        int i = c + 1 + e / m, l = c + 1 + e % m;
-        if (l > i) continue;
-        G[(long long)i * keep + l] -= G[(long long)i * keep + c] * G[(long long)l * keep + c];
-      }
-      __syncthreads();
-    }
-    // X <- X R^{-1}, R = L^T, one thread per row of X
-    for (int i = tid; i < n; i += ET) {
-      double* xr = X + (long long)i * keep;
-      for (int c = 0; c < keep; ++c) {
-        double v = xr[c];
-        for (int l = 0; l < c; ++l) v -= xr[l] * G[(long long)c * keep + l];
-        xr[c] = (piv[c] > 0) ? v / piv[c] : 0.0;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------- E4
-// evec = Q diag(omega) X, Q = H_0 ... H_{n-3}; reflectors applied in blocks of NB from the
-// last block to the first as (I - V T V^dag).
-constexpr int NB = 16;
+// evec = Q diag(omega) X, Q = H_0 ... H_{n-3} with u_j in column j below the diagonal;
+// reflectors are applied in blocks of NB from the last block to the first as
+// (I - V T V^dag), with V staged in LDS.  Thread c owns column c of Z (and, when keep is
+// smaller than the workgroup, one of several row slices of it).
+template <int NMAX, int NB>
 __global__ __launch_bounds__(ET) void k_backtransform(int n, int keep, const c64d* __restrict__ Ag, long long sA,
                                                       double* __restrict__ ws, long long sW,
                                                       c64d* __restrict__ Zg, long long sZ) {
+  __shared__ c64d Vb[NMAX][NB];
   __shared__ c64d Tm[NB][NB];
   __shared__ c64d Sv[NB][NB];
-  __shared__ c64d Wt[NB][EMAX / 2];        // NB x keep (keep <= 256)
+  __shared__ c64d Wred[ET][NB];
   const c64d* A = Ag + blockIdx.x * sA;
   double* W = ws + blockIdx.x * sW;
   const c64d* om = (const c64d*)(W + 4 * n);
   const double* X = W + 6 * n;
   c64d* Z = Zg + blockIdx.x * sZ;
   const int tid = threadIdx.x;
+  const int nslice = keep >= ET ? 1 : ET / keep;           // row slices per column
+  const int c = tid % keep, slice = tid / keep;
+  const bool active = tid < keep * nslice;
   // Z = diag(omega) X
-  for (int i = 0; i < n; ++i)
-    for (int c = tid; c < keep; c += ET) {
-      double x = X[(long long)i * keep + c];
-      Z[(long long)i * keep + c] = c64d{om[i].re * x, om[i].im * x};
-    }
+  for (int i = tid; i < n * keep; i += ET) {
+    const int r = i / keep;
+    const double x = X[i];
+    Z[i] = c64d{om[r].re * x, om[r].im * x};
+  }
   __syncthreads();
-  const int nref = n - 2;   // reflectors j = 0 .. n-3
+  const int nref = n - 2;
   if (nref <= 0) return;
   const int nblk = (nref + NB - 1) / NB;
   for (int blk = nblk - 1; blk >= 0; --blk) {
     const int j0 = blk * NB, nb = min(NB, nref - j0);
-    // u_j (column jj of V) lives in row j of A at columns j+1..n-1; V[i][jj] = A[j][i] for i > j
-    // S = V^dag V
+    for (int e = tid; e < n * NB; e += ET) {
+      const int i = e / NB, a = e % NB;
+      const int ja = j0 + a;
+      Vb[i][a] = (a < nb && i > ja) ? A[(long long)i * n + ja] : c64d{0, 0};
+    }
+    __syncthreads();
     for (int e = tid; e < nb * nb; e += ET) {
-      int a = e / nb, b = e % nb;
-      int ja = j0 + a, jb = j0 + b;
-      int start = max(ja, jb) + 1;
+      const int a = e / nb, b = e % nb;
       c64d s = {0, 0};
-      for (int i = start; i < n; ++i) s = s + cmulc(A[(long long)ja * n + i], A[(long long)jb * n + i]);
+      for (int i = j0 + 1; i < n; ++i) s = s + cmulc(Vb[i][a], Vb[i][b]);
       Sv[a][b] = s;
     }
     __syncthreads();
-    if (tid == 0) {
-      // T upper triangular: T_jj = 2, T[0:j, j] = -2 T[0:j, 0:j] S[0:j, j]
-      for (int a = 0; a < nb; ++a)
-        for (int b = 0; b < nb; ++b) Tm[a][b] = c64d{0, 0};
-      for (int jj = 0; jj < nb; ++jj) {
-        for (int a = 0; a < jj; ++a) {
+    for (int e = tid; e < NB * NB; e += ET) Tm[e / NB][e % NB] = c64d{0, 0};
+    __syncthreads();
+    for (int jj = 0; jj < nb; ++jj) {
+      if (tid < jj) {
+        const int a = tid;
+        c64d s = {0, 0};
+        for (int b = a; b < jj; ++b) s = s + Tm[a][b] * Sv[b][jj];
+        Tm[a][jj] = -2.0 * s;
+      }
+      if (tid == 0) Tm[jj][jj] = c64d{2.0, 0.0};
+      __syncthreads();
+    }
+    // Wt = V^dag Z (column c, partial over this thread's row slice)
+    c64d acc[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) acc[a] = c64d{0, 0};
+    if (active) {
+      int i = j0 + 1 + slice;
+      for (; i + 3 * nslice < n; i += 4 * nslice) {
+        c64d z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z[u] = Z[(long long)(i + u * nslice) * keep + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int a = 0; a < NB; ++a) acc[a] = acc[a] + cmulc(Vb[i + u * nslice][a], z[u]);
+      }
+      for (; i < n; i += nslice) {
+        const c64d z = Z[(long long)i * keep + c];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) acc[a] = acc[a] + cmulc(Vb[i][a], z);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) Wred[tid][a] = acc[a];
+    __syncthreads();
+    c64d wt[NB];
+    if (active) {
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        c64d s = {0, 0};
+        for (int q = 0; q < nslice; ++q) s = s + Wred[q * keep + c][a];
+        wt[a] = s;
+      }
+      // wt <- T wt
+      c64d tw[NB];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        c64d s = {0, 0};
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          if (b >= a && b < nb) s = s + Tm[a][b] * wt[b];
+        tw[a] = s;
+      }
+      // Z -= V tw
+      int i = j0 + 1 + slice;
+      for (; i + 3 * nslice < n; i += 4 * nslice) {
+        c64d z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z[u] = Z[(long long)(i + u * nslice) * keep + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
           c64d s = {0, 0};
-          for (int b = a; b < jj; ++b) s = s + Tm[a][b] * Sv[b][jj];
-          Tm[a][jj] = -2.0 * s;
+#pragma unroll
+          for (int a = 0; a < NB; ++a) s = s + Vb[i + u * nslice][a] * tw[a];
+          Z[(long long)(i + u * nslice) * keep + c] = z[u] - s;
         }
-        Tm[jj][jj] = c64d{2.0, 0.0};
       }
-    }
-    __syncthreads();
-    // Wt = V^dag Z  (nb x keep)
-    for (int e = tid; e < nb * keep; e += ET) {
-      int a = e / keep, c = e % keep;
-      int ja = j0 + a;
-      c64d s = {0, 0};
-      for (int i = ja + 1; i < n; ++i) s = s + cmulc(A[(long long)ja * n + i], Z[(long long)i * keep + c]);
-      Wt[a][c] = s;
-    }
-    __syncthreads();
-    // Wt = T Wt (upper triangular, in place top-down)
-    for (int c = tid; c < keep; c += ET) {
-      c64d tmp[NB];
-      for (int a = 0; a < nb; ++a) {
+      for (; i < n; i += nslice) {
         c64d s = {0, 0};
-        for (int b = a; b < nb; ++b) s = s + Tm[a][b] * Wt[b][c];
-        tmp[a] = s;
-      }
-      for (int a = 0; a < nb; ++a) Wt[a][c] = tmp[a];
-    }
-    __syncthreads();
-    // Z -= V Wt
-    for (int i = j0 + 1; i < n; ++i) {
-      const int amax = min(nb, i - j0);   // V[i][a] nonzero only if i > j0 + a
-      for (int c = tid; c < keep; c += ET) {
-        c64d s = {0, 0};
-        for (int a = 0; a < amax; ++a) s = s + A[(long long)(j0 + a) * n + i] * Wt[a][c];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) s = s + Vb[i][a] * tw[a];
         Z[(long long)i * keep + c] = Z[(long long)i * keep + c] - s;
       }
     }
@@ -449,12 +579,24 @@ size_t heev_gws_doubles(int keep) { return (size_t)keep * keep + 64; }
 hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long long sA, double* ws, long long sW,
                       double* gws, long long sG, double* evals, long long sE, double* kept_sum, void* Z, long long sZ,
                       int batch, hipStream_t st) {
-  if (n > EMAX || keep > n || keep > EMAX / 2) return hipErrorInvalidValue;
+  if (n > EMAX || keep > n || keep > EMAX / 2 || keep < 1) return hipErrorInvalidValue;
+  (void)gws;
+  (void)sG;
   switch (phase) {
-    case 0: hipLaunchKernelGGL(k_tridiag, dim3(batch), dim3(ET), 0, st, n, (c64d*)A, sA, ws, sW); break;
-    case 1: hipLaunchKernelGGL(k_tri_eig, dim3(batch), dim3(ET), 0, st, n, keep, zero_tol, ws, sW, evals, sE, kept_sum); break;
-    case 2: hipLaunchKernelGGL(k_cholqr, dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, gws, sG); break;
-    default: hipLaunchKernelGGL(k_backtransform, dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ); break;
+    case 0:
+      if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 16, 4>), dim3(batch), dim3(ET), 0, st, n, (c64d*)A, sA, ws, sW);
+      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 16, 4>), dim3(batch), dim3(ET), 0, st, n, (c64d*)A, sA, ws, sW);
+      else hipLaunchKernelGGL((k_tridiag<512, 4, 2>), dim3(batch), dim3(ET), 0, st, n, (c64d*)A, sA, ws, sW);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_tri_eig, dim3(batch), dim3(ET), 0, st, n, keep, zero_tol, ws, sW, evals, sE, kept_sum);
+      break;
+    case 2:
+      break;   // (reserved)
+    default:
+      if (n <= 256) hipLaunchKernelGGL((k_backtransform<256, 16>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
+      else hipLaunchKernelGGL((k_backtransform<512, 8>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
+      break;
   }
   return hipGetLastError();
 }

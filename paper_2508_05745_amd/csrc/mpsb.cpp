@@ -225,6 +225,7 @@ hipError_t heev_all(mpsb_batch* h, int n, int keep, double zt, void* A, long lon
                     double* gws, long long sG, double* ev, long long sE, double* kept, void* Z, long long sZ, int batch) {
   const int cls[4] = {PC_TRIDIAG, PC_TRIEIG, PC_CHOLQR, PC_BACK};
   for (int ph = 0; ph < 4; ++ph) {
+    if (ph == 2) continue;
     ProfSec s(h, cls[ph]);
     hipError_t e = heev_phase(ph, n, keep, zt, A, sA, ws, sW, gws, sG, ev, sE, kept, Z, sZ, batch, h->st);
     if (e != hipSuccess) return e;
