@@ -23,6 +23,7 @@ namespace mpsb {
 constexpr int ET = 256;           // threads per workgroup
 constexpr int EMAX = 512;         // largest matrix dimension
 
+template <int NT = ET>
 __device__ inline double block_sum(double v, double* red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -31,7 +32,7 @@ __device__ inline double block_sum(double v, double* red) {
   if (lane == 0) red[wv] = v;
   __syncthreads();
   double s = 0;
-  for (int w = 0; w < ET / 64; ++w) s += red[w];
+  for (int w = 0; w < NT / 64; ++w) s += red[w];
   return s;
 }
 
@@ -42,14 +43,14 @@ __device__ inline double block_sum(double v, double* red) {
 // trailing matrix (the matrix-vector product), and the panel's rank-2NB update is applied
 // once at the end of the panel.  The panel vectors live in LDS (column-major by vector, so
 // that lanes read consecutive rows).  u_j is kept in column j below the diagonal.
-template <int NMAX, int NB, int RB>
-__global__ __launch_bounds__(ET) void k_tridiag(int n, c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
+template <int NMAX, int NB, int RB, int NT>
+__global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
                                                 long long sW) {
   __shared__ c64d Vt[NB][NMAX], Wt[NB][NMAX];
   __shared__ c64d su[NMAX], sp[NMAX];
-  __shared__ c64d part[ET / 64][NMAX];
+  __shared__ c64d part[NT / 64][NMAX];
   __shared__ c64d cdot[2 * NB];
-  __shared__ double red[ET / 64];
+  __shared__ double red[NT / 64];
   c64d* A = Ag + blockIdx.x * sA;
   double* W = ws + blockIdx.x * sW;
   double* d = W;                          // [n]
@@ -59,8 +60,8 @@ __global__ __launch_bounds__(ET) void k_tridiag(int n, c64d* __restrict__ Ag, lo
   constexpr int SLOTS = NMAX / 64;
 
   double t = 0;
-  for (int i = tid; i < n; i += ET) t += A[(long long)i * n + i].re;
-  t = block_sum(t, red);
+  for (int i = tid; i < n; i += NT) t += A[(long long)i * n + i].re;
+  t = block_sum<NT>(t, red);
   if (tid == 0) tr[0] = t;
 
   for (int j0 = 0; j0 + 2 < n; j0 += NB) {
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(ET) void k_tridiag(int n, c64d* __restrict__ Ag, lo
       const int j = j0 + k;
       const int m = n - j - 1;
       // corrected column j (rows j..n-1) -> su (rows j+1..) and the diagonal
-      for (int r = j + tid; r < n; r += ET) {
+      for (int r = j + tid; r < n; r += NT) {
         c64d a = A[(long long)r * n + j];
         for (int kk = 0; kk < k; ++kk) {
           c64d corr = Vt[kk][r] * conj(Wt[kk][j]) + Wt[kk][r] * conj(Vt[kk][j]);
@@ -80,8 +81,8 @@ __global__ __launch_bounds__(ET) void k_tridiag(int n, c64d* __restrict__ Ag, lo
       }
       __syncthreads();
       double s2 = 0;
-      for (int i = tid; i < m; i += ET) s2 += norm2(su[i]);
-      s2 = block_sum(s2, red);
+      for (int i = tid; i < m; i += NT) s2 += norm2(su[i]);
+      s2 = block_sum<NT>(s2, red);
       const double alpha = sqrt(s2);
       const c64d x0 = su[0];
       const double ax0 = sqrt(norm2(x0));
@@ -89,24 +90,24 @@ __global__ __launch_bounds__(ET) void k_tridiag(int n, c64d* __restrict__ Ag, lo
       const c64d ph = ax0 > 0 ? c64d{x0.re / ax0, x0.im / ax0} : c64d{1.0, 0.0};
       const double vn = skip ? 1.0 : sqrt(2.0 * alpha * (alpha + ax0));
       __syncthreads();
-      for (int i = tid; i < m; i += ET) {
+      for (int i = tid; i < m; i += NT) {
         c64d xi = su[i];
         if (i == 0) xi = xi + alpha * ph;
         c64d u = skip ? c64d{0, 0} : c64d{xi.re / vn, xi.im / vn};
         su[i] = u;
         A[(long long)(j + 1 + i) * n + j] = u;
       }
-      for (int r = tid; r <= j; r += ET) Vt[k][r] = c64d{0, 0};
+      for (int r = tid; r <= j; r += NT) Vt[k][r] = c64d{0, 0};
       if (tid == 0) ec[j] = skip ? x0 : c64d{-ph.re * alpha, -ph.im * alpha};
       __syncthreads();
-      for (int i = tid; i < m; i += ET) Vt[k][j + 1 + i] = su[i];
+      for (int i = tid; i < m; i += NT) Vt[k][j + 1 + i] = su[i];
       // p = (lower-stored Hermitian A22) u: row parts by waves (RB rows at a time, loads
       // issued together), column parts accumulated in registers (lane owns columns
       // lane + 64 s)
       c64d colacc[SLOTS];
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) colacc[s] = c64d{0, 0};
-      for (int i0 = wv * RB; i0 < m; i0 += (ET / 64) * RB) {
+      for (int i0 = wv * RB; i0 < m; i0 += (NT / 64) * RB) {
         c64d av[RB][SLOTS];
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(ET) void k_tridiag(int n, c64d* __restrict__ Ag, lo
         if (kk < m) part[wv][kk] = colacc[s];
       }
       // dot products of the panel vectors with u (rows j+1..n-1)
-      for (int dd = wv; dd < 2 * k; dd += ET / 64) {
+      for (int dd = wv; dd < 2 * k; dd += NT / 64) {
         const int kk = dd >> 1;
         const bool isw = dd & 1;
         double cr = 0, ci = 0;
@@ -176,10 +177,10 @@ __global__ __launch_bounds__(ET) void k_tridiag(int n, c64d* __restrict__ Ag, lo
         if (lane == 0) cdot[dd] = c64d{cr, ci};   // even: V^dag u, odd: W^dag u
       }
       __syncthreads();
-      for (int i = tid; i < m; i += ET) {
+      for (int i = tid; i < m; i += NT) {
         c64d p = sp[i];
 #pragma unroll
-        for (int w = 0; w < ET / 64; ++w) p = p + part[w][i];
+        for (int w = 0; w < NT / 64; ++w) p = p + part[w][i];
         const int r = j + 1 + i;
         for (int kk = 0; kk < k; ++kk) {
           c64d corr = Vt[kk][r] * cdot[2 * kk + 1] + Wt[kk][r] * cdot[2 * kk];
@@ -189,17 +190,17 @@ __global__ __launch_bounds__(ET) void k_tridiag(int n, c64d* __restrict__ Ag, lo
       }
       __syncthreads();
       double kq = 0;
-      for (int i = tid; i < m; i += ET) kq += su[i].re * sp[i].re + su[i].im * sp[i].im;
-      kq = block_sum(kq, red);
-      for (int r = tid; r <= j; r += ET) Wt[k][r] = c64d{0, 0};
-      for (int i = tid; i < m; i += ET) Wt[k][j + 1 + i] = sp[i] - kq * su[i];
+      for (int i = tid; i < m; i += NT) kq += su[i].re * sp[i].re + su[i].im * sp[i].im;
+      kq = block_sum<NT>(kq, red);
+      for (int r = tid; r <= j; r += NT) Wt[k][r] = c64d{0, 0};
+      for (int i = tid; i < m; i += NT) Wt[k][j + 1 + i] = sp[i] - kq * su[i];
       __syncthreads();
     }
     // trailing update of the lower triangle, rows/cols >= t0:
     // A[r][c] -= 2 sum_k (V[r][k] conj(W[c][k]) + W[r][k] conj(V[c][k])), RB rows per wave and
     // SLOTS columns per lane register-blocked
     const int t0 = j0 + jb;
-    for (int r0 = t0 + wv * RB; r0 < n; r0 += (ET / 64) * RB) {
+    for (int r0 = t0 + wv * RB; r0 < n; r0 += (NT / 64) * RB) {
       c64d acc[RB][SLOTS];
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr)
@@ -584,9 +585,9 @@ hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long
   (void)sG;
   switch (phase) {
     case 0:
-      if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 16, 4>), dim3(batch), dim3(ET), 0, st, n, (c64d*)A, sA, ws, sW);
-      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 16, 4>), dim3(batch), dim3(ET), 0, st, n, (c64d*)A, sA, ws, sW);
-      else hipLaunchKernelGGL((k_tridiag<512, 4, 2>), dim3(batch), dim3(ET), 0, st, n, (c64d*)A, sA, ws, sW);
+      if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 8, 4, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
+      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 8, 4, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
+      else hipLaunchKernelGGL((k_tridiag<512, 4, 2, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
       break;
     case 1:
       hipLaunchKernelGGL(k_tri_eig, dim3(batch), dim3(ET), 0, st, n, keep, zero_tol, ws, sW, evals, sE, kept_sum);
