@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PROF_NAMES = ["theta", "events", "kraus_pair", "gram", "tridiag", "tri_eig", "cholqr", "backtransform",
+PROF_NAMES = ["theta", "events", "kraus_pair", "gram", "tridiag", "tri_eig", "hop_eig", "backtransform",
               "recompose", "hop", "idle", "expect"]
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
 
@@ -167,11 +167,16 @@ def main():
     fp64 = None
     if not args.no_fp64:
         dt64, prof64, obs64 = run_gpu(wl, warm, timed, M.FP64, profile=False)
-        d = np.abs(obs32 - obs64)
+        # the optimal decomposition is not unique, so paired FP32 / FP64 trajectories can
+        # take different (equally optimal) branches: compare the trajectory averages
+        nt = obs32.shape[0]
+        se = np.sqrt(obs32.var(0, ddof=1) / nt + obs64.var(0, ddof=1) / nt) + 1e-300
+        dmean = np.abs(obs32.mean(0) - obs64.mean(0))
         fp64 = dict(value=gate_steps / dt64, ms_per_step=1e3 * dt64 / K,
-                    obs_abs_diff_max=float(d.max()), obs_abs_diff_mean=float(d.mean()),
-                    mean_obs_abs_diff_max=float(np.abs(obs32.mean(0) - obs64.mean(0)).max()))
-        print(f"# fp64: {dt64:.3f} s, max |dO| fp32 vs fp64 {d.max():.2e}", file=sys.stderr, flush=True)
+                    mean_obs_abs_diff_max=float(dmean.max()), mean_obs_z_max=float((dmean / se).max()),
+                    observables=f"<Z_i>, <Z_i Z_i+1> after layer {W + K - 1}, {nt} trajectories each")
+        print(f"# fp64: {dt64:.3f} s, max |d mean<O>| {dmean.max():.2e} (z {float((dmean / se).max()):.2f})",
+              file=sys.stderr, flush=True)
     # roofline of the dominant kernel class
     work = algorithmic_work(c.n, wl.chi, timed, wl.n_traj)
     dom = max(prof, key=lambda k: prof[k][0])

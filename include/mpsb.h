@@ -152,8 +152,9 @@ int expect(mpsb_handle h, double* mean, double* m2, double* per_traj);
  * launches (host arrays of n entries); the return value is the number of classes.  Class
  * order: 0 theta contraction + gate + two-site RDM, 1 noise events (unravel + sample),
  * 2 Kraus-pair application, 3 truncation Gram matrix, 4 tridiagonalisation, 5 tridiagonal
- * eigenvalues + inverse iteration, 6 CholeskyQR2, 7 eigenvector back-transformation,
- * 8 recomposition, 9 centre-hop contractions, 10 idle-qubit events, 11 observables. */
+ * eigenvalues + inverse iteration, 6 centre-hop eigensolver (all phases), 7 eigenvector
+ * back-transformation, 8 recomposition, 9 centre-hop contractions, 10 idle-qubit events,
+ * 11 observables (phases 4, 5, 7 are those of the truncation eigensolver). */
 int mps_profile(mpsb_handle h, int enable);
 int mps_profile_read(mpsb_handle h, double* ms, long long* count, int n);
 

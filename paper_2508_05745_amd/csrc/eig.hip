@@ -421,17 +421,18 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
         const double sc = (mx > 0) ? 1.0 / mx : 1.0;
         for (int i = 0; i < n; ++i) X[(long long)i * keep + k] *= sc;
         // orthogonalise against the previous members of the cluster
+        if (k == k0) continue;
         for (int p = k0; p < k; ++p) {
           double dot = 0;
           for (int i = 0; i < n; ++i) dot += X[(long long)i * keep + p] * X[(long long)i * keep + k];
           for (int i = 0; i < n; ++i) X[(long long)i * keep + k] -= dot * X[(long long)i * keep + p];
         }
-        double nn = 0;
-        for (int i = 0; i < n; ++i) {
-          const double y = X[(long long)i * keep + k];
-          nn += y * y;
+        double nn2 = 0;
+        for (int r = 0; r < n; ++r) {
+          const double y = X[(long long)r * keep + k];
+          nn2 += y * y;
         }
-        const double inv = nn > 0 ? 1.0 / sqrt(nn) : 0.0;
+        const double inv = nn2 > 0 ? 1.0 / sqrt(nn2) : 0.0;
         for (int i = 0; i < n; ++i) X[(long long)i * keep + k] *= inv;
       }
     }
@@ -586,7 +587,7 @@ hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long
   switch (phase) {
     case 0:
       if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 8, 4, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
-      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 8, 4, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
+      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 4, 4, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
       else hipLaunchKernelGGL((k_tridiag<512, 4, 2, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
       break;
     case 1:

@@ -1,0 +1,130 @@
+// Centre hop by Cholesky factorisation of the Gram matrix (LDS-resident, FP64).
+//
+// Left-to-right hop of the orthogonality centre from site j to j+1: C_j (rows (a,s), n = chi_R
+// columns) = Q R with E = C^dag C = R^dag R (upper-triangular R); Q = C R^{-1} replaces C_j in
+// place (row by row, a wave per row) and R is written out for C_{j+1} = R B_{j+1}.
+// Right-to-left hop from j to j-1: C_j (n = chi_L rows, 2 chi_R columns) = R^dag Q with
+// E = C C^dag = R^dag R; Q = R^{-dag} C replaces C_j (column by column) and R is written out
+// for C_{j-1} = A_{j-1} R^dag.
+// Pivots below tol * max(diag E) are dropped (the row of R and the column of R^{-1} become
+// zero): such directions carry no weight of the state.
+#include "common.h"
+#include "kernels.h"
+
+namespace mpsb {
+
+constexpr int HT = 512;
+
+__device__ inline int pk(int i, int k, int n) { return i * n - (i * (i - 1)) / 2 + (k - i); }   // packed upper
+
+template <typename T, int NMAX>
+__global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int other, const c64d* __restrict__ Eg,
+                                                 long long sE, cplx<T>* __restrict__ C, long long sC,
+                                                 cplx<T>* __restrict__ Rout, long long sR, double tol) {
+  __shared__ c64d R[NMAX * (NMAX + 1) / 2];
+  __shared__ double piv[NMAX];
+  __shared__ double red[HT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const c64d* E = Eg + blockIdx.x * sE;
+  cplx<T>* Cj = C + blockIdx.x * sC;
+  cplx<T>* Ro = Rout + blockIdx.x * sR;
+  // load the upper triangle, find max diagonal
+  double dm = 0;
+  for (int i = wv; i < n; i += HT / 64)
+    for (int k = i + lane; k < n; k += 64) {
+      c64d v = E[(long long)i * n + k];
+      R[pk(i, k, n)] = v;
+      if (k == i) dm = fmax(dm, v.re);
+    }
+  for (int off = 32; off > 0; off >>= 1) dm = fmax(dm, __shfl_down(dm, off, 64));
+  if (lane == 0) red[wv] = dm;
+  __syncthreads();
+  double dmax = 0;
+  for (int w = 0; w < HT / 64; ++w) dmax = fmax(dmax, red[w]);
+  const double cut = tol * dmax;
+  // right-looking Cholesky E = R^dag R
+  for (int c = 0; c < n; ++c) {
+    __syncthreads();   // previous trailing update complete
+    const double p = R[pk(c, c, n)].re;
+    const bool keep = p > cut && p > 0.0;
+    const double r = keep ? sqrt(p) : 0.0;
+    __syncthreads();   // everyone has read the pivot before row c is rewritten
+    for (int k = c + tid; k < n; k += HT) {
+      c64d v = R[pk(c, k, n)];
+      R[pk(c, k, n)] = keep ? (k == c ? c64d{r, 0.0} : c64d{v.re / r, v.im / r}) : c64d{0, 0};
+    }
+    if (tid == 0) piv[c] = r;
+    __syncthreads();
+    if (keep) {
+      // E[i][k] -= conj(R[c][i]) R[c][k], c < i <= k: all pairs in parallel
+      const int m = n - c - 1;
+      for (int e = tid; e < m * m; e += HT) {
+        const int i = c + 1 + e / m, k = c + 1 + e % m;
+        if (i > k) continue;
+        R[pk(i, k, n)] = R[pk(i, k, n)] - cmulc(R[pk(c, i, n)], R[pk(c, k, n)]);
+      }
+    }
+  }
+  __syncthreads();
+  // R out (upper, zeros below), precision of the state
+  for (int i = wv; i < n; i += HT / 64)
+    for (int k = lane; k < n; k += 64) {
+      c64d v = k >= i ? R[pk(i, k, n)] : c64d{0, 0};
+      Ro[(long long)i * n + k] = cplx<T>{(T)v.re, (T)v.im};
+    }
+  // triangular solves, one wave per vector; lane owns entries lane + 64 s
+  constexpr int SL = NMAX / 64;
+  const int nvec = other;
+  for (int vidx = wv; vidx < nvec; vidx += HT / 64) {
+    c64d x[SL];
+    // load the vector: L->R: row vidx of C (length n, contiguous); R->L: column vidx of C,
+    // conjugated (C^dag row), stride `other`
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int k = lane + 64 * s;
+      cplx<T> v = {0, 0};
+      if (k < n) v = left_to_right ? Cj[(long long)vidx * n + k] : Cj[(long long)k * other + vidx];
+      x[s] = left_to_right ? c64d{(double)v.re, (double)v.im} : c64d{(double)v.re, -(double)v.im};
+    }
+    // solve q R = x: q_k = (x_k - sum_{i<k} q_i R[i][k]) / R[k][k], column-oriented updates
+    for (int k = 0; k < n; ++k) {
+      const int owner = k & 63, slot = k >> 6;
+      c64d xk = {0, 0};
+#pragma unroll
+      for (int s = 0; s < SL; ++s)
+        if (s == slot) xk = x[s];
+      xk.re = __shfl(xk.re, owner, 64);
+      xk.im = __shfl(xk.im, owner, 64);
+      const double rkk = piv[k];
+      const c64d qk = rkk > 0 ? c64d{xk.re / rkk, xk.im / rkk} : c64d{0, 0};
+#pragma unroll
+      for (int s = 0; s < SL; ++s) {
+        const int j = lane + 64 * s;
+        if (j == k) x[s] = qk;
+        else if (j > k && j < n && rkk > 0) x[s] = x[s] - qk * R[pk(k, j, n)];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int k = lane + 64 * s;
+      if (k < n) {
+        if (left_to_right) Cj[(long long)vidx * n + k] = cplx<T>{(T)x[s].re, (T)x[s].im};
+        else Cj[(long long)k * other + vidx] = cplx<T>{(T)x[s].re, (T)(-x[s].im)};
+      }
+    }
+  }
+}
+
+hipError_t hop_chol(int prec, int n, int left_to_right, int other, const void* E, long long sE, void* C, long long sC,
+                    void* Rout, long long sR, double tol, int n_traj, hipStream_t st) {
+  if (n > 128) return hipErrorInvalidValue;
+  if (prec == 0)
+    hipLaunchKernelGGL((k_hop_chol<float, 128>), dim3(n_traj), dim3(HT), 0, st, n, left_to_right, other,
+                       (const c64d*)E, sE, (c32*)C, sC, (c32*)Rout, sR, tol);
+  else
+    hipLaunchKernelGGL((k_hop_chol<double, 128>), dim3(n_traj), dim3(HT), 0, st, n, left_to_right, other,
+                       (const c64d*)E, sE, (c64d*)C, sC, (c64d*)Rout, sR, tol);
+  return hipGetLastError();
+}
+
+}  // namespace mpsb

@@ -65,6 +65,10 @@ hipError_t trunc_factors(const double* kept, const double* ws, long long sW, int
 hipError_t hop_scales(const double* evals, long long sE, int n, double* inv_sqrt, double* sqrt_, int n_traj,
                       hipStream_t st);
 
+// centre hop by Gram-Cholesky (n <= 128): Q replaces C in place, R written to Rout
+hipError_t hop_chol(int prec, int n, int left_to_right, int other, const void* E, long long sE, void* C, long long sC,
+                    void* Rout, long long sR, double tol, int n_traj, hipStream_t st);
+
 // observables
 hipError_t env_init(double* env, long long s_env, int n_traj, hipStream_t st);
 hipError_t widen(const void* in, long long s_in, void* out, long long s_out, long long len, int n_traj, hipStream_t st);

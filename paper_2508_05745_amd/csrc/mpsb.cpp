@@ -139,7 +139,7 @@ int make_layout(int n_traj, int n, int chi, int prec, Layout& L) {
 
 // kernel classes timed by the optional profiler
 enum ProfClass {
-  PC_THETA = 0, PC_EVENTS, PC_KRAUS, PC_GRAM, PC_TRIDIAG, PC_TRIEIG, PC_CHOLQR, PC_BACK, PC_RECOMPOSE, PC_HOPGEMM,
+  PC_THETA = 0, PC_EVENTS, PC_KRAUS, PC_GRAM, PC_TRIDIAG, PC_TRIEIG, PC_HOPEIG, PC_BACK, PC_RECOMPOSE, PC_HOPGEMM,
   PC_SMALL, PC_EXPECT, PC_COUNT
 };
 
@@ -222,11 +222,12 @@ void prof_collect(mpsb_batch* h) {
 }
 
 hipError_t heev_all(mpsb_batch* h, int n, int keep, double zt, void* A, long long sA, double* ws, long long sW,
-                    double* gws, long long sG, double* ev, long long sE, double* kept, void* Z, long long sZ, int batch) {
-  const int cls[4] = {PC_TRIDIAG, PC_TRIEIG, PC_CHOLQR, PC_BACK};
+                    double* gws, long long sG, double* ev, long long sE, double* kept, void* Z, long long sZ, int batch,
+                    bool hop = false) {
+  const int cls[4] = {PC_TRIDIAG, PC_TRIEIG, PC_HOPEIG, PC_BACK};
   for (int ph = 0; ph < 4; ++ph) {
     if (ph == 2) continue;
-    ProfSec s(h, cls[ph]);
+    ProfSec s(h, hop ? PC_HOPEIG : cls[ph]);
     hipError_t e = heev_phase(ph, n, keep, zt, A, sA, ws, sW, gws, sG, ev, sE, kept, Z, sZ, batch, h->st);
     if (e != hipSuccess) return e;
   }
@@ -268,8 +269,12 @@ int hop_right(mpsb_batch* h, int j) {
     ProfSec s(h, PC_HOPGEMM);
     HIPCHK(gemm(p, 1, true, false, cr, cr, 2 * cl, Cj, cr, L.s_traj, Cj, cr, L.s_traj, gram, cr, L.s_gram, nullptr, T, h->st));
   }
+  if (cr <= 128) {
+    ProfSec sh(h, PC_HOPEIG);
+    HIPCHK(hop_chol(p, cr, 1, 2 * cl, gram, L.s_gram, Cj, L.s_traj, W<char>(h, L.o_rm), L.s_wm, zero_tol(L), T, h->st));
+  } else {
   HIPCHK(heev_all(h, cr, cr, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
-              W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), W<double>(h, L.o_z), L.s_z, T));
+              W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), W<double>(h, L.o_z), L.s_z, T, true));
   ProfSec shop(h, PC_HOPGEMM);
   double* invs = W<double>(h, L.o_invs);
   double* sq = W<double>(h, L.o_sqrt);
@@ -277,10 +282,13 @@ int hop_right(mpsb_batch* h, int j) {
   // Wm = W Lambda^{-1/2}, Rm = Lambda^{1/2} W^dag
   HIPCHK(scale_cast(p, cr, cr, W<double>(h, L.o_z), cr, L.s_z, invs, cr, false, W<char>(h, L.o_wm), cr, L.s_wm, T, h->st));
   HIPCHK(scale_cast(p, cr, cr, W<double>(h, L.o_z), cr, L.s_z, sq, cr, true, W<char>(h, L.o_rm), cr, L.s_wm, T, h->st));
-  // A_j = C Wm  -> tmp -> site j
+  }
   char* tmp = W<char>(h, L.o_tmp);
-  HIPCHK(gemm(p, p, false, false, 2 * cl, cr, cr, Cj, cr, L.s_traj, W<char>(h, L.o_wm), cr, L.s_wm, tmp, cr, L.s_tmp, nullptr, T, h->st));
-  HIPCHK(copy_blocks(Cj, L.s_traj * L.esz, tmp, L.s_tmp * L.esz, (size_t)2 * cl * cr * L.esz, T, h->st));
+  if (cr > 128) {
+    // A_j = C Wm  -> tmp -> site j
+    HIPCHK(gemm(p, p, false, false, 2 * cl, cr, cr, Cj, cr, L.s_traj, W<char>(h, L.o_wm), cr, L.s_wm, tmp, cr, L.s_tmp, nullptr, T, h->st));
+    HIPCHK(copy_blocks(Cj, L.s_traj * L.esz, tmp, L.s_tmp * L.esz, (size_t)2 * cl * cr * L.esz, T, h->st));
+  }
   // C_{j+1} = Rm B_{j+1}
   HIPCHK(gemm(p, p, false, false, cr, 2 * cr2, cr, W<char>(h, L.o_rm), cr, L.s_wm, Bn, 2 * cr2, L.s_traj, tmp, 2 * cr2, L.s_tmp, nullptr, T, h->st));
   HIPCHK(copy_blocks(Bn, L.s_traj * L.esz, tmp, L.s_tmp * L.esz, (size_t)cr * 2 * cr2 * L.esz, T, h->st));
@@ -300,8 +308,19 @@ int hop_left(mpsb_batch* h, int j) {
     ProfSec s(h, PC_HOPGEMM);
     HIPCHK(gemm(p, 1, false, true, cl, cl, 2 * cr, Cj, 2 * cr, L.s_traj, Cj, 2 * cr, L.s_traj, gram, cl, L.s_gram, nullptr, T, h->st));
   }
+  char* tmp = W<char>(h, L.o_tmp);
+  if (cl <= 128) {
+    ProfSec sh(h, PC_HOPEIG);
+    HIPCHK(hop_chol(p, cl, 0, 2 * cr, gram, L.s_gram, Cj, L.s_traj, W<char>(h, L.o_rm), L.s_wm, zero_tol(L), T, h->st));
+    ProfSec shg(h, PC_HOPGEMM);
+    // C_{j-1} = A_{j-1} R^dag
+    HIPCHK(gemm(p, p, false, true, 2 * cl2, cl, cl, Ap, cl, L.s_traj, W<char>(h, L.o_rm), cl, L.s_wm, tmp, cl, L.s_tmp, nullptr, T, h->st));
+    HIPCHK(copy_blocks(Ap, L.s_traj * L.esz, tmp, L.s_tmp * L.esz, (size_t)2 * cl2 * cl * L.esz, T, h->st));
+    h->centre = j - 1;
+    return MPSB_OK;
+  }
   HIPCHK(heev_all(h, cl, cl, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
-              W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), W<double>(h, L.o_z), L.s_z, T));
+              W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), W<double>(h, L.o_z), L.s_z, T, true));
   ProfSec shop(h, PC_HOPGEMM);
   double* invs = W<double>(h, L.o_invs);
   double* sq = W<double>(h, L.o_sqrt);
@@ -309,7 +328,6 @@ int hop_left(mpsb_batch* h, int j) {
   // Wm = Lambda^{-1/2} W^dag, Rm = W Lambda^{1/2}
   HIPCHK(scale_cast(p, cl, cl, W<double>(h, L.o_z), cl, L.s_z, invs, cl, true, W<char>(h, L.o_wm), cl, L.s_wm, T, h->st));
   HIPCHK(scale_cast(p, cl, cl, W<double>(h, L.o_z), cl, L.s_z, sq, cl, false, W<char>(h, L.o_rm), cl, L.s_wm, T, h->st));
-  char* tmp = W<char>(h, L.o_tmp);
   // B_j = Wm C
   HIPCHK(gemm(p, p, false, false, cl, 2 * cr, cl, W<char>(h, L.o_wm), cl, L.s_wm, Cj, 2 * cr, L.s_traj, tmp, 2 * cr, L.s_tmp, nullptr, T, h->st));
   HIPCHK(copy_blocks(Cj, L.s_traj * L.esz, tmp, L.s_tmp * L.esz, (size_t)cl * 2 * cr * L.esz, T, h->st));

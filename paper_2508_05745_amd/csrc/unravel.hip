@@ -475,7 +475,7 @@ __device__ void write_record(const EventArgs& ea, int traj, int qubit, int j, co
 
 // Gate events: reduce the theta tiles' RDM partials (fixed order), then the events of the
 // lower and upper qubit; writes kops[traj] = {Ks, Kt} (normalised by 1/sqrt(p)).
-__global__ void k_gate_events(EventArgs ea, const double* __restrict__ partial, int n_tiles, int q, int has_s, int has_t,
+__global__ __launch_bounds__(64) void k_gate_events(EventArgs ea, const double* __restrict__ partial, int n_tiles, int q, int has_s, int has_t,
                               double* __restrict__ kops, int* __restrict__ status) {
   const int ch_s = has_s ? 0 : -1, ch_t = has_t ? 1 : -1;
   int traj = blockIdx.x * blockDim.x + threadIdx.x;
@@ -539,7 +539,7 @@ __global__ void k_gate_events(EventArgs ea, const double* __restrict__ partial, 
 
 // Single-site event on the centre tensor: rho1 [traj][2][2] c128 (unnormalised) -> kops
 // (first 2x2 block = selected operator, second = identity).
-__global__ void k_site_event(EventArgs ea, const double* __restrict__ rho1, int q, int ch /* slot */, const int* __restrict__ forced,
+__global__ __launch_bounds__(64) void k_site_event(EventArgs ea, const double* __restrict__ rho1, int q, int ch /* slot */, const int* __restrict__ forced,
                              double* __restrict__ kops, double* __restrict__ p_out, int* __restrict__ status) {
   int traj = blockIdx.x * blockDim.x + threadIdx.x;
   if (traj >= ea.n_traj) return;
@@ -574,7 +574,7 @@ __global__ void k_site_event(EventArgs ea, const double* __restrict__ rho1, int 
 
 // Forced-branch feasibility check (run before any state change): flags status bit 2 when
 // a forced branch has zero probability.
-__global__ void k_site_event_check(EventArgs ea, const double* __restrict__ rho1, int ch, const int* __restrict__ forced,
+__global__ __launch_bounds__(64) void k_site_event_check(EventArgs ea, const double* __restrict__ rho1, int ch, const int* __restrict__ forced,
                                    int* __restrict__ status) {
   int traj = blockIdx.x * blockDim.x + threadIdx.x;
   if (traj >= ea.n_traj || !forced || forced[traj] < 0) return;
@@ -594,7 +594,7 @@ __global__ void k_site_event_check(EventArgs ea, const double* __restrict__ rho1
 }
 
 // ------------------------------------------------------------------ unravel_opt
-__global__ void k_unravel_opt(int batch, const double* __restrict__ rho_q, const double* __restrict__ kraus,
+__global__ __launch_bounds__(64) void k_unravel_opt(int batch, const double* __restrict__ rho_q, const double* __restrict__ kraus,
                               const int* __restrict__ kraus_id, int r, double* __restrict__ U, double* __restrict__ p_out,
                               double* __restrict__ eof) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
