@@ -420,13 +420,13 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
         }
         const double sc = (mx > 0) ? 1.0 / mx : 1.0;
         for (int i = 0; i < n; ++i) X[(long long)i * keep + k] *= sc;
-        // orthogonalise against the previous members of the cluster
-        if (k == k0) continue;
+        // orthogonalise against the previous (finished, unit) members of the cluster
         for (int p = k0; p < k; ++p) {
           double dot = 0;
           for (int i = 0; i < n; ++i) dot += X[(long long)i * keep + p] * X[(long long)i * keep + k];
           for (int i = 0; i < n; ++i) X[(long long)i * keep + k] -= dot * X[(long long)i * keep + p];
         }
+        if (itr == 0) continue;   // the unit 2-norm is only needed for the final vector
         double nn2 = 0;
         for (int r = 0; r < n; ++r) {
           const double y = X[(long long)r * keep + k];

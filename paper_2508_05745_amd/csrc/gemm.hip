@@ -135,32 +135,58 @@ hipError_t gemm(int prec_in, int prec_out, bool ca, bool cb, int M, int N, int K
 // t' chi_r + b), and the two-site reduced density matrix
 //   rho[x][y] = sum_{a,b} thetaG[x][a,b] conj(thetaG[y][a,b]),  x = 2s'+t'
 // is accumulated per tile (FP64) into partial[traj][tile][16] c128.
-// Tile: 32 values of a (64 rows) x 32 values of b for both t (64 columns); 256 threads,
-// each 2 a x 2 b x 4 (s,t) accumulators.
+// Tile: 32 values of a (64 rows) x 32 values of b for both t (64 columns), 4 waves of 64.
+// Each wave owns 16 values of a x 16 values of b and all four (s,t) blocks, so the gate mix
+// and the RDM stay in registers.  Complex products are four real 16x16x4 MFMAs (re*re,
+// -im*im, re*im, im*re) per (s,t) block and k-step of 4.
+// Lane layout of the 16x16x4 MFMAs: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k; the
+// result D[i][j] sits in lane j + 16 (i / 4), register i % 4 for the f32 instruction and in
+// lane j + 16 (i % 4), register i / 4 for the f64 one (checked on the device).
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaAcc;
+template <> struct MfmaAcc<float> {
+  using V = v4f;
+  static __device__ inline V mac(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane_hi, int reg) { return 4 * lane_hi + reg; }
+};
+template <> struct MfmaAcc<double> {
+  using V = v4d;
+  static __device__ inline V mac(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane_hi, int reg) { return lane_hi + 4 * reg; }
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, const cplx<T>* __restrict__ Cs,
-                                               const cplx<T>* __restrict__ Bs, long long s_traj,
-                                               cplx<T>* __restrict__ out, long long s_out, Mat4 gate,
-                                               double* __restrict__ partial, int n_tiles) {
+                                                    const cplx<T>* __restrict__ Bs, long long s_traj,
+                                                    cplx<T>* __restrict__ out, long long s_out, Mat4 gate,
+                                                    double* __restrict__ partial, int n_tiles) {
+  using M = MfmaAcc<T>;
+  using V = typename M::V;
   __shared__ T A_re[GB_K][64 + 4], A_im[GB_K][64 + 4];   // [k][row = 2*(a-a0)+s]
   __shared__ T B_re[GB_K][64 + 4], B_im[GB_K][64 + 4];   // [k][col = t*32 + (b-b0)]
-  __shared__ double red[256 / 64][32];
+  __shared__ double red[4][32];
   const int traj = blockIdx.z;
   const cplx<T>* Cp = Cs + traj * s_traj;
   const cplx<T>* Bp = Bs + traj * s_traj;
   cplx<T>* O = out + traj * s_out;
   const int a0 = blockIdx.y * 32, b0 = blockIdx.x * 32;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int ldc = 2 * chi_m;   // C as (a,s) x c row-major: row stride chi_m, (a,s) -> 2a+s
-  const int ldb = 2 * chi_r;   // B as c x (t,b)
-  T acc_re[2][2][2][2], acc_im[2][2][2][2];   // [ai][s][bj][t]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wa = wv >> 1, wb = wv & 1;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int ldb = 2 * chi_r;
+  V acc_re[4], acc_im[4];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) { (&acc_re[0][0][0][0])[i] = 0; (&acc_im[0][0][0][0])[i] = 0; }
+  for (int x = 0; x < 4; ++x) {
+    acc_re[x] = V{0, 0, 0, 0};
+    acc_im[x] = V{0, 0, 0, 0};
+  }
   for (int k0 = 0; k0 < chi_m; k0 += GB_K) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int e = tid + 256 * r;
-      int kk = e & 15, row = e >> 4;               // row = 2*(a-a0)+s
+      int kk = e & 15, row = e >> 4;
       int a = a0 + (row >> 1), s = row & 1, k = k0 + kk;
       cplx<T> v = {0, 0};
       if (a < chi_l && k < chi_m) v = Cp[(long long)(2 * a + s) * chi_m + k];
@@ -170,7 +196,7 @@ __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int e = tid + 256 * r;
-      int col = e & 63, kk = e >> 6;               // col = t*32 + (b-b0)
+      int col = e & 63, kk = e >> 6;
       int t = col >> 5, b = b0 + (col & 31), k = k0 + kk;
       cplx<T> v = {0, 0};
       if (b < chi_r && k < chi_m) v = Bp[(long long)k * ldb + t * chi_r + b];
@@ -178,77 +204,70 @@ __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, 
       B_im[kk][col] = v.im;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < GB_K; ++kk) {
-      T ar[2][2], ai[2][2], br[2][2], bi[2][2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+    for (int k4 = 0; k4 < GB_K / 4; ++k4) {
+      const int kk = 4 * k4 + kq;
+      T ar[2], ai[2], br[2], bi[2];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          int row = 2 * (ty + 16 * i) + s;
-          ar[i][s] = A_re[kk][row];
-          ai[i][s] = A_im[kk][row];
-        }
+      for (int s = 0; s < 2; ++s) {
+        const int row = 2 * (16 * wa + r16) + s;
+        ar[s] = A_re[kk][row];
+        ai[s] = A_im[kk][row];
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int t = 0; t < 2; ++t) {
+        const int col = 32 * t + 16 * wb + r16;
+        br[t] = B_re[kk][col];
+        bi[t] = B_im[kk][col];
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          int col = t * 32 + tx + 16 * j;
-          br[j][t] = B_re[kk][col];
-          bi[j][t] = B_im[kk][col];
+          const int x = 2 * s + t;
+          acc_re[x] = M::mac(ar[s], br[t], acc_re[x]);
+          acc_re[x] = M::mac(-ai[s], bi[t], acc_re[x]);
+          acc_im[x] = M::mac(ar[s], bi[t], acc_im[x]);
+          acc_im[x] = M::mac(ai[s], br[t], acc_im[x]);
         }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-              acc_re[i][s][j][t] += ar[i][s] * br[j][t] - ai[i][s] * bi[j][t];
-              acc_im[i][s][j][t] += ar[i][s] * bi[j][t] + ai[i][s] * br[j][t];
-            }
     }
     __syncthreads();
   }
-  // ---- epilogue: gate mix, store, RDM partial sums in FP64
+  // epilogue: lane holds rows a = a0 + 16 wa + row(kq, i), column b = b0 + 16 wb + r16
   double rr[16], ri[16];
 #pragma unroll
   for (int x = 0; x < 16; ++x) rr[x] = ri[x] = 0.0;
+  const int b = b0 + 16 * wb + r16;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i) {
+    const int a = a0 + 16 * wa + M::row(kq, i);
+    if (a >= chi_l || b >= chi_r) continue;
+    double vr[4], vi[4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      int a = a0 + ty + 16 * i, b = b0 + tx + 16 * j;
-      if (a >= chi_l || b >= chi_r) continue;
-      double vr[4], vi[4];
+    for (int x = 0; x < 4; ++x) {
+      double sr = 0, si = 0;
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        double sr = 0, si = 0;
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          double gr = gate.v[2 * (4 * x + y)], gi = gate.v[2 * (4 * x + y) + 1];
-          double tr = (double)acc_re[i][y >> 1][j][y & 1], tim = (double)acc_im[i][y >> 1][j][y & 1];
-          sr += gr * tr - gi * tim;
-          si += gr * tim + gi * tr;
-        }
-        cplx<T> o;
-        o.re = (T)sr;
-        o.im = (T)si;
-        O[(long long)(2 * a + (x >> 1)) * ldb + (x & 1) * chi_r + b] = o;
-        vr[x] = (double)o.re;   // RDM of the stored (rounded) values
-        vi[x] = (double)o.im;
+      for (int y = 0; y < 4; ++y) {
+        const double gr = gate.v[2 * (4 * x + y)], gi = gate.v[2 * (4 * x + y) + 1];
+        const double tr = (double)acc_re[y][i], tim = (double)acc_im[y][i];
+        sr += gr * tr - gi * tim;
+        si += gr * tim + gi * tr;
       }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          rr[4 * x + y] += vr[x] * vr[y] + vi[x] * vi[y];
-          ri[4 * x + y] += vi[x] * vr[y] - vr[x] * vi[y];
-        }
+      cplx<T> o;
+      o.re = (T)sr;
+      o.im = (T)si;
+      O[(long long)(2 * a + (x >> 1)) * ldb + (x & 1) * chi_r + b] = o;
+      vr[x] = (double)o.re;
+      vi[x] = (double)o.im;
     }
-  // block reduction of the 32 doubles, fixed order (wave shuffles then LDS)
-  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        rr[4 * x + y] += vr[x] * vr[y] + vi[x] * vi[y];
+        ri[4 * x + y] += vi[x] * vr[y] - vr[x] * vi[y];
+      }
+  }
 #pragma unroll
   for (int x = 0; x < 32; ++x) {
     double v = (x < 16) ? rr[x] : ri[x - 16];
