@@ -30,39 +30,71 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PROF_NAMES = ["theta", "events", "kraus_pair", "gram", "tridiag", "tri_eig", "hop_eig", "backtransform",
-              "recompose", "hop", "idle", "expect"]
+              "recompose", "hop", "idle", "expect", "tridiag_s", "tridiag_l", "backtransform_l"]
+# kernel instance timed by each single-instance class
+KERNEL = {"theta": "k_theta<float>", "tridiag": "k_tridiag<256, 4, 4, 512>", "tridiag_s": "k_tridiag<128, 8, 4, 512>",
+          "tridiag_l": "k_tridiag<512, 4, 2, 512>", "backtransform": "k_backtransform<256, 16>",
+          "backtransform_l": "k_backtransform<512, 8>", "tri_eig": "k_tri_eig"}
+TRIDIAG = {"tridiag_s": (0, 128), "tridiag": (129, 256), "tridiag_l": (257, 512)}
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
+EIG_SRC = os.path.join(ROOT, "paper_2508_05745_amd", "csrc", "eig.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.txt")
 
 
 def caps(n, chi):
     return [min(chi, 2 ** (k + 1), 2 ** (n - k - 1)) for k in range(n - 1)]
 
 
+def tridiag_bytes(m):
+    """HBM bytes the one-stage Householder reduction of an m x m c128 Hermitian matrix must
+    read: the lower triangle of the trailing matrix once per column (the matrix-vector
+    product), sum over the m - 2 reflectors of r (r + 1) / 2 elements of 16 bytes, r = m - j - 1."""
+    return 16.0 * sum(r * (r + 1) // 2 for r in range(2, m))
+
+
 def algorithmic_work(n, chi, layers, n_traj):
-    """Algorithmic flops of the timed launches, per kernel class (see the design notes):
-    theta 32*cl*cm*cr, Gram 64*c^2*c' (full Hermitian product), tridiagonalisation
-    16/3 m^3 per matrix (m = Gram dimension; the hop matrices included), back-transformation
-    8 m^2 k, recomposition 32 D cl cr, hop contractions 8 c^2 2c (Gram) + 2 x 16 c^2 cl."""
+    """Algorithmic work of the timed launches, per kernel class: flops for the contractions
+    (theta 32*cl*cm*cr, Gram 64*cl^2*cr (full Hermitian product), recomposition 32 D cl cr),
+    back-transformation 8 m^2 D, and for the tridiagonalisations both the flops (16/3 m^3)
+    and the HBM bytes of `tridiag_bytes` (m = Gram dimension)."""
     cp = caps(n, chi)
     dl = lambda k: 1 if k == 0 else cp[k - 1]
     dr = lambda k: 1 if k == n - 1 else cp[k]
     w = {k: 0.0 for k in PROF_NAMES}
-    centre = None
+    by = {k: 0.0 for k in PROF_NAMES}
     for l in layers:
         par = l % 2
         pairs = list(range(par, n - 1, 2))
-        if par == 1:
-            pairs = pairs[::-1]
         for q in pairs:
             cl, cm, cr = dl(q), dr(q), dr(q + 1)
             D = cm
             w["theta"] += 32.0 * cl * cm * cr
             m = 2 * cl if par == 0 else 2 * cr
-            w["gram"] += 8.0 * m * m * (4 * cl * cr) / m
-            w["tridiag"] += 16.0 / 3.0 * m ** 3
-            w["backtransform"] += 8.0 * m * m * D
+            w["gram"] += 32.0 * m * cl * cr
+            cls = next(k for k, (lo, hi) in TRIDIAG.items() if lo <= m <= hi)
+            w[cls] += 16.0 / 3.0 * m ** 3
+            by[cls] += tridiag_bytes(m)
+            w["backtransform" if m <= 256 else "backtransform_l"] += 8.0 * m * m * D
             w["recompose"] += 32.0 * D * cl * cr
-    return {k: v * n_traj for k, v in w.items()}
+    return {k: v * n_traj for k, v in w.items()}, {k: v * n_traj for k, v in by.items()}
+
+
+def measured_traffic(kernel, n_traj, chi):
+    """HBM bytes per launch of `kernel` from the committed PMC summary (FETCH_SIZE and
+    WRITE_SIZE per dispatch, scaled by the same counters on a plain copy kernel), or None when
+    the summary is for another workload or the eigensolver source changed since."""
+    import hashlib
+    if not os.path.exists(TRAFFIC):
+        return None
+    sha = hashlib.sha256(open(EIG_SRC, "rb").read()).hexdigest()
+    for line in open(TRAFFIC):
+        if line.startswith("#") or "=" not in line:
+            continue
+        f = dict(kv.split("=", 1) for kv in line.strip().split(";"))
+        if (f.get("kernel") == kernel and f.get("eig_hip_sha256") == sha and int(f["n_traj"]) == n_traj
+                and int(f["chi"]) == chi):
+            return (float(f["fetch_kib"]) * float(f["fetch_scale"]) + float(f["write_kib"]) * float(f["write_scale"])) * 1024.0
+    return None
 
 
 def run_gpu(workload, layers_warm, layers_timed, precision, profile=True):
@@ -88,10 +120,10 @@ def run_gpu(workload, layers_warm, layers_timed, precision, profile=True):
     b.sync()
     prof = None
     if profile:
-        ms = (ctypes.c_double * 16)()
-        cnt = (ctypes.c_longlong * 16)()
+        ms = (ctypes.c_double * 32)()
+        cnt = (ctypes.c_longlong * 32)()
         lib.mps_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
-        nc = lib.mps_profile_read(b.h, ms, cnt, 16)
+        nc = lib.mps_profile_read(b.h, ms, cnt, 32)
         prof = {PROF_NAMES[i]: (ms[i], cnt[i]) for i in range(min(nc, len(PROF_NAMES)))}
         lib.mps_profile(b.h, 0)
     _, _, pt = b.expect()
@@ -136,6 +168,20 @@ def cpu_baseline(workload, budget_s=25.0):
                        f"NumPy/LAPACK complex128")
 
 
+def calibrate_copy(nbytes=1 << 30, reps=4):
+    """A plain copy kernel of known size: under `rocprofv3 --pmc FETCH_SIZE` (or WRITE_SIZE)
+    each dispatch should read (write) nbytes; the ratio counter / nbytes scales the counters
+    taken on the path's kernels."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)   # one elementwise kernel: reads and writes nbytes
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": nbytes, "dispatches": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,7 +191,12 @@ def main():
     ap.add_argument("--traj", type=int, default=2048)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB elementwise copy kernel 4 times (HBM counter scale)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding (disjoint "
                                    "trajectory ranges) is designed but not implemented",
@@ -177,19 +228,30 @@ def main():
                     observables=f"<Z_i>, <Z_i Z_i+1> after layer {W + K - 1}, {nt} trajectories each")
         print(f"# fp64: {dt64:.3f} s, max |d mean<O>| {dmean.max():.2e} (z {float((dmean / se).max()):.2f})",
               file=sys.stderr, flush=True)
-    # roofline of the dominant kernel class
-    work = algorithmic_work(c.n, wl.chi, timed, wl.n_traj)
+    # roofline of the dominant kernel class (each timed class is one kernel instance)
+    work, nbytes = algorithmic_work(c.n, wl.chi, timed, wl.n_traj)
     dom = max(prof, key=lambda k: prof[k][0])
     ms, cnt = prof[dom]
-    fl = work.get(dom, 0.0)
-    if dom in ("theta", "gram", "recompose"):
-        peak, unit, bound = PEAK["fp32"], "TFLOP/s", "mfma"
+    sec = ms * 1e-3
+    if dom in TRIDIAG:
+        # one pass over the trailing lower triangle per column: about 2 flop per byte, far
+        # below the FP64 ridge point (78.6 TFLOP/s / 8 TB/s), so HBM bounds it
+        achieved = nbytes[dom] / sec if sec > 0 else 0.0
+        roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK["hbm"] / 1e9, unit="GB/s",
+                    frac=achieved / PEAK["hbm"],
+                    traffic=measured_traffic(KERNEL[dom], wl.n_traj, wl.chi),
+                    algorithmic_bytes_per_launch=nbytes[dom] / max(cnt, 1),
+                    fp64_tflops=work[dom] / sec / 1e12 if sec > 0 else 0.0)
+    elif dom in ("theta", "gram", "recompose"):
+        achieved = work[dom] / sec if sec > 0 else 0.0
+        roof = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAK["fp32"] / 1e12, unit="TFLOP/s",
+                    frac=achieved / PEAK["fp32"], traffic=None)
     else:
-        peak, unit, bound = PEAK["fp64"], "TFLOP/s", "alu"
-    achieved = fl / (ms * 1e-3) if ms > 0 else 0.0
-    roof = dict(kernel=dom, bound=bound, achieved=achieved / 1e12, peak=peak / 1e12, unit=unit,
-                frac=achieved / peak, traffic=None, launches=int(cnt), avg_launch_ms=ms / max(cnt, 1))
-    kern = {k: dict(ms=v[0], launches=int(v[1])) for k, v in prof.items()}
+        achieved = work.get(dom, 0.0) / sec if sec > 0 else 0.0
+        roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK["fp64"] / 1e12, unit="TFLOP/s",
+                    frac=achieved / PEAK["fp64"], traffic=None)
+    roof.update(kernel=KERNEL.get(dom, dom), launches=int(cnt), avg_launch_ms=ms / max(cnt, 1))
+    kern = {k: dict(ms=v[0], launches=int(v[1])) for k, v in prof.items() if v[1] > 0}
     th = prof.get("theta", (0, 1))
     theta_rate = work["theta"] / (th[0] * 1e-3) if th[0] > 0 else 0.0
     cpu = None if args.no_cpu else cpu_baseline(wl)
@@ -201,8 +263,9 @@ def main():
         "data": "synthetic (seeded Haar brickwork, depolarizing p=0.02)",
         "config": {"workload": wl.name, "n_qubits": c.n, "depth": c.depth, "chi": wl.chi,
                    "n_traj": wl.n_traj, "unravel": "optimal", "parallelism": "trajectories (1 GPU)"},
-        "roofline": roof, "theta_roofline": dict(achieved=theta_rate / 1e12, peak=PEAK["fp32"] / 1e12,
-                                                 unit="TFLOP/s", frac=theta_rate / PEAK["fp32"]),
+        "roofline": roof, "theta_roofline": dict(kernel=KERNEL["theta"], bound="mfma", achieved=theta_rate / 1e12,
+                                                 peak=PEAK["fp32"] / 1e12, unit="TFLOP/s",
+                                                 frac=theta_rate / PEAK["fp32"]),
         "kernels_ms": kern, "fp64": fp64, "cpu_baseline": cpu,
     }
     print(json.dumps(line))

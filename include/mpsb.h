@@ -151,10 +151,13 @@ int expect(mpsb_handle h, double* mean, double* m2, double* per_traj);
  * synchronises and returns, per class, the summed milliseconds and the number of timed
  * launches (host arrays of n entries); the return value is the number of classes.  Class
  * order: 0 theta contraction + gate + two-site RDM, 1 noise events (unravel + sample),
- * 2 Kraus-pair application, 3 truncation Gram matrix, 4 tridiagonalisation, 5 tridiagonal
- * eigenvalues + inverse iteration, 6 centre-hop eigensolver (all phases), 7 eigenvector
- * back-transformation, 8 recomposition, 9 centre-hop contractions, 10 idle-qubit events,
- * 11 observables (phases 4, 5, 7 are those of the truncation eigensolver). */
+ * 2 Kraus-pair application, 3 truncation Gram matrix, 4 tridiagonalisation of matrices with
+ * 128 < n <= 256, 5 tridiagonal eigenvalues + inverse iteration, 6 centre-hop factorisation
+ * (all phases), 7 eigenvector back-transformation (n <= 256), 8 recomposition, 9 centre-hop
+ * contractions, 10 idle-qubit events, 11 observables, 12 tridiagonalisation (n <= 128),
+ * 13 tridiagonalisation (256 < n <= 512), 14 back-transformation (256 < n <= 512).  Classes
+ * 4, 12, 13, 7 and 14 each time a single kernel instance (phases 4/12/13, 5, 7/14 are those of
+ * the truncation eigensolver). */
 int mps_profile(mpsb_handle h, int enable);
 int mps_profile_read(mpsb_handle h, double* ms, long long* count, int n);
 

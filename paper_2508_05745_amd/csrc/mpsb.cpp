@@ -140,7 +140,7 @@ int make_layout(int n_traj, int n, int chi, int prec, Layout& L) {
 // kernel classes timed by the optional profiler
 enum ProfClass {
   PC_THETA = 0, PC_EVENTS, PC_KRAUS, PC_GRAM, PC_TRIDIAG, PC_TRIEIG, PC_HOPEIG, PC_BACK, PC_RECOMPOSE, PC_HOPGEMM,
-  PC_SMALL, PC_EXPECT, PC_COUNT
+  PC_SMALL, PC_EXPECT, PC_TRIDIAG_S, PC_TRIDIAG_L, PC_BACK_L, PC_COUNT
 };
 
 struct Prof {
@@ -224,7 +224,10 @@ void prof_collect(mpsb_batch* h) {
 hipError_t heev_all(mpsb_batch* h, int n, int keep, double zt, void* A, long long sA, double* ws, long long sW,
                     double* gws, long long sG, double* ev, long long sE, double* kept, void* Z, long long sZ, int batch,
                     bool hop = false) {
-  const int cls[4] = {PC_TRIDIAG, PC_TRIEIG, PC_HOPEIG, PC_BACK};
+  // one class per kernel instance: the tridiagonalisation has instances for n <= 128,
+  // n <= 256 and n <= 512, the back-transformation for n <= 256 and n <= 512
+  const int tri = n <= 128 ? PC_TRIDIAG_S : n <= 256 ? PC_TRIDIAG : PC_TRIDIAG_L;
+  const int cls[4] = {tri, PC_TRIEIG, PC_HOPEIG, n <= 256 ? PC_BACK : PC_BACK_L};
   for (int ph = 0; ph < 4; ++ph) {
     if (ph == 2) continue;
     ProfSec s(h, hop ? PC_HOPEIG : cls[ph]);
