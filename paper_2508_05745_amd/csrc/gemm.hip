@@ -285,9 +285,190 @@ __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, 
   }
 }
 
+// Large-tile FP32 variant for the bulk bonds (chi_L, chi_R >= 64): 64 values of a x 64
+// values of b per workgroup (128 rows x 128 columns of theta), 2 x 2 waves of 32 x 32 values,
+// each wave 2 x 2 MFMA sub-tiles of 16 x 16 for each of the four (s,t) blocks (128
+// accumulator registers per lane).  The next K block of 16 is loaded into registers while
+// the current one is multiplied out of LDS.  The site tensors are stored in LDS as [k][s][a]
+// and [k][t][b] with a row pitch of 144 floats, so that the four k-rows a wave reads at once
+// fall in different bank halves.  Workgroup ids are remapped so that all tiles of one
+// trajectory run on one XCD (the hardware deals consecutive ids round-robin over the 8 XCDs)
+// and share the trajectory's site tensors in that XCD's L2.
+constexpr int TL_P = 144;
+
+__global__ __launch_bounds__(256) void k_theta_l(int chi_l, int chi_m, int chi_r, const c32* __restrict__ Cs,
+                                                 const c32* __restrict__ Bs, long long s_traj, c32* __restrict__ out,
+                                                 long long s_out, Mat4 gate, double* __restrict__ partial, int tiles_a,
+                                                 int tiles_b) {
+  __shared__ float A_re[16][TL_P], A_im[16][TL_P];   // [k][s*64 + (a - a0)]
+  __shared__ float B_re[16][TL_P], B_im[16][TL_P];   // [k][t*64 + (b - b0)]
+  __shared__ double red[4][32];
+  // XCD-aware numbering: hardware id w runs on XCD w % 8; logical ids of XCD x are the
+  // contiguous range starting at x * q + min(x, r) (q = G / 8, r = G % 8)
+  const int G = gridDim.x, w = blockIdx.x;
+  const int q8 = G >> 3, r8 = G & 7, x8 = w & 7;
+  const int L = x8 * q8 + min(x8, r8) + (w >> 3);
+  const int nt = tiles_a * tiles_b;
+  const int traj = L / nt, tile = L - traj * nt;
+  const int ta = tile / tiles_b, tb = tile - ta * tiles_b;
+  const c32* Cp = Cs + traj * s_traj;
+  const c32* Bp = Bs + traj * s_traj;
+  c32* O = out + traj * s_out;
+  const int a0 = ta * 64, b0 = tb * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wa = wv >> 1, wb = wv & 1;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int ldb = 2 * chi_r;
+  v4f acc_re[2][2][4], acc_im[2][2][4];   // [ia][jb][2s+t]
+#pragma unroll
+  for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        acc_re[ia][jb][x] = v4f{0, 0, 0, 0};
+        acc_im[ia][jb][x] = v4f{0, 0, 0, 0};
+      }
+  c32 pa[8], pb[8];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tid + 256 * r;
+      const int kk = e & 15, row = e >> 4;   // row = 2 (a - a0) + s
+      const int a = a0 + (row >> 1), k = k0 + kk;
+      pa[r] = (a < chi_l && k < chi_m) ? Cp[(long long)(2 * a + (row & 1)) * chi_m + k] : c32{0, 0};
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tid + 256 * r;
+      const int col = e & 127, kk = e >> 7;  // col = t * 64 + (b - b0)
+      const int b = b0 + (col & 63), k = k0 + kk;
+      pb[r] = (b < chi_r && k < chi_m) ? Bp[(long long)k * ldb + (col >> 6) * chi_r + b] : c32{0, 0};
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < chi_m; k0 += 16) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tid + 256 * r;
+      const int kk = e & 15, row = e >> 4;
+      const int c = (row & 1) * 64 + (row >> 1);
+      A_re[kk][c] = pa[r].re;
+      A_im[kk][c] = pa[r].im;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tid + 256 * r;
+      const int col = e & 127, kk = e >> 7;
+      B_re[kk][col] = pb[r].re;
+      B_im[kk][col] = pb[r].im;
+    }
+    __syncthreads();
+    if (k0 + 16 < chi_m) gload(k0 + 16);
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      const int kk = 4 * k4 + kq;
+      float ar[2][2], ai[2][2], br[2][2], bi[2][2];
+#pragma unroll
+      for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const int ca = s2 * 64 + 32 * wa + 16 * i2 + r16;
+          ar[i2][s2] = A_re[kk][ca];
+          ai[i2][s2] = A_im[kk][ca];
+          const int cb = s2 * 64 + 32 * wb + 16 * i2 + r16;
+          br[i2][s2] = B_re[kk][cb];
+          bi[i2][s2] = B_im[kk][cb];
+        }
+#pragma unroll
+      for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int t2 = 0; t2 < 2; ++t2) {
+              const int x = 2 * s2 + t2;
+              v4f cr = acc_re[ia][jb][x], ci = acc_im[ia][jb][x];
+              cr = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ia][s2], br[jb][t2], cr, 0, 0, 0);
+              cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[ia][s2], bi[jb][t2], cr, 0, 0, 0);
+              ci = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ia][s2], bi[jb][t2], ci, 0, 0, 0);
+              ci = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[ia][s2], br[jb][t2], ci, 0, 0, 0);
+              acc_re[ia][jb][x] = cr;
+              acc_im[ia][jb][x] = ci;
+            }
+    }
+    __syncthreads();
+  }
+  // epilogue: lane holds a = a0 + 32 wa + 16 ia + 4 kq + i, b = b0 + 32 wb + 16 jb + r16
+  double rr[16], ri[16];
+#pragma unroll
+  for (int x = 0; x < 16; ++x) rr[x] = ri[x] = 0.0;
+#pragma unroll
+  for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      const int b = b0 + 32 * wb + 16 * jb + r16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int a = a0 + 32 * wa + 16 * ia + 4 * kq + i;
+        if (a >= chi_l || b >= chi_r) continue;
+        double vr[4], vi[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          double sr = 0, si = 0;
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            const double gr = gate.v[2 * (4 * x + y)], gi = gate.v[2 * (4 * x + y) + 1];
+            const double tr = (double)acc_re[ia][jb][y][i], tim = (double)acc_im[ia][jb][y][i];
+            sr += gr * tr - gi * tim;
+            si += gr * tim + gi * tr;
+          }
+          c32 o;
+          o.re = (float)sr;
+          o.im = (float)si;
+          O[(long long)(2 * a + (x >> 1)) * ldb + (x & 1) * chi_r + b] = o;
+          vr[x] = (double)o.re;
+          vi[x] = (double)o.im;
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            rr[4 * x + y] += vr[x] * vr[y] + vi[x] * vi[y];
+            ri[4 * x + y] += vi[x] * vr[y] - vr[x] * vi[y];
+          }
+      }
+    }
+#pragma unroll
+  for (int x = 0; x < 32; ++x) {
+    double v = (x < 16) ? rr[x] : ri[x - 16];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][x] = v;
+  }
+  __syncthreads();
+  if (tid < 32) {
+    double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    int x = tid & 15;
+    double* p = partial + ((long long)traj * nt + tile) * 32;
+    if (tid < 16) p[2 * x] = v; else p[2 * x + 1] = v;
+  }
+}
+
+static bool theta_large(int prec, int chi_l, int chi_r) { return prec == 0 && chi_l >= 64 && chi_r >= 64; }
+
 hipError_t theta(int prec, int chi_l, int chi_m, int chi_r, const void* Cs, const void* Bs,
                  long long s_traj, void* out, long long s_out, const Mat4& gate, double* partial,
                  int n_traj, hipStream_t st) {
+  if (theta_large(prec, chi_l, chi_r)) {
+    const int ta = (chi_l + 63) / 64, tb = (chi_r + 63) / 64;
+    const long long blocks = (long long)ta * tb * n_traj;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_theta_l, dim3((unsigned)blocks), dim3(256), 0, st, chi_l, chi_m, chi_r, (const c32*)Cs,
+                       (const c32*)Bs, s_traj, (c32*)out, s_out, gate, partial, ta, tb);
+    return hipGetLastError();
+  }
   dim3 grid((chi_r + 31) / 32, (chi_l + 31) / 32, n_traj);
   int nt = grid.x * grid.y;
   if (prec == 0)
@@ -297,7 +478,11 @@ hipError_t theta(int prec, int chi_l, int chi_m, int chi_r, const void* Cs, cons
   return hipGetLastError();
 }
 
-int theta_tiles(int chi_l, int chi_r) { return ((chi_r + 31) / 32) * ((chi_l + 31) / 32); }
+// number of RDM tile partials theta writes per trajectory (never more than for 32 x 32 tiles)
+int theta_tiles(int prec, int chi_l, int chi_r) {
+  if (theta_large(prec, chi_l, chi_r)) return ((chi_r + 63) / 64) * ((chi_l + 63) / 64);
+  return ((chi_r + 31) / 32) * ((chi_l + 31) / 32);
+}
 
 // ============================================================================ Kraus pair
 // X[(a,s),(t,b)] <- sum_{s0,t0} Ks[s][s0] Kt[t][t0] X[(a,s0),(t0,b)] in place, with the

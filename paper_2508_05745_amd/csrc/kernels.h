@@ -26,7 +26,7 @@ hipError_t gemm(int prec_in, int prec_out, bool conj_a, bool conj_b, int M, int 
                 const double* alpha, int batch, hipStream_t st);
 hipError_t theta(int prec, int chi_l, int chi_m, int chi_r, const void* Cs, const void* Bs, long long s_traj,
                  void* out, long long s_out, const Mat4& gate, double* partial, int n_traj, hipStream_t st);
-int theta_tiles(int chi_l, int chi_r);
+int theta_tiles(int prec, int chi_l, int chi_r);
 hipError_t kraus_pair(int prec, int chi_l, int chi_r, void* X, long long s_traj, const double* kops, int n_traj,
                       hipStream_t st);
 hipError_t scale_cast(int prec, int rows, int cols, const void* in, int ld_in, long long s_in,

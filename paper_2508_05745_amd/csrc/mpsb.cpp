@@ -396,7 +396,7 @@ int two_site_step(mpsb_batch* h, int layer, int q, const Mat4& gate, int ch_s, i
     ProfSec s(h, PC_THETA);
     HIPCHK(theta(p, cl, cm, cr, Sq, Sn, L.s_traj, X, L.s_x, gate, partial, T, h->st));
   }
-  const int nt = theta_tiles(cl, cr);
+  const int nt = theta_tiles(p, cl, cr);
   if (ch_s >= 0 || ch_t >= 0) {
     EventArgs ea = base_event_args(h, layer, branch, w_record, h->mode);
     if (ch_s >= 0) fill_channel_slot(h, ea, 0, ch_s);
