@@ -93,8 +93,10 @@ def _event_on_theta(theta, which, kraus, mode, u, fixed_u, record, q, replay=Non
 
 
 def gate_step(m: MPS, l: int, q: int, circuit, chi: int, traj: int, seed: int, mode,
-              fixed_u=None, record=None, replay=None):
-    """One trajectory gate-step on the pair (q, q+1); returns the discarded weight."""
+              fixed_u=None, record=None, replay=None, spectra=None):
+    """One trajectory gate-step on the pair (q, q+1); returns the discarded weight.  If
+    `spectra` is a list, the full singular-value spectrum of the split (before truncation)
+    is appended to it."""
     m.move_centre(q)
     theta = np.einsum("sab,tbc->stac", m.t[q], m.t[q + 1])
     g = circuit.gate(l, q).reshape(2, 2, 2, 2)
@@ -108,6 +110,8 @@ def gate_step(m: MPS, l: int, q: int, circuit, chi: int, traj: int, seed: int, m
     _, _, dl, dr = theta.shape
     mat = theta.transpose(0, 2, 1, 3).reshape(2 * dl, 2 * dr)
     u_, s, vh = np.linalg.svd(mat, full_matrices=False)
+    if spectra is not None:
+        spectra.append(s.copy())
     tot = float(np.sum(s ** 2))
     d = min(chi, s.size)
     kept = float(np.sum(s[:d] ** 2))
@@ -139,7 +143,7 @@ def idle_event(m: MPS, l: int, q: int, circuit, traj: int, seed: int, mode, fixe
 
 def trajectory(circuit, chi: int, traj: int, seed: int, mode=_unr.MODE_OPTIMAL,
                fixed_u=None, layers=None, record=None, layer_range=None, m: MPS = None,
-               replay=None):
+               replay=None, spectra=None):
     """Run one trajectory; returns (MPS, list of per-gate discarded weights)."""
     if m is None:
         m = MPS(circuit.n)
@@ -149,7 +153,7 @@ def trajectory(circuit, chi: int, traj: int, seed: int, mode=_unr.MODE_OPTIMAL,
         for kind, q in _sv.sweep_ops(circuit, l):
             if kind == "gate":
                 eps.append(gate_step(m, l, q, circuit, chi, traj, seed, mode, fixed_u, record,
-                                     replay))
+                                     replay, spectra))
             else:
                 idle_event(m, l, q, circuit, traj, seed, mode, fixed_u, record, replay)
     return m, eps

@@ -193,6 +193,29 @@ def random_two_site_states(count: int, chi_l: int, chi_r: int, seed: int,
     return x.astype(dtype)
 
 
+def random_two_site_states_torch(count: int, chi_l: int, chi_r: int, seed: int, device: str = "cuda"):
+    """Same distribution as ``random_two_site_states`` (complex64), drawn with torch's seeded
+    generator directly on ``device``, for batches too large to draw on the host."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    shape = (count, chi_l, 2, 2, chi_r)
+    x = torch.complex(torch.randn(shape, generator=g, device=device, dtype=torch.float32),
+                      torch.randn(shape, generator=g, device=device, dtype=torch.float32))
+    nrm = torch.linalg.vector_norm(x.reshape(count, -1), dim=1)
+    x /= nrm.reshape(count, 1, 1, 1, 1)
+    return x
+
+
+def haar_unitaries(count: int, seed: int, d: int = 4) -> np.ndarray:
+    """``count`` Haar-random d x d unitaries (batched form of ``haar_unitary``)."""
+    rng = np.random.default_rng(seed)
+    z = (rng.standard_normal((count, d, d)) + 1j * rng.standard_normal((count, d, d))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    dg = np.diagonal(r, axis1=1, axis2=2)
+    return (q * (dg / np.abs(dg))[:, None, :]).astype(np.complex128)
+
+
 def random_mixing_params(count: int, seed: int, scale: float = 0.1) -> np.ndarray:
     """``count`` x 16 real parameters of a U(4) mixing, N(0, scale^2)."""
     rng = np.random.default_rng(seed)

@@ -53,3 +53,72 @@ def oracle_obs_mps(circuit, chi, t, seed, mode, fixed_u=None, replay=None, recor
                              record=record)
     zi, zz = omps.z_expectations(m)
     return np.concatenate([zi, zz]), eps
+
+
+def run_gpu_sampled(circuit, chi, n_traj, seed, precision, mode, layers, sample):
+    """Run `layers` brickwork layers on the whole batch (the launch configuration of a
+    production run) and keep the recorded mixings / branches / observables of the sampled
+    trajectories only."""
+    import torch
+
+    from paper_2508_05745_amd import mpsb as M
+    b = M.Batch(n_traj, circuit.n, chi, precision, seed)
+    b.set_circuit(circuit, mode)
+    idx = torch.as_tensor(list(sample), device="cuda")
+    w = torch.zeros((n_traj, circuit.n, 4, 4), dtype=torch.complex128, device="cuda")
+    br = torch.zeros((n_traj, circuit.n), dtype=torch.int32, device="cuda")
+    ws, brs = [], []
+    for l in range(layers):
+        b.apply_layer(l, branch=br, w_record=w)
+        ws.append(w[idx].cpu().numpy())
+        brs.append(br[idx].cpu().numpy())
+    mean, m2, pt = b.expect()
+    b.sync()
+    out = dict(mean=mean.cpu().numpy(), m2=m2.cpu().numpy(), per_traj=pt[idx].cpu().numpy(),
+               all_per_traj=pt.cpu().numpy(), w=ws, branch=brs, sample=list(sample), layers=layers)
+    b.close()
+    del w, br, pt, mean, m2
+    torch.cuda.empty_cache()
+    return out
+
+
+def replay_sampled(circuit, chi, seed, out, row):
+    """Oracle MPS replay of sampled trajectory out['sample'][row] over out['layers'] layers:
+    returns (oracle observables, Replay object, GPU branches, oracle branches, singular-value
+    spectra of every split)."""
+    t = out["sample"][row]
+    ws, js = [], []
+    for l in range(out["layers"]):
+        for kind, q in osv.sweep_ops(circuit, l):
+            for x in osv.event_qubits(circuit, l, kind, q):
+                ws.append(out["w"][l][row, x].T.copy())
+                js.append(int(out["branch"][l][row, x]))
+    rp = osv.Replay(ws)
+    rec, spectra = [], []
+    m, _ = omps.trajectory(circuit, chi, t, seed, mode=3, layers=out["layers"], record=rec, replay=rp,
+                           spectra=spectra)
+    zi, zz = omps.z_expectations(m)
+    return np.concatenate([zi, zz]), rp, js, [r["j"] for r in rec], spectra
+
+
+def gram_truncation_bound(spectra, chi, unit_roundoff, const=64.0):
+    """Expected size of the per-trajectory difference between a truncation through the
+    eigenvectors of the Gram matrix M M^dag and one through the SVD of M, from the exact
+    spectra of the splits.  The Gram (and its eigen-solve) carries an absolute error of order
+    u ||M||^2, which rotates the kept subspace into the discarded one by u s_1^2 / (s_D^2 -
+    s_(D+1)^2) (Davis-Kahan); the truncated state then moves by that angle times s_(D+1), and
+    an observable by at most twice that.  Summed over the gate-steps where the cut separates
+    non-zero singular values, with s normalised to unit 2-norm and r = s_(D+1) / s_D:
+        sum_steps u / (s_D (1 - r^2)),
+    capped per step at 2 s_D (the cut can at most misplace the weight next to it).  `const`
+    (64) covers the growth of the rounding error with the inner dimensions (sums of up to 2 chi
+    terms in the Gram, the eigen-solver's backward error) and the factor 2 of an observable."""
+    tot = 0.0
+    for s in spectra:
+        s = s / np.sqrt(np.sum(s ** 2))
+        d = min(chi, s.size)
+        if d >= s.size or s[d] <= 1e-12 * s[0]:
+            continue
+        sd, r = s[d - 1], s[d] / s[d - 1]
+        tot += min(unit_roundoff / (sd * (1.0 - r * r)), 2.0 * sd)
+    return const * tot
