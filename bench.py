@@ -13,6 +13,7 @@ observables) gives `value`; the full-FP64 path is timed on the same steps and th
 difference of the per-trajectory observables is reported.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--chi 128] [--traj 2048]
+       python bench.py --mixed [--traj 16384] [--steps K] [--warmup W]   (mixed-batch workload)
 """
 from __future__ import annotations
 
@@ -182,6 +183,47 @@ def calibrate_copy(nbytes=1 << 30, reps=4):
     print(json.dumps({"calibrate_copy_bytes": nbytes, "dispatches": reps}))
 
 
+def bench_mixed(args):
+    """Mixed batch: 16384 trajectories, each its own circuit (width 24..64, depth 16..32, chi
+    in {16, 32, 64, 128}, depolarizing 0.005..0.03, gates from a 2^16 pool), FP32-bulk, all
+    sub-batches of a layer in one graph launch.  Counts the real gates (not the identity
+    padding past a trajectory's depth) of the timed layers."""
+    import torch
+
+    from paper_2508_05745_amd import inputs as I
+    from paper_2508_05745_amd import mpsb as M
+    n_traj = args.traj if args.traj != 2048 else 16384
+    wl = I.config_mixed(n_traj)
+    mc = wl.circuit
+    W, K = args.warmup, args.steps
+    b = M.Batch(mc.n_traj, mc.widths, mc.chis, M.FP32_BULK, wl.seed)
+    b.set_circuit(mc, M.OPTIMAL)
+    for l in range(W):
+        b.apply_layer(l)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for l in range(W, W + K):
+        b.apply_layer(l)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.sync()
+    gates = int((mc.gate_id[:, W:W + K, :] >= 0).sum())
+    per_chi = {int(c): int((mc.gate_id[mc.chis == c][:, W:W + K, :] >= 0).sum()) for c in np.unique(mc.chis)}
+    n_sub = int(np.count_nonzero(np.diff(mc.widths) != 0) + np.count_nonzero(np.diff(mc.chis) != 0) + 1)
+    b.close()
+    line = {
+        "metric": "trajectory gate-steps/s (mixed batch)", "value": gates / dt, "unit": "trajectory gate-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * dt / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 contractions (fp32) + fp64 eig/unravel",
+        "data": "synthetic (seeded per-trajectory Haar brickwork from a 2^16-gate pool)",
+        "config": {"workload": wl.name, "n_traj": mc.n_traj, "max_width": mc.n, "max_depth": mc.depth,
+                   "sub_batches_upper_bound": n_sub, "timed_layers": [W, W + K - 1],
+                   "gate_steps_timed": gates, "gate_steps_per_chi": per_chi},
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,11 +233,18 @@ def main():
     ap.add_argument("--traj", type=int, default=2048)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mixed", action="store_true", help="the mixed-batch workload instead of the headline one")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB elementwise copy kernel 4 times (HBM counter scale)")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.mixed:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU", "n_gpus": args.gpus}))
+            sys.exit(2)
+        bench_mixed(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding (disjoint "

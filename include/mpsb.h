@@ -52,55 +52,88 @@ extern "C" {
 
 #define MPSB_MAX_CHI 256      /* largest supported bond dimension                       */
 #define MPSB_MAX_QUBITS 4096
-#define MPSB_MAX_CHANNELS 16
+#define MPSB_MAX_CHANNELS 1048576   /* channel table entries (device table) */
 
 typedef struct mpsb_batch* mpsb_handle;
 
 /* Noisy brickwork circuit (the classical description D of the paper's truncated
  * trajectory sampling task: qubit order = chain order, initial state |0...0>, a string
  * of layers of two-qubit gates composed with single-qubit noise).  Host pointers; the
- * library copies everything it needs during mps_batch_set_circuit.
+ * library copies what it needs into the caller's circuit buffer during
+ * mps_batch_set_circuit.  W = the widest trajectory of the batch.
  *
- *   layer l (0-based) acts on the pairs (p, p+1), (p+2, p+3), ... with p = l % 2;
- *   gates  [depth][n_qubits/2][4][4] c128: slot i of layer l is the pair (p+2i, p+2i+1),
- *          basis index 2*s + t with s the lower qubit of the pair;
+ *   layer l (0-based) acts on the pairs (p, p+1), (p+2, p+3), ... with p = l % 2 (only the
+ *          pairs inside a trajectory's own width);
+ *   n_gates == 0: gates [depth][W/2][4][4] c128, one circuit shared by all trajectories:
+ *          slot i of layer l is the pair (p+2i, p+2i+1), basis index 2*s + t with s the
+ *          lower qubit of the pair;
+ *   n_gates > 0: gates is a pool [n_gates][4][4] c128 and gate_id [n_traj][depth][W/2] the
+ *          pool index of slot i of layer l of each trajectory, -1 = identity (used past a
+ *          trajectory's own depth);
  *   kraus  [n_channels][4][2][2] c128, zero padded; n_kraus[c] in 1..4 operators used;
- *   events [depth][n_qubits] int32: channel applied to qubit q in layer l, -1 = none.
- *          Noise on a gate's qubits follows that gate (lower qubit first); noise on an
- *          idle qubit is applied when the layer's sweep reaches it;
+ *   events [depth][W] (events_per_traj == 0) or [n_traj][depth][W] (events_per_traj == 1)
+ *          int32: channel applied to qubit q in layer l, -1 = none.  Noise on a gate's
+ *          qubits follows that gate (lower qubit first); noise on an idle qubit is applied
+ *          when the layer's sweep reaches it;
  *   fixed_u [n_channels][4][4] c128 (row j = output operator), used with MPSB_FIXED.
  */
 typedef struct {
     int depth;
     const double* gates;
+    int n_gates;
+    const int32_t* gate_id;
     int n_channels;
     const double* kraus;
     const int32_t* n_kraus;
     const int32_t* events;
+    int events_per_traj;
     int unravel_mode;
     const double* fixed_u; /* may be NULL unless unravel_mode == MPSB_FIXED */
 } mpsb_circuit;
 
-/* Sizes of the two caller buffers for n_traj trajectories of an n_qubits chain truncated
- * to bond dimension chi (1..MPSB_MAX_CHI).  Bond k (between qubits k and k+1) has the fixed
- * capacity min(chi, 2^(k+1), 2^(n-k-1)).  precision: MPSB_FP32_BULK or MPSB_FP64.
- * Returns MPSB_EINVAL for bad arguments. */
-int mps_batch_plan(int n_traj, int n_qubits, int chi, int precision, size_t* state_bytes,
-                   size_t* work_bytes);
+/* Sizes of the two caller buffers for n_traj trajectories; trajectory t is a chain of
+ * width[t] qubits truncated to bond dimension chi[t] (1..MPSB_MAX_CHI).  Bond k (between
+ * qubits k and k+1) has the fixed capacity min(chi, 2^(k+1), 2^(n-k-1)).  Maximal runs of
+ * consecutive trajectories with equal (width, chi) form the batch's uniform sub-batches
+ * (group equal shapes together); a batch of one run is a uniform batch.  precision:
+ * MPSB_FP32_BULK or MPSB_FP64.  Host arrays.  Returns MPSB_EINVAL for bad arguments. */
+int mps_batch_plan(int n_traj, const int32_t* width, const int32_t* chi, int precision,
+                   size_t* state_bytes, size_t* work_bytes);
 
 /* Creates a batch in |0...0> with the orthogonality centre at qubit 0.  state_buf /
  * work_buf: device buffers of at least the planned sizes (256-byte aligned); seed keys the
  * counter-based branch sampler (SplitMix64 output number 1 + (traj<<32 | layer<<16 |
- * qubit)).  The initial state is written asynchronously on `stream`. */
-int mps_batch_create(int n_traj, int n_qubits, int chi, int precision, uint64_t seed,
-                     void* state_buf, size_t state_bytes, void* work_buf, size_t work_bytes,
-                     void* stream, mpsb_handle* out);
+ * qubit), traj = index in the batch).  The initial state is written on `stream`, which all
+ * later calls use; a mixed batch also creates private streams (default priority) on which
+ * its sub-batches run concurrently.  The handle owns host metadata, streams, events and
+ * captured graphs only. */
+int mps_batch_create(int n_traj, const int32_t* width, const int32_t* chi, int precision,
+                     uint64_t seed, void* state_buf, size_t state_bytes, void* work_buf,
+                     size_t work_bytes, void* stream, mpsb_handle* out);
 
-/* Copies and validates the circuit: every Kraus set must satisfy
- * ||sum_i K_i^dag K_i - I||_max <= 1e-12 (else MPSB_EKRAUS), every gate
- * ||G^dag G - I||_max <= 1e-12 (else MPSB_EINVAL), event ids must name a channel or be
- * -1, FIXED mixings must be unitary on the used columns. */
-int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c);
+/* Bytes of the device circuit buffer mps_batch_set_circuit needs for circuit c on batch h. */
+int mps_circuit_bytes(mpsb_handle h, const mpsb_circuit* c, size_t* bytes);
+
+/* Validates the circuit and writes its device tables (gate pool, gate ids, channel table,
+ * event ids, the device layer counter) into circuit_buf (device, 256-byte aligned, at least
+ * mps_circuit_bytes; caller-owned, must stay allocated while layers are applied).  Checks:
+ * every Kraus set ||sum_i K_i^dag K_i - I||_max <= 1e-12 (else MPSB_EKRAUS), every gate
+ * ||G^dag G - I||_max <= 1e-12 (else MPSB_EINVAL), gate ids in -1..n_gates-1, event ids
+ * name a channel or are -1, FIXED mixings unitary on the used columns.  Blocks until the
+ * tables are on the device. */
+int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c, void* circuit_buf,
+                          size_t circuit_bytes);
+
+/* Whole-layer graphs (default on): the first layer with a given launch signature (sweep
+ * parity, operations, centre position) runs directly, the second is captured into a HIP
+ * graph and every later one replays it with a single graph launch.  Layers that write
+ * records, or run while profiling, always run directly. */
+int mps_batch_set_graphs(mpsb_handle h, int enable);
+
+/* Autotuning of the theta kernel's tile shape (default on): the first time a shape occurs
+ * outside a capture, each applicable variant is timed on the live operands and the faster
+ * one is kept for the batch.  Disabling it (or re-enabling) clears the choices. */
+int mps_batch_set_autotune(mpsb_handle h, int enable);
 
 /* Applies brickwork layer `layer` (0 <= layer < depth) to every trajectory: for each pair
  * in sweep order (left to right for even layers, right to left for odd layers) the two-
@@ -108,12 +141,12 @@ int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c);
  * sampled Kraus operator; Alg. 1), truncation of the pair's bond to its capacity with
  * renormalisation, and the move of the orthogonality centre to the next pair; idle-qubit
  * noise when the sweep reaches the qubit.  Layers must be applied in order 0, 1, 2, ...
- * Optional device outputs (NULL to skip):
- *   discarded [n_traj][n_qubits/2] FP64: discarded weight sum_{i>D} lambda_i / sum_i
- *             lambda_i of each gate (slot i = pair p+2i; untouched slots are set to 0);
- *   branch    [n_traj][n_qubits] int32: sampled branch of the event on each qubit (-1 =
- *             no event);
- *   w_record  [n_traj][n_qubits][4][4] c128: the mixing U used by each event (K'_j =
+ * Optional device outputs (NULL to skip; W = the widest trajectory):
+ *   discarded [n_traj][W/2] FP64: discarded weight sum_{i>D} lambda_i / sum_i lambda_i of
+ *             each gate (slot i = pair p+2i; untouched slots are set to 0);
+ *   branch    [n_traj][W] int32: sampled branch of the event on each qubit (-1 = no
+ *             event);
+ *   w_record  [n_traj][W][4][4] c128: the mixing U used by each event (K'_j =
  *             sum_i U[j][i] K_i), rows j, columns i (unused columns zero). */
 int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch,
                 double* w_record);
@@ -128,6 +161,8 @@ int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch,
 int sample_kraus(mpsb_handle h, const int32_t* qubit, int channel, int unravel_mode,
                  int rng_layer, const int32_t* forced, int32_t* branch, double* p);
 
+/* (sample_kraus and mps_truncate need a uniform batch: MPSB_ENOTSUP otherwise.) */
+
 /* Approximation subprocedure on demand (Sec. "Class of Truncated Trajectory Sampling
  * Algorithms"): truncates every bond to min(chi, capacity) with a full left-to-right sweep
  * (discarding the smallest Schmidt values, renormalising), then moves the centre back to
@@ -136,14 +171,16 @@ int sample_kraus(mpsb_handle h, const int32_t* qubit, int channel, int unravel_m
  * that it does not collide with the POSIX truncate(2) declaration.) */
 int mps_truncate(mpsb_handle h, int chi, double* discarded);
 
-/* Host-only validation of a circuit for an n_qubits chain: the checks of
- * mps_batch_set_circuit, without a handle or a device. */
-int mps_circuit_validate(int n_qubits, const mpsb_circuit* c);
+/* Host-only validation of a circuit for n_traj trajectories of widths width[] (host
+ * array): the checks of mps_batch_set_circuit, without a handle or a device. */
+int mps_circuit_validate(int n_traj, const int32_t* width, const mpsb_circuit* c);
 
 /* Observables of every trajectory: <Z_i> (i = 0..n-1) then <Z_i Z_{i+1}> (i = 0..n-2),
  * computed in FP64 with left/right environments (normalised by <psi|psi>).  Device
  * outputs: mean [2n-1] and m2 [2n-1] (sum of squared deviations) over trajectories,
- * reduced in a fixed order (bitwise reproducible); per_traj [n_traj][2n-1] (or NULL). */
+ * reduced in a fixed order (bitwise reproducible), or both NULL; per_traj [n_traj][2W-1]
+ * (or NULL), rows NaN-padded past a trajectory's own 2n-1 entries.  A mixed batch
+ * reports per_traj only (mean = m2 = NULL, else MPSB_ENOTSUP). */
 int expect(mpsb_handle h, double* mean, double* m2, double* per_traj);
 
 /* Optional per-kernel-class timing with HIP events recorded on the batch stream (for

@@ -2,6 +2,8 @@
 // Gram matrices, recomposition, centre hops and environments, the two-site theta
 // contraction with the gate and two-site reduced density matrix fused in its epilogue, the
 // in-place application of the sampled Kraus pair, and small cast/scale helpers.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -143,6 +145,20 @@ hipError_t gemm(int prec_in, int prec_out, bool ca, bool cb, int M, int N, int K
 // result D[i][j] sits in lane j + 16 (i / 4), register i % 4 for the f32 instruction and in
 // lane j + 16 (i % 4), register i / 4 for the f64 one (checked on the device).
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// the 4x4 gate of trajectory traj (uniform over the workgroup)
+__device__ inline void load_gate(const Mat4& gate, const GateRef& gref, int traj, double (&gg)[32]) {
+  if (gref.pool) {
+    const int id = gref.ids[traj * gref.traj_stride + (long long)(*gref.layer) * gref.layer_stride + gref.pair];
+    const double* g = gref.pool + 32LL * id;
+#pragma unroll
+    for (int x = 0; x < 32; ++x) gg[x] = g[x];
+  } else {
+#pragma unroll
+    for (int x = 0; x < 32; ++x) gg[x] = gate.v[x];
+  }
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <typename T> struct MfmaAcc;
@@ -160,7 +176,7 @@ template <> struct MfmaAcc<double> {
 template <typename T>
 __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, const cplx<T>* __restrict__ Cs,
                                                     const cplx<T>* __restrict__ Bs, long long s_traj,
-                                                    cplx<T>* __restrict__ out, long long s_out, Mat4 gate,
+                                                    cplx<T>* __restrict__ out, long long s_out, Mat4 gate, GateRef gref,
                                                     double* __restrict__ partial, int n_tiles) {
   using M = MfmaAcc<T>;
   using V = typename M::V;
@@ -234,6 +250,8 @@ __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, 
     __syncthreads();
   }
   // epilogue: lane holds rows a = a0 + 16 wa + row(kq, i), column b = b0 + 16 wb + r16
+  double gg[32];
+  load_gate(gate, gref, traj, gg);
   double rr[16], ri[16];
 #pragma unroll
   for (int x = 0; x < 16; ++x) rr[x] = ri[x] = 0.0;
@@ -248,7 +266,7 @@ __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, 
       double sr = 0, si = 0;
 #pragma unroll
       for (int y = 0; y < 4; ++y) {
-        const double gr = gate.v[2 * (4 * x + y)], gi = gate.v[2 * (4 * x + y) + 1];
+        const double gr = gg[2 * (4 * x + y)], gi = gg[2 * (4 * x + y) + 1];
         const double tr = (double)acc_re[y][i], tim = (double)acc_im[y][i];
         sr += gr * tr - gi * tim;
         si += gr * tim + gi * tr;
@@ -298,7 +316,7 @@ constexpr int TL_P = 144;
 
 __global__ __launch_bounds__(256) void k_theta_l(int chi_l, int chi_m, int chi_r, const c32* __restrict__ Cs,
                                                  const c32* __restrict__ Bs, long long s_traj, c32* __restrict__ out,
-                                                 long long s_out, Mat4 gate, double* __restrict__ partial, int tiles_a,
+                                                 long long s_out, Mat4 gate, GateRef gref, double* __restrict__ partial, int tiles_a,
                                                  int tiles_b) {
   __shared__ float A_re[16][TL_P], A_im[16][TL_P];   // [k][s*64 + (a - a0)]
   __shared__ float B_re[16][TL_P], B_im[16][TL_P];   // [k][t*64 + (b - b0)]
@@ -401,6 +419,8 @@ __global__ __launch_bounds__(256) void k_theta_l(int chi_l, int chi_m, int chi_r
     __syncthreads();
   }
   // epilogue: lane holds a = a0 + 32 wa + 16 ia + 4 kq + i, b = b0 + 32 wb + 16 jb + r16
+  double gg[32];
+  load_gate(gate, gref, traj, gg);
   double rr[16], ri[16];
 #pragma unroll
   for (int x = 0; x < 16; ++x) rr[x] = ri[x] = 0.0;
@@ -419,7 +439,7 @@ __global__ __launch_bounds__(256) void k_theta_l(int chi_l, int chi_m, int chi_r
           double sr = 0, si = 0;
 #pragma unroll
           for (int y = 0; y < 4; ++y) {
-            const double gr = gate.v[2 * (4 * x + y)], gi = gate.v[2 * (4 * x + y) + 1];
+            const double gr = gg[2 * (4 * x + y)], gi = gg[2 * (4 * x + y) + 1];
             const double tr = (double)acc_re[ia][jb][y][i], tim = (double)acc_im[ia][jb][y][i];
             sr += gr * tr - gi * tim;
             si += gr * tim + gi * tr;
@@ -456,32 +476,74 @@ __global__ __launch_bounds__(256) void k_theta_l(int chi_l, int chi_m, int chi_r
   }
 }
 
-static bool theta_large(int prec, int chi_l, int chi_r) { return prec == 0 && chi_l >= 64 && chi_r >= 64; }
+int theta_variant_ok(int prec, int variant, int chi_l, int chi_r) {
+  if (variant == 0) return 1;
+  if (variant == 1) return prec == 0 && chi_l >= 16 && chi_r >= 16;
+  return 0;
+}
+
+int theta_default_variant(int prec, int chi_l, int chi_r) { return (prec == 0 && chi_l >= 64 && chi_r >= 64) ? 1 : 0; }
 
 hipError_t theta(int prec, int chi_l, int chi_m, int chi_r, const void* Cs, const void* Bs,
-                 long long s_traj, void* out, long long s_out, const Mat4& gate, double* partial,
-                 int n_traj, hipStream_t st) {
-  if (theta_large(prec, chi_l, chi_r)) {
+                 long long s_traj, void* out, long long s_out, const Mat4& gate, const GateRef& gref, double* partial,
+                 int n_traj, hipStream_t st, int variant) {
+  if (variant < 0) variant = theta_default_variant(prec, chi_l, chi_r);
+  if (!theta_variant_ok(prec, variant, chi_l, chi_r)) return hipErrorInvalidValue;
+  if (variant == 1) {
     const int ta = (chi_l + 63) / 64, tb = (chi_r + 63) / 64;
     const long long blocks = (long long)ta * tb * n_traj;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_theta_l, dim3((unsigned)blocks), dim3(256), 0, st, chi_l, chi_m, chi_r, (const c32*)Cs,
-                       (const c32*)Bs, s_traj, (c32*)out, s_out, gate, partial, ta, tb);
+                       (const c32*)Bs, s_traj, (c32*)out, s_out, gate, gref, partial, ta, tb);
     return hipGetLastError();
   }
   dim3 grid((chi_r + 31) / 32, (chi_l + 31) / 32, n_traj);
   int nt = grid.x * grid.y;
   if (prec == 0)
-    hipLaunchKernelGGL(k_theta<float>, grid, dim3(256), 0, st, chi_l, chi_m, chi_r, (const c32*)Cs, (const c32*)Bs, s_traj, (c32*)out, s_out, gate, partial, nt);
+    hipLaunchKernelGGL(k_theta<float>, grid, dim3(256), 0, st, chi_l, chi_m, chi_r, (const c32*)Cs, (const c32*)Bs, s_traj, (c32*)out, s_out, gate, gref, partial, nt);
   else
-    hipLaunchKernelGGL(k_theta<double>, grid, dim3(256), 0, st, chi_l, chi_m, chi_r, (const c64d*)Cs, (const c64d*)Bs, s_traj, (c64d*)out, s_out, gate, partial, nt);
+    hipLaunchKernelGGL(k_theta<double>, grid, dim3(256), 0, st, chi_l, chi_m, chi_r, (const c64d*)Cs, (const c64d*)Bs, s_traj, (c64d*)out, s_out, gate, gref, partial, nt);
   return hipGetLastError();
 }
 
-// number of RDM tile partials theta writes per trajectory (never more than for 32 x 32 tiles)
-int theta_tiles(int prec, int chi_l, int chi_r) {
-  if (theta_large(prec, chi_l, chi_r)) return ((chi_r + 63) / 64) * ((chi_l + 63) / 64);
+// number of RDM tile partials the theta variant writes per trajectory (never more than for
+// 32 x 32 tiles)
+int theta_tiles(int variant, int chi_l, int chi_r) {
+  if (variant == 1) return ((chi_r + 63) / 64) * ((chi_l + 63) / 64);
   return ((chi_r + 31) / 32) * ((chi_l + 31) / 32);
+}
+
+// device layer counter
+__global__ void k_set_int(int* p, int v) { *p = v; }
+__global__ void k_inc_int(int* p) { *p += 1; }
+hipError_t set_int(int* p, int v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v);
+  return hipGetLastError();
+}
+hipError_t inc_int(int* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_inc_int, dim3(1), dim3(1), 0, st, p);
+  return hipGetLastError();
+}
+
+// batched strided block copy (16-byte or 8-byte elements)
+template <typename T>
+__global__ void k_copy_blocks(cplx<T>* dst, long long s_dst, const cplx<T>* src, long long s_src, long long elems,
+                              int n_traj) {
+  const long long total = elems * n_traj;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const long long t = e / elems, i = e - t * elems;
+    dst[t * s_dst + i] = src[t * s_src + i];
+  }
+}
+
+hipError_t copy_blocks_k(int prec, void* dst, long long s_dst, const void* src, long long s_src, long long elems,
+                         int n_traj, hipStream_t st) {
+  long long total = elems * n_traj;
+  int nb = (int)std::min<long long>((total + 255) / 256, 65536);
+  if (nb < 1) return hipSuccess;
+  if (prec == 0) hipLaunchKernelGGL(k_copy_blocks<float>, dim3(nb), dim3(256), 0, st, (c32*)dst, s_dst, (const c32*)src, s_src, elems, n_traj);
+  else hipLaunchKernelGGL(k_copy_blocks<double>, dim3(nb), dim3(256), 0, st, (c64d*)dst, s_dst, (const c64d*)src, s_src, elems, n_traj);
+  return hipGetLastError();
 }
 
 // ============================================================================ Kraus pair

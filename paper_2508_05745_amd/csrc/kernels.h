@@ -7,17 +7,41 @@
 
 namespace mpsb {
 
-// Arguments of the noise-event kernels.  Channel data of at most two channels (slot 0: the
-// lower / single qubit of the launch, slot 1: the upper qubit of a gate) travel by value.
+// Arguments of the noise-event kernels.  Channel data either travel by value (at most two
+// channels: slot 0 the lower / single qubit of the launch, slot 1 the upper qubit of a gate),
+// or, when ev_ids is set, come from the device circuit tables: the channel of the event on
+// qubit x of trajectory t in the current layer is
+//   ev_ids[t * ev_traj_stride + layer * ev_layer_stride + x]   (-1: no event),
+// with its Kraus operators, their count and the fixed mixing in kraus_tab / nk_tab / fixed_tab.
+// The layer is read from *layer_ptr when that is set (device layer counter), else `layer`.
+// Branch draws are keyed by the global trajectory index traj_base + t.
 struct EventArgs {
   int n_traj, n_qubits, layer, mode;
   int rec_stride, rec_qbase;   // record index = traj * rec_stride + (qubit - rec_qbase)
   uint64_t seed;
-  int32_t* branch_out;   // [n_traj][n_qubits] or NULL
-  double* w_out;         // [n_traj][n_qubits][4][4] c128 or NULL
+  int32_t* branch_out;   // [n_traj][rec_stride] or NULL
+  double* w_out;         // [n_traj][rec_stride][4][4] c128 or NULL
   int n_kraus[2];
   double kraus[2][32];
   double fixed_u[2][32];
+  const int* ev_ids;
+  long long ev_traj_stride;
+  int ev_layer_stride;
+  const double* kraus_tab;   // [n_ch][4][2][2] c128
+  const int* nk_tab;         // [n_ch]
+  const double* fixed_tab;   // [n_ch][4][4] c128 or NULL
+  const int* layer_ptr;
+  int traj_base;
+};
+
+// Gate of a two-site step: by value, or (pool set) pool[ids[t * traj_stride + layer *
+// layer_stride + pair]] with the layer read from *layer.
+struct GateRef {
+  const double* pool;   // [n][4][4] c128
+  const int* ids;
+  long long traj_stride;
+  int layer_stride, pair;
+  const int* layer;
 };
 
 // prec: 0 = complex64 storage / FP32 arithmetic, 1 = complex128 / FP64
@@ -25,8 +49,19 @@ hipError_t gemm(int prec_in, int prec_out, bool conj_a, bool conj_b, int M, int 
                 long long sA, const void* B, int ldb, long long sB, void* C, int ldc, long long sC,
                 const double* alpha, int batch, hipStream_t st);
 hipError_t theta(int prec, int chi_l, int chi_m, int chi_r, const void* Cs, const void* Bs, long long s_traj,
-                 void* out, long long s_out, const Mat4& gate, double* partial, int n_traj, hipStream_t st);
-int theta_tiles(int prec, int chi_l, int chi_r);
+                 void* out, long long s_out, const Mat4& gate, const GateRef& gref, double* partial, int n_traj,
+                 hipStream_t st, int variant = -1);
+// theta kernel variants: 0 = 32 x 32 tiles, 1 = 64 x 64 tiles (FP32 only); -1 = default rule
+int theta_variant_ok(int prec, int variant, int chi_l, int chi_r);
+int theta_default_variant(int prec, int chi_l, int chi_r);
+int theta_tiles(int variant, int chi_l, int chi_r);
+// device layer counter
+hipError_t set_int(int* p, int v, hipStream_t st);
+hipError_t inc_int(int* p, hipStream_t st);
+// batched strided copy of rows x row_elems elements between per-trajectory blocks (a kernel,
+// so that it can sit in a captured graph)
+hipError_t copy_blocks_k(int prec, void* dst, long long s_dst, const void* src, long long s_src, long long elems,
+                         int n_traj, hipStream_t st);
 hipError_t kraus_pair(int prec, int chi_l, int chi_r, void* X, long long s_traj, const double* kops, int n_traj,
                       hipStream_t st);
 hipError_t scale_cast(int prec, int rows, int cols, const void* in, int ld_in, long long s_in,
@@ -76,7 +111,7 @@ hipError_t neg_cols(void* X, long long sX, int rows, int ld, int c0, int w, int 
 hipError_t zero_cols(int prec, void* X, long long sX, int rows, int ld, int c0, int w, int n_traj, hipStream_t st);
 hipError_t obs_trace(int chi, const double* X, long long s_env, const double* R, long long s_R, double* out,
                      int out_stride, int n_traj, hipStream_t st);
-hipError_t obs_normalise(double* per_traj, int n_obs, const double* norms, int n_traj, hipStream_t st);
+hipError_t obs_normalise(double* per_traj, int n_obs, int stride, const double* norms, int n_traj, hipStream_t st);
 hipError_t obs_reduce(const double* per_traj, int n_obs, int n_traj, double* mean, double* m2, hipStream_t st);
 
 // unravelling cost

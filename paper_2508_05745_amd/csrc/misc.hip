@@ -212,16 +212,20 @@ hipError_t obs_trace(int chi, const double* X, long long s_env, const double* R,
   return hipGetLastError();
 }
 
-__global__ void k_obs_normalise(double* per_traj, int n_obs, const double* norms, int n_traj) {
-  long long total = (long long)n_obs * n_traj;
+// per_traj[t][0..n_obs) /= norms[t]; then columns [n_obs, stride) (padding of a mixed batch)
+// are set to NaN
+__global__ void k_obs_normalise(double* per_traj, int n_obs, int stride, const double* norms, int n_traj) {
+  long long total = (long long)stride * n_traj;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
-    int t = (int)(e / n_obs);
-    per_traj[e] /= norms[t];
+    int t = (int)(e / stride), o = (int)(e % stride);
+    if (o < n_obs) per_traj[e] /= norms[t];
+    else per_traj[e] = __builtin_nan("");
   }
 }
 
-hipError_t obs_normalise(double* per_traj, int n_obs, const double* norms, int n_traj, hipStream_t st) {
-  hipLaunchKernelGGL(k_obs_normalise, dim3(nblocks((long long)n_obs * n_traj)), dim3(256), 0, st, per_traj, n_obs, norms, n_traj);
+hipError_t obs_normalise(double* per_traj, int n_obs, int stride, const double* norms, int n_traj, hipStream_t st) {
+  hipLaunchKernelGGL(k_obs_normalise, dim3(nblocks((long long)stride * n_traj)), dim3(256), 0, st, per_traj, n_obs, stride,
+                     norms, n_traj);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -152,25 +153,56 @@ struct Prof {
   long long count[PC_COUNT] = {0};
 };
 
+// device circuit tables (in the caller's circuit buffer)
+struct Tables {
+  int* layer = nullptr;
+  const double* gpool = nullptr;
+  const int* gid = nullptr;
+  long long gid_ts = 0;
+  int gid_ls = 0;
+  const double* kraus = nullptr;
+  const int* nk = nullptr;
+  const double* fixed = nullptr;
+  const int* ev = nullptr;
+  long long ev_ts = 0;
+  int ev_ls = 0;
+};
+
 struct mpsb_batch {
   Prof prof;
   Layout L;
-  uint64_t seed;
-  char* state;
-  char* work;
-  hipStream_t st;
-  int centre;
-  int next_layer;
-  bool has_circuit;
-  // circuit (host copy)
-  int depth;
-  std::vector<double> gates;
-  int n_channels;
+  uint64_t seed = 0;
+  char* state = nullptr;
+  char* work = nullptr;
+  hipStream_t st = nullptr;
+  int centre = 0;
+  int next_layer = 0;
+  bool has_circuit = false;
+  // circuit (host copy of what the launches need)
+  int depth = 0;
+  int n_channels = 0;
   std::vector<double> kraus;
   std::vector<int> n_kraus;
-  std::vector<int> events;
-  int mode;
+  int mode = MPSB_OPTIMAL;
   std::vector<double> fixed_u;
+  std::vector<unsigned char> any_ev;   // [depth][n]: some trajectory has an event on (layer, qubit)
+  Tables tab;
+  int traj_base = 0;                   // global index of trajectory 0 (sub-batch of a mixed batch)
+  int rec_stride = 0;                  // record row length (the widest trajectory of the batch)
+  // mixed batch: sub-batches and their streams
+  std::vector<mpsb_batch*> sub;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> fork_ev, join_ev;
+  int n_traj_total = 0;
+  std::vector<int> width, chi;         // per trajectory (mixed batch)
+  // whole-layer graphs
+  hipStream_t cap_st = nullptr;
+  bool graphs_on = true;
+  struct Graph { hipGraphExec_t exec; int centre_after; };
+  std::map<std::string, Graph> graphs;
+  // theta kernel variant per shape (autotuned on first use)
+  std::map<long long, int> theta_var;
+  bool autotune = true;
 };
 
 namespace {
@@ -253,9 +285,10 @@ int check_status(mpsb_batch* h) {
   return MPSB_OK;
 }
 
-// batched strided copy of a (rows x row_bytes) block from the temp buffer into a site
+// batched strided copy of one contiguous block per trajectory (byte pitches and sizes are
+// multiples of 8); a kernel rather than a 2-D memcpy so that layers can be graph-captured
 hipError_t copy_blocks(void* dst, size_t dpitch, const void* src, size_t spitch, size_t bytes, int n_traj, hipStream_t st) {
-  return hipMemcpy2DAsync(dst, dpitch, src, spitch, bytes, n_traj, hipMemcpyDeviceToDevice, st);
+  return copy_blocks_k(0, dst, (long long)(dpitch / 8), src, (long long)(spitch / 8), (long long)(bytes / 8), n_traj, st);
 }
 
 double zero_tol(const Layout& L) { return L.prec == MPSB_FP64 ? ZERO_TOL_FP64 : ZERO_TOL_FP32; }
@@ -362,6 +395,7 @@ void fill_channel_slot(mpsb_batch* h, EventArgs& ea, int slot, int ch) {
   }
 }
 
+// record outputs point at trajectory 0 of the batch; rows are rec_stride qubits long
 EventArgs base_event_args(mpsb_batch* h, int layer, int32_t* branch, double* w_record, int mode) {
   EventArgs ea;
   memset(&ea, 0, sizeof(ea));
@@ -372,15 +406,63 @@ EventArgs base_event_args(mpsb_batch* h, int layer, int32_t* branch, double* w_r
   ea.seed = h->seed;
   ea.branch_out = branch;
   ea.w_out = w_record;
-  ea.rec_stride = h->L.n;
+  ea.rec_stride = h->rec_stride;
   ea.rec_qbase = 0;
+  ea.traj_base = h->traj_base;
   return ea;
+}
+
+void set_event_tables(mpsb_batch* h, EventArgs& ea) {
+  ea.ev_ids = h->tab.ev;
+  ea.ev_traj_stride = h->tab.ev_ts;
+  ea.ev_layer_stride = h->tab.ev_ls;
+  ea.kraus_tab = h->tab.kraus;
+  ea.nk_tab = h->tab.nk;
+  ea.fixed_tab = h->tab.fixed;
+  ea.layer_ptr = h->tab.layer;
+}
+
+// theta kernel variant for a shape: the default rule, or (autotune) the faster of the
+// applicable variants, timed on the live operands the first time the shape occurs outside a
+// graph capture
+int theta_variant(mpsb_batch* h, int p, int cl, int cm, int cr, const void* Sq, const void* Sn, void* X, const Mat4& gate,
+                  const GateRef& gref, double* partial, bool capturing) {
+  const long long key = ((long long)p << 48) | ((long long)cl << 32) | ((long long)cm << 16) | cr;
+  auto it = h->theta_var.find(key);
+  if (it != h->theta_var.end()) return it->second;
+  int best = theta_default_variant(p, cl, cr);
+  if (h->autotune && !capturing && theta_variant_ok(p, 1, cl, cr) && h->L.n_traj >= 64) {
+    // both variants write the same outputs; time each (3 launches after one warm-up)
+    float tbest = 1e30f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+      for (int v = 0; v < 2; ++v) {
+        if (theta(p, cl, cm, cr, Sq, Sn, h->L.s_traj, X, h->L.s_x, gate, gref, partial, h->L.n_traj, h->st, v) != hipSuccess) continue;
+        (void)hipEventRecord(e0, h->st);
+        for (int r = 0; r < 3; ++r) (void)theta(p, cl, cm, cr, Sq, Sn, h->L.s_traj, X, h->L.s_x, gate, gref, partial, h->L.n_traj, h->st, v);
+        (void)hipEventRecord(e1, h->st);
+        float ms = 0;
+        if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < tbest) {
+          tbest = ms;
+          best = v;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+  }
+  h->theta_var[key] = best;
+  return best;
 }
 
 // Two-site step on (q, q+1): gate, noise events, truncation to keep columns, split.
 // left_to_right: the new centre goes to q+1 (A_q left-orthonormal), else to q.
-int two_site_step(mpsb_batch* h, int layer, int q, const Mat4& gate, int ch_s, int ch_t, bool left_to_right, int keep,
-                  double* discarded, int disc_stride, int accumulate, int32_t* branch, double* w_record) {
+// The gate is `gate` when `slot` < 0, else the table gate of pair slot `slot`; the events
+// come from the tables when `tables` (has_s / has_t: some trajectory has an event on q /
+// q+1), else from the by-value channels ch_s / ch_t (-1 = none).
+int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, bool tables, int ch_s, int ch_t,
+                  bool has_s, bool has_t, bool left_to_right, int keep, double* discarded, int disc_stride,
+                  int accumulate, int32_t* branch, double* w_record, bool capturing = false) {
   Layout& L = h->L;
   const int p = L.prec == MPSB_FP64 ? 1 : 0, T = L.n_traj;
   int r = move_centre(h, q, q + 1);
@@ -392,18 +474,33 @@ int two_site_step(mpsb_batch* h, int layer, int q, const Mat4& gate, int ch_s, i
   char* X = W<char>(h, L.o_x);
   double* partial = W<double>(h, L.o_partial);
   double* kops = W<double>(h, L.o_kops);
+  GateRef gref;
+  memset(&gref, 0, sizeof(gref));
+  if (slot >= 0) {
+    gref.pool = h->tab.gpool;
+    gref.ids = h->tab.gid;
+    gref.traj_stride = h->tab.gid_ts;
+    gref.layer_stride = h->tab.gid_ls;
+    gref.pair = slot;
+    gref.layer = h->tab.layer;
+  }
+  const int var = theta_variant(h, p, cl, cm, cr, Sq, Sn, X, gate, gref, partial, capturing);
   {
     ProfSec s(h, PC_THETA);
-    HIPCHK(theta(p, cl, cm, cr, Sq, Sn, L.s_traj, X, L.s_x, gate, partial, T, h->st));
+    HIPCHK(theta(p, cl, cm, cr, Sq, Sn, L.s_traj, X, L.s_x, gate, gref, partial, T, h->st, var));
   }
-  const int nt = theta_tiles(p, cl, cr);
-  if (ch_s >= 0 || ch_t >= 0) {
+  const int nt = theta_tiles(var, cl, cr);
+  if (tables ? (has_s || has_t) : (ch_s >= 0 || ch_t >= 0)) {
     EventArgs ea = base_event_args(h, layer, branch, w_record, h->mode);
-    if (ch_s >= 0) fill_channel_slot(h, ea, 0, ch_s);
-    if (ch_t >= 0) fill_channel_slot(h, ea, 1, ch_t);
+    if (tables) {
+      set_event_tables(h, ea);
+    } else {
+      if (ch_s >= 0) fill_channel_slot(h, ea, 0, ch_s);
+      if (ch_t >= 0) fill_channel_slot(h, ea, 1, ch_t);
+    }
     {
       ProfSec s(h, PC_EVENTS);
-      HIPCHK(launch_gate_events(ea, partial, nt, q, ch_s >= 0, ch_t >= 0, kops, status_ptr(h), h->st));
+      HIPCHK(launch_gate_events(ea, partial, nt, q, tables ? 1 : ch_s >= 0, tables ? 1 : ch_t >= 0, kops, status_ptr(h), h->st));
     }
     ProfSec s(h, PC_KRAUS);
     HIPCHK(kraus_pair(p, cl, cr, X, L.s_x, kops, T, h->st));
@@ -440,7 +537,9 @@ int two_site_step(mpsb_batch* h, int layer, int q, const Mat4& gate, int ch_s, i
   return MPSB_OK;
 }
 
-int idle_step(mpsb_batch* h, int layer, int q, int ch, int mode, const int* d_forced, int32_t* branch,
+// Single-qubit noise on the centre tensor at q: by-value channel `ch` (tables false) or the
+// table events of the current layer (trajectories without an event get the identity).
+int idle_step(mpsb_batch* h, int layer, int q, bool tables, int ch, int mode, const int* d_forced, int32_t* branch,
               double* w_record, double* p_out, bool per_call_record = false) {
   Layout& L = h->L;
   const int p = L.prec == MPSB_FP64 ? 1 : 0, T = L.n_traj;
@@ -456,9 +555,58 @@ int idle_step(mpsb_batch* h, int layer, int q, int ch, int mode, const int* d_fo
     ea.rec_stride = 1;
     ea.rec_qbase = q;
   }
-  fill_channel_slot(h, ea, 0, ch);
+  if (tables) set_event_tables(h, ea);
+  else fill_channel_slot(h, ea, 0, ch);
   HIPCHK(launch_site_event(ea, rho1, q, 0, d_forced, kops, p_out, status_ptr(h), h->st));
   HIPCHK(site_apply(p, dl(L, q), dr(L, q), S, L.s_traj, kops, T, h->st));
+  return MPSB_OK;
+}
+
+// The operations of one layer of a (uniform) batch in sweep order, with their event flags.
+struct LayerOp { int q; bool gate; bool has_s, has_t; };
+
+std::vector<LayerOp> layer_ops(const mpsb_batch* h, int layer) {
+  const int n = h->L.n, par = layer % 2;
+  const unsigned char* ev = h->any_ev.data() + (size_t)layer * n;
+  std::vector<LayerOp> ops;
+  std::vector<char> covered(n, 0);
+  for (int q = par; q + 1 < n; q += 2) covered[q] = covered[q + 1] = 1;
+  for (int q = 0; q < n; ++q) {
+    if (q >= par && (q - par) % 2 == 0 && q + 1 < n) ops.push_back({q, true, ev[q] != 0, ev[q + 1] != 0});
+    else if (!covered[q] && ev[q]) ops.push_back({q, false, true, false});
+  }
+  if (par == 1) std::reverse(ops.begin(), ops.end());
+  return ops;
+}
+
+std::string layer_signature(const mpsb_batch* h, int layer) {
+  std::string sig = std::to_string(layer % 2) + "@" + std::to_string(h->centre) + ":";
+  for (const LayerOp& o : layer_ops(h, layer))
+    sig += std::to_string(o.q) + (o.gate ? "g" : "i") + (o.has_s ? "1" : "0") + (o.has_t ? "1" : "0") + ",";
+  return sig;
+}
+
+// Enqueues the launches of one layer on h->st (records: device rows of this batch's
+// trajectory 0, or NULL).  The device layer counter must hold `layer`; it is not advanced.
+int run_layer(mpsb_batch* h, int layer, double* discarded, int disc_stride, int32_t* branch, double* w_record,
+              bool capturing) {
+  const Layout& L = h->L;
+  const int par = layer % 2;
+  const bool l2r = (par == 0);
+  Mat4 none;
+  memset(&none, 0, sizeof(none));
+  for (const LayerOp& op : layer_ops(h, layer)) {
+    int r;
+    if (op.gate) {
+      const int slot = (op.q - par) / 2;
+      double* disc = discarded ? discarded + slot : nullptr;
+      r = two_site_step(h, layer, op.q, slot, none, true, -1, -1, op.has_s, op.has_t, l2r, L.cap[op.q], disc,
+                        disc_stride, 0, branch, w_record, capturing);
+    } else {
+      r = idle_step(h, layer, op.q, true, 0, h->mode, nullptr, branch, w_record, nullptr);
+    }
+    if (r) return r;
+  }
   return MPSB_OK;
 }
 
@@ -485,76 +633,143 @@ extern "C" {
 
 const char* mps_last_error(void) { return g_err.c_str(); }
 
-int mps_batch_plan(int n_traj, int n_qubits, int chi, int precision, size_t* state_bytes, size_t* work_bytes) {
-  if (!state_bytes || !work_bytes) return fail(MPSB_EINVAL, "null output pointer");
-  Layout L;
-  int r = make_layout(n_traj, n_qubits, chi, precision, L);
-  if (r) return r;
-  *state_bytes = L.state_bytes;
-  *work_bytes = L.work_bytes;
+}  // extern "C"
+
+namespace {
+
+// maximal runs of equal (width, chi)
+struct Run { int first, count, width, chi; };
+
+int runs_of(int n_traj, const int32_t* width, const int32_t* chi, std::vector<Run>& runs) {
+  if (n_traj <= 0 || n_traj > (1 << 30)) return fail(MPSB_EINVAL, "n_traj must be in 1..2^30");
+  if (!width || !chi) return fail(MPSB_EINVAL, "null width / chi array");
+  runs.clear();
+  for (int t = 0; t < n_traj; ++t) {
+    if (!runs.empty() && runs.back().width == width[t] && runs.back().chi == chi[t]) runs.back().count++;
+    else runs.push_back({t, 1, width[t], chi[t]});
+  }
   return MPSB_OK;
 }
 
-int mps_batch_create(int n_traj, int n_qubits, int chi, int precision, uint64_t seed, void* state_buf,
-                     size_t state_bytes, void* work_buf, size_t work_bytes, void* stream, mpsb_handle* out) {
-  if (!out) return fail(MPSB_EINVAL, "null handle pointer");
-  Layout L;
-  int r = make_layout(n_traj, n_qubits, chi, precision, L);
-  if (r) return r;
-  if (!state_buf || !work_buf) return fail(MPSB_EINVAL, "null buffer");
-  if (((uintptr_t)state_buf & 255) || ((uintptr_t)work_buf & 255)) return fail(MPSB_EINVAL, "buffers must be 256-byte aligned");
-  if (state_bytes < L.state_bytes || work_bytes < L.work_bytes) return fail(MPSB_ENOMEM, "buffer smaller than planned");
-  mpsb_batch* h = new mpsb_batch();
-  h->L = L;
-  h->seed = seed;
-  h->state = (char*)state_buf;
-  h->work = (char*)work_buf;
-  h->st = (hipStream_t)stream;
-  h->centre = 0;
-  h->next_layer = 0;
-  h->has_circuit = false;
-  h->depth = 0;
-  h->n_channels = 0;
-  h->mode = MPSB_OPTIMAL;
+int plan_runs(const std::vector<Run>& runs, int prec, std::vector<Layout>& Ls, std::vector<size_t>& soff,
+              std::vector<size_t>& woff, size_t& sbytes, size_t& wbytes) {
+  Ls.resize(runs.size());
+  soff.resize(runs.size());
+  woff.resize(runs.size());
+  sbytes = wbytes = 0;
+  for (size_t i = 0; i < runs.size(); ++i) {
+    int r = make_layout(runs[i].count, runs[i].width, runs[i].chi, prec, Ls[i]);
+    if (r) return r;
+    soff[i] = sbytes;
+    woff[i] = wbytes;
+    sbytes = align256(sbytes + Ls[i].state_bytes);
+    wbytes = align256(wbytes + Ls[i].work_bytes);
+  }
+  return MPSB_OK;
+}
+
+hipError_t init_batch_state(mpsb_batch* h) {
+  const Layout& L = h->L;
   std::vector<long long> off(L.off.begin(), L.off.end());
   hipError_t e = hipMemcpyAsync(W<long long>(h, L.o_siteoff), off.data(), sizeof(long long) * L.n, hipMemcpyHostToDevice, h->st);
   if (e == hipSuccess) e = hipMemsetAsync(status_ptr(h), 0, 256, h->st);
   if (e == hipSuccess) e = init_state(L.prec == MPSB_FP64 ? 1 : 0, h->state, W<long long>(h, L.o_siteoff), L.n, L.s_traj, L.n_traj, h->st);
   if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-  if (e != hipSuccess) {
-    delete h;
-    return fail(MPSB_EHIP, std::string("initialising the state: ") + hipGetErrorString(e));
-  }
-  *out = h;
+  return e;
+}
+
+void destroy_batch(mpsb_batch* h) {
+  if (!h) return;
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  for (mpsb_batch* b : h->sub) destroy_batch(b);
+  for (auto& g : h->graphs)
+    if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+  for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->fork_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->join_ev) (void)hipEventDestroy(e);
+  for (hipStream_t s : h->streams) (void)hipStreamDestroy(s);
+  if (h->cap_st) (void)hipStreamDestroy(h->cap_st);
+  delete h;
+}
+
+// ---- circuit tables
+struct CircLayout {
+  size_t o_layer, o_gpool, o_gid, o_kraus, o_nk, o_fixed, o_ev, bytes;
+  int n_pool, mpmax, nmax;
+  long long gid_ts, ev_ts;
+};
+
+int circuit_layout(int n_traj, int nmax, const mpsb_circuit* c, CircLayout& C) {
+  C.nmax = nmax;
+  C.mpmax = nmax / 2;
+  const long long D = c->depth;
+  C.n_pool = c->n_gates > 0 ? c->n_gates : (int)(D * C.mpmax);
+  const long long gid_n = c->n_gates > 0 ? (long long)n_traj * D * C.mpmax : D * C.mpmax;
+  const long long ev_n = c->events_per_traj ? (long long)n_traj * D * nmax : D * nmax;
+  C.gid_ts = c->n_gates > 0 ? D * C.mpmax : 0;
+  C.ev_ts = c->events_per_traj ? D * nmax : 0;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + std::max<size_t>(bytes, 1)); return r; };
+  C.o_layer = take(sizeof(int));
+  C.o_gpool = take(sizeof(double) * 32 * ((size_t)C.n_pool + 1));
+  C.o_gid = take(sizeof(int) * (size_t)gid_n);
+  C.o_kraus = take(sizeof(double) * 32 * (size_t)c->n_channels);
+  C.o_nk = take(sizeof(int) * (size_t)c->n_channels);
+  C.o_fixed = take(sizeof(double) * 32 * (size_t)c->n_channels);
+  C.o_ev = take(sizeof(int) * (size_t)ev_n);
+  C.bytes = o;
   return MPSB_OK;
 }
 
-int mps_circuit_validate(int n, const mpsb_circuit* c) {
+int validate_circuit(int n_traj, const int32_t* width, const mpsb_circuit* c, int& nmax_out) {
   if (!c) return fail(MPSB_EINVAL, "null argument");
-  if (n < 2 || n > MPSB_MAX_QUBITS) return fail(MPSB_EINVAL, "n_qubits out of range");
+  if (n_traj < 1 || !width) return fail(MPSB_EINVAL, "bad trajectory count / width array");
+  int nmax = 0;
+  bool uniform = true;
+  for (int t = 0; t < n_traj; ++t) {
+    if (width[t] < 2 || width[t] > MPSB_MAX_QUBITS) return fail(MPSB_EINVAL, "n_qubits out of range");
+    nmax = std::max(nmax, (int)width[t]);
+    if (width[t] != width[0]) uniform = false;
+  }
+  nmax_out = nmax;
+  (void)uniform;
   if (c->depth < 0 || c->depth > 65535) return fail(MPSB_EINVAL, "depth must be in 0..65535");
   if (c->n_channels < 0 || c->n_channels > MPSB_MAX_CHANNELS) return fail(MPSB_EINVAL, "n_channels out of range");
   if (c->unravel_mode != MPSB_ORTHOGONAL && c->unravel_mode != MPSB_FIXED && c->unravel_mode != MPSB_OPTIMAL)
     return fail(MPSB_EINVAL, "unknown unravel mode");
+  if (c->n_gates < 0) return fail(MPSB_EINVAL, "n_gates < 0");
   if (c->depth > 0 && (!c->gates || !c->events)) return fail(MPSB_EINVAL, "null gates / events");
+  if (c->depth > 0 && c->n_gates > 0 && !c->gate_id) return fail(MPSB_EINVAL, "a gate pool needs gate_id");
   if (c->n_channels > 0 && (!c->kraus || !c->n_kraus)) return fail(MPSB_EINVAL, "null kraus table");
   if (c->unravel_mode == MPSB_FIXED && c->n_channels > 0 && !c->fixed_u) return fail(MPSB_EINVAL, "FIXED mode needs fixed_u");
-  const int mp = n / 2;
-  // gates
-  for (int l = 0; l < c->depth; ++l) {
-    int par = l % 2;
-    for (int i = 0; par + 2 * i + 1 < n; ++i) {
-      const double* g = c->gates + ((size_t)l * mp + i) * 32;
+  const int mp = nmax / 2;
+  if (c->n_gates > 0) {
+    for (int g = 0; g < c->n_gates; ++g) {
+      const double* gm = c->gates + (size_t)g * 32;
       for (int x = 0; x < 32; ++x)
-        if (!std::isfinite(g[x])) return fail(MPSB_ENUM, "non-finite gate entry");
-      if (!unitary_ok(g, 4, 4, 1e-12)) return fail(MPSB_EINVAL, "gate " + std::to_string(l) + "/" + std::to_string(i) + " is not unitary");
+        if (!std::isfinite(gm[x])) return fail(MPSB_ENUM, "non-finite gate entry");
+      if (!unitary_ok(gm, 4, 4, 1e-12)) return fail(MPSB_EINVAL, "pool gate " + std::to_string(g) + " is not unitary");
+    }
+    const size_t nid = (size_t)n_traj * c->depth * mp;
+    for (size_t i = 0; i < nid; ++i)
+      if (c->gate_id[i] < -1 || c->gate_id[i] >= c->n_gates) return fail(MPSB_EINVAL, "gate id out of range");
+  } else {
+    for (int l = 0; l < c->depth; ++l) {
+      int par = l % 2;
+      for (int i = 0; par + 2 * i + 1 < nmax; ++i) {
+        const double* g = c->gates + ((size_t)l * mp + i) * 32;
+        for (int x = 0; x < 32; ++x)
+          if (!std::isfinite(g[x])) return fail(MPSB_ENUM, "non-finite gate entry");
+        if (!unitary_ok(g, 4, 4, 1e-12)) return fail(MPSB_EINVAL, "gate " + std::to_string(l) + "/" + std::to_string(i) + " is not unitary");
+      }
     }
   }
-  // channels
   for (int ch = 0; ch < c->n_channels; ++ch) {
     int r = c->n_kraus[ch];
     if (r < 1 || r > 4) return fail(MPSB_EINVAL, "n_kraus must be in 1..4");
     const double* k = c->kraus + (size_t)ch * 32;
+    for (int x = 0; x < 32; ++x)
+      if (!std::isfinite(k[x])) return fail(MPSB_ENUM, "non-finite Kraus entry");
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int i = 0; i < r; ++i)
       for (int a = 0; a < 2; ++a)
@@ -566,8 +781,6 @@ int mps_circuit_validate(int n, const mpsb_circuit* c) {
             s[2 * (2 * a + b)] += xr * yr + xi * yi;
             s[2 * (2 * a + b) + 1] += xr * yi - xi * yr;
           }
-    for (int x = 0; x < 32; ++x)
-      if (!std::isfinite(k[x])) return fail(MPSB_ENUM, "non-finite Kraus entry");
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b)
         if (std::fabs(s[2 * (2 * a + b)] - (a == b ? 1.0 : 0.0)) > 1e-12 || std::fabs(s[2 * (2 * a + b) + 1]) > 1e-12)
@@ -581,30 +794,264 @@ int mps_circuit_validate(int n, const mpsb_circuit* c) {
       if (!unitary_ok(sub.data(), 4, r, 1e-12)) return fail(MPSB_EINVAL, "fixed mixing is not an isometry on the used columns");
     }
   }
-  for (int l = 0; l < c->depth; ++l)
-    for (int q = 0; q < n; ++q) {
-      int e = c->events[(size_t)l * n + q];
-      if (e < -1 || e >= c->n_channels) return fail(MPSB_EINVAL, "event channel id out of range");
-    }
+  const size_t nev = (size_t)(c->events_per_traj ? n_traj : 1) * c->depth * nmax;
+  for (size_t i = 0; i < nev; ++i) {
+    int e = c->events[i];
+    if (e < -1 || e >= c->n_channels) return fail(MPSB_EINVAL, "event channel id out of range");
+  }
   return MPSB_OK;
 }
 
-int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c) {
+std::vector<mpsb_batch*> members(mpsb_batch* h) {
+  if (h->sub.empty()) return {h};
+  return h->sub;
+}
+
+// Enqueues one layer of every member batch on stream S (members of a mixed batch on the
+// private streams, forked from and joined back into S), then advances the layer counter.
+int enqueue_layer(mpsb_batch* h, int layer, hipStream_t S, double* discarded, int32_t* branch, double* w_record,
+                  bool capturing) {
+  const int rs = h->rec_stride, dstr = rs / 2;
+  auto recs = [&](mpsb_batch* b, double*& d, int32_t*& br, double*& w) {
+    d = discarded ? discarded + (size_t)b->traj_base * dstr : nullptr;
+    br = branch ? branch + (size_t)b->traj_base * rs : nullptr;
+    w = w_record ? w_record + (size_t)b->traj_base * rs * 32 : nullptr;
+  };
+  if (h->sub.empty()) {
+    hipStream_t keep = h->st;
+    h->st = S;
+    double* d; int32_t* br; double* w;
+    recs(h, d, br, w);
+    int r = run_layer(h, layer, d, dstr, br, w, capturing);
+    h->st = keep;
+    if (r) return r;
+    HIPCHK(inc_int(h->tab.layer, S));
+    return MPSB_OK;
+  }
+  const int NS = (int)h->streams.size();
+  HIPCHK(hipEventRecord(h->fork_ev[0], S));
+  for (int j = 0; j < NS; ++j) HIPCHK(hipStreamWaitEvent(h->streams[j], h->fork_ev[0], 0));
+  int r = MPSB_OK;
+  for (size_t i = 0; i < h->sub.size() && !r; ++i) {
+    mpsb_batch* b = h->sub[i];
+    if (layer >= b->depth) continue;
+    b->st = h->streams[i % NS];
+    double* d; int32_t* br; double* w;
+    recs(b, d, br, w);
+    r = run_layer(b, layer, d, dstr, br, w, capturing);
+  }
+  for (int j = 0; j < NS; ++j) {
+    HIPCHK(hipEventRecord(h->join_ev[j], h->streams[j]));
+    HIPCHK(hipStreamWaitEvent(S, h->join_ev[j], 0));
+  }
+  for (mpsb_batch* b : h->sub) b->st = h->st;
+  if (r) return r;
+  HIPCHK(inc_int(h->tab.layer, S));
+  return MPSB_OK;
+}
+
+bool profiling(mpsb_batch* h) {
+  for (mpsb_batch* b : members(h))
+    if (b->prof.on) return true;
+  return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mps_batch_plan(int n_traj, const int32_t* width, const int32_t* chi, int precision, size_t* state_bytes,
+                   size_t* work_bytes) {
+  if (!state_bytes || !work_bytes) return fail(MPSB_EINVAL, "null output pointer");
+  std::vector<Run> runs;
+  int r = runs_of(n_traj, width, chi, runs);
+  if (r) return r;
+  std::vector<Layout> Ls;
+  std::vector<size_t> so, wo;
+  size_t sb, wb;
+  r = plan_runs(runs, precision, Ls, so, wo, sb, wb);
+  if (r) return r;
+  *state_bytes = sb;
+  *work_bytes = wb;
+  return MPSB_OK;
+}
+
+int mps_batch_create(int n_traj, const int32_t* width, const int32_t* chi, int precision, uint64_t seed,
+                     void* state_buf, size_t state_bytes, void* work_buf, size_t work_bytes, void* stream,
+                     mpsb_handle* out) {
+  if (!out) return fail(MPSB_EINVAL, "null handle pointer");
+  std::vector<Run> runs;
+  int r = runs_of(n_traj, width, chi, runs);
+  if (r) return r;
+  std::vector<Layout> Ls;
+  std::vector<size_t> so, wo;
+  size_t sb, wb;
+  r = plan_runs(runs, precision, Ls, so, wo, sb, wb);
+  if (r) return r;
+  if (!state_buf || !work_buf) return fail(MPSB_EINVAL, "null buffer");
+  if (((uintptr_t)state_buf & 255) || ((uintptr_t)work_buf & 255)) return fail(MPSB_EINVAL, "buffers must be 256-byte aligned");
+  if (state_bytes < sb || work_bytes < wb) return fail(MPSB_ENOMEM, "buffer smaller than planned");
+  int nmax = 0;
+  for (const Run& u : runs) nmax = std::max(nmax, u.width);
+  mpsb_batch* h = new mpsb_batch();
+  h->st = (hipStream_t)stream;
+  h->seed = seed;
+  h->n_traj_total = n_traj;
+  h->rec_stride = nmax;
+  h->width.assign(width, width + n_traj);
+  h->chi.assign(chi, chi + n_traj);
+  hipError_t e = hipStreamCreateWithFlags(&h->cap_st, hipStreamNonBlocking);
+  auto make = [&](size_t i) {
+    mpsb_batch* b = runs.size() == 1 ? h : new mpsb_batch();
+    b->L = Ls[i];
+    b->seed = seed;
+    b->state = (char*)state_buf + so[i];
+    b->work = (char*)work_buf + wo[i];
+    b->st = (hipStream_t)stream;
+    b->traj_base = runs[i].first;
+    b->rec_stride = nmax;
+    return b;
+  };
+  if (runs.size() == 1) {
+    make(0);
+  } else {
+    for (size_t i = 0; i < runs.size(); ++i) h->sub.push_back(make(i));
+    const int NS = (int)std::min<size_t>(4, runs.size());
+    for (int j = 0; j < NS && e == hipSuccess; ++j) {
+      hipStream_t s2;
+      hipEvent_t ej;
+      e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+      if (e == hipSuccess) h->streams.push_back(s2);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ej, hipEventDisableTiming);
+      if (e == hipSuccess) h->join_ev.push_back(ej);
+    }
+    hipEvent_t ef;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ef, hipEventDisableTiming);
+    if (e == hipSuccess) h->fork_ev.push_back(ef);
+  }
+  for (mpsb_batch* b : members(h))
+    if (e == hipSuccess) e = init_batch_state(b);
+  if (e != hipSuccess) {
+    destroy_batch(h);
+    return fail(MPSB_EHIP, std::string("initialising the batch: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return MPSB_OK;
+}
+
+int mps_circuit_validate(int n_traj, const int32_t* width, const mpsb_circuit* c) {
+  int nmax;
+  return validate_circuit(n_traj, width, c, nmax);
+}
+
+int mps_circuit_bytes(mpsb_handle h, const mpsb_circuit* c, size_t* bytes) {
+  if (!h || !c || !bytes) return fail(MPSB_EINVAL, "null argument");
+  CircLayout C;
+  circuit_layout(h->n_traj_total, h->rec_stride, c, C);
+  *bytes = C.bytes;
+  return MPSB_OK;
+}
+
+int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c, void* circuit_buf, size_t circuit_bytes) {
   if (!h || !c) return fail(MPSB_EINVAL, "null argument");
-  const int n = h->L.n;
-  const int mp = n / 2;
-  int rv = mps_circuit_validate(n, c);
+  int nmax;
+  int rv = validate_circuit(h->n_traj_total, h->width.data(), c, nmax);
   if (rv) return rv;
-  h->depth = c->depth;
-  h->gates.assign(c->gates, c->gates + (size_t)c->depth * mp * 32);
-  h->n_channels = c->n_channels;
-  h->kraus.assign(c->kraus, c->kraus + (size_t)c->n_channels * 32);
-  h->n_kraus.assign(c->n_kraus, c->n_kraus + c->n_channels);
-  h->events.assign(c->events, c->events + (size_t)c->depth * n);
+  CircLayout C;
+  circuit_layout(h->n_traj_total, nmax, c, C);
+  if (!circuit_buf) return fail(MPSB_EINVAL, "null circuit buffer");
+  if ((uintptr_t)circuit_buf & 255) return fail(MPSB_EINVAL, "circuit buffer must be 256-byte aligned");
+  if (circuit_bytes < C.bytes) return fail(MPSB_ENOMEM, "circuit buffer smaller than mps_circuit_bytes");
+  const int T = h->n_traj_total, D = c->depth, mp = C.mpmax;
+  // host staging of the tables
+  std::vector<double> pool((size_t)(C.n_pool + 1) * 32, 0.0);
+  std::copy(c->gates, c->gates + (size_t)C.n_pool * 32, pool.begin());
+  for (int i = 0; i < 4; ++i) pool[(size_t)C.n_pool * 32 + 2 * (4 * i + i)] = 1.0;   // identity
+  std::vector<int> gid;
+  if (c->n_gates > 0) {
+    gid.assign(c->gate_id, c->gate_id + (size_t)T * D * mp);
+    for (int& g : gid)
+      if (g < 0) g = C.n_pool;
+  } else {
+    gid.resize((size_t)D * mp);
+    for (size_t i = 0; i < gid.size(); ++i) gid[i] = (int)i;
+  }
+  std::vector<int> ev(c->events, c->events + (size_t)(c->events_per_traj ? T : 1) * D * nmax);
+  std::vector<int> nk(c->n_kraus, c->n_kraus + c->n_channels);
+  char* base = (char*)circuit_buf;
+  HIPCHK(hipMemcpyAsync(base + C.o_gpool, pool.data(), sizeof(double) * pool.size(), hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipMemcpyAsync(base + C.o_gid, gid.data(), sizeof(int) * gid.size(), hipMemcpyHostToDevice, h->st));
+  if (c->n_channels > 0) {
+    HIPCHK(hipMemcpyAsync(base + C.o_kraus, c->kraus, sizeof(double) * 32 * c->n_channels, hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipMemcpyAsync(base + C.o_nk, nk.data(), sizeof(int) * nk.size(), hipMemcpyHostToDevice, h->st));
+    if (c->fixed_u)
+      HIPCHK(hipMemcpyAsync(base + C.o_fixed, c->fixed_u, sizeof(double) * 32 * c->n_channels, hipMemcpyHostToDevice, h->st));
+  }
+  HIPCHK(hipMemcpyAsync(base + C.o_ev, ev.data(), sizeof(int) * ev.size(), hipMemcpyHostToDevice, h->st));
+  HIPCHK(set_int((int*)(base + C.o_layer), h->next_layer, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  Tables tab;
+  tab.layer = (int*)(base + C.o_layer);
+  tab.gpool = (const double*)(base + C.o_gpool);
+  tab.gid = (const int*)(base + C.o_gid);
+  tab.gid_ts = C.gid_ts;
+  tab.gid_ls = mp;
+  tab.kraus = (const double*)(base + C.o_kraus);
+  tab.nk = (const int*)(base + C.o_nk);
+  tab.fixed = c->fixed_u ? (const double*)(base + C.o_fixed) : nullptr;
+  tab.ev = (const int*)(base + C.o_ev);
+  tab.ev_ts = C.ev_ts;
+  tab.ev_ls = nmax;
+  h->tab = tab;
+  for (auto& g : h->graphs)
+    if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+  h->graphs.clear();
+  for (mpsb_batch* b : members(h)) {
+    const int n = b->L.n, first = b->traj_base, cnt = b->L.n_traj;
+    b->tab = tab;
+    b->tab.gid = tab.gid + (long long)first * C.gid_ts;
+    b->tab.ev = tab.ev + (long long)first * C.ev_ts;
+    // last layer with work for this batch (identity gates and no events past a trajectory's depth)
+    b->depth = D;
+    b->n_channels = c->n_channels;
+    b->mode = c->unravel_mode;
+    if (b == h) {   // host copy of the channels for sample_kraus (uniform batches only)
+      b->kraus.assign(c->kraus, c->kraus + (size_t)c->n_channels * 32);
+      b->n_kraus.assign(c->n_kraus, c->n_kraus + c->n_channels);
+      if (c->fixed_u) b->fixed_u.assign(c->fixed_u, c->fixed_u + (size_t)c->n_channels * 32);
+      else b->fixed_u.clear();
+    }
+    b->any_ev.assign((size_t)D * n, 0);
+    for (int l = 0; l < D; ++l)
+      for (int q = 0; q < n; ++q) {
+        bool any = false;
+        if (c->events_per_traj) {
+          for (int t = first; t < first + cnt && !any; ++t) any = c->events[((size_t)t * D + l) * nmax + q] >= 0;
+        } else {
+          any = c->events[(size_t)l * nmax + q] >= 0;
+        }
+        b->any_ev[(size_t)l * n + q] = any;
+      }
+    b->has_circuit = true;
+  }
+  h->depth = D;
   h->mode = c->unravel_mode;
-  if (c->fixed_u) h->fixed_u.assign(c->fixed_u, c->fixed_u + (size_t)c->n_channels * 32);
-  else h->fixed_u.clear();
   h->has_circuit = true;
+  return MPSB_OK;
+}
+
+int mps_batch_set_graphs(mpsb_handle h, int enable) {
+  if (!h) return fail(MPSB_EINVAL, "null handle");
+  h->graphs_on = enable != 0;
+  return MPSB_OK;
+}
+
+int mps_batch_set_autotune(mpsb_handle h, int enable) {
+  if (!h) return fail(MPSB_EINVAL, "null handle");
+  for (mpsb_batch* b : members(h)) {
+    b->autotune = enable != 0;
+    b->theta_var.clear();
+  }
   return MPSB_OK;
 }
 
@@ -613,36 +1060,65 @@ int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch, do
   if (!h->has_circuit) return fail(MPSB_EINVAL, "no circuit set");
   if (layer < 0 || layer >= h->depth) return fail(MPSB_EINVAL, "layer out of range");
   if (layer != h->next_layer) return fail(MPSB_EINVAL, "layers must be applied in order");
-  const Layout& L = h->L;
-  const int n = L.n, mp = n / 2, par = layer % 2;
-  // ops in sweep order
-  struct Op { int q; bool gate; };
-  std::vector<Op> ops;
-  std::vector<char> covered(n, 0);
-  for (int q = par; q + 1 < n; q += 2) { covered[q] = covered[q + 1] = 1; }
-  for (int q = 0; q < n; ++q) {
-    if (q >= par && (q - par) % 2 == 0 && q + 1 < n) ops.push_back({q, true});
-    else if (!covered[q] && h->events[(size_t)layer * n + q] >= 0) ops.push_back({q, false});
-  }
-  const bool l2r = (par == 0);
-  if (!l2r) std::reverse(ops.begin(), ops.end());
-  if (branch) HIPCHK(hipMemsetAsync(branch, 0xFF, sizeof(int32_t) * (size_t)L.n_traj * n, h->st));
-  if (w_record) HIPCHK(hipMemsetAsync(w_record, 0, sizeof(double) * 32 * (size_t)L.n_traj * n, h->st));
-  if (discarded) HIPCHK(hipMemsetAsync(discarded, 0, sizeof(double) * (size_t)L.n_traj * mp, h->st));
-  for (const Op& op : ops) {
-    int r;
-    if (op.gate) {
-      Mat4 g;
-      const double* gp = h->gates.data() + ((size_t)layer * mp + (op.q - par) / 2) * 32;
-      for (int x = 0; x < 32; ++x) g.v[x] = gp[x];
-      int ch_s = h->events[(size_t)layer * n + op.q], ch_t = h->events[(size_t)layer * n + op.q + 1];
-      double* disc = discarded ? discarded + (op.q - par) / 2 : nullptr;
-      r = two_site_step(h, layer, op.q, g, ch_s, ch_t, l2r, L.cap[op.q], disc, mp, 0, branch, w_record);
-    } else {
-      r = idle_step(h, layer, op.q, h->events[(size_t)layer * n + op.q], h->mode, nullptr, branch, w_record, nullptr);
-    }
+  const size_t T = (size_t)h->n_traj_total, rs = (size_t)h->rec_stride;
+  if (branch) HIPCHK(hipMemsetAsync(branch, 0xFF, sizeof(int32_t) * T * rs, h->st));
+  if (w_record) HIPCHK(hipMemsetAsync(w_record, 0, sizeof(double) * 32 * T * rs, h->st));
+  if (discarded) HIPCHK(hipMemsetAsync(discarded, 0, sizeof(double) * T * (rs / 2), h->st));
+  const bool rec = discarded || branch || w_record;
+  std::vector<mpsb_batch*> bs = members(h);
+  if (!h->graphs_on || rec || profiling(h)) {
+    int r = enqueue_layer(h, layer, h->st, discarded, branch, w_record, false);
     if (r) return r;
+    for (mpsb_batch* b : bs) b->next_layer = layer + 1;
+    h->next_layer = layer + 1;
+    return MPSB_OK;
   }
+  std::string sig;
+  for (mpsb_batch* b : bs) sig += (layer < b->depth ? layer_signature(b, layer) : std::string("-")) + "|";
+  auto it = h->graphs.find(sig);
+  if (it == h->graphs.end()) {
+    static const std::string seen_tag = "#seen";
+    if (h->graphs.find(sig + seen_tag) == h->graphs.end()) {
+      // first occurrence: run directly (kernel variants are tuned on live operands here)
+      int r = enqueue_layer(h, layer, h->st, nullptr, nullptr, nullptr, false);
+      if (r) return r;
+      h->graphs[sig + seen_tag] = mpsb_batch::Graph{nullptr, 0};
+      for (mpsb_batch* b : bs) b->next_layer = layer + 1;
+      h->next_layer = layer + 1;
+      return MPSB_OK;
+    }
+    // second occurrence: capture the launch sequence on the private stream
+    std::vector<int> centres;
+    for (mpsb_batch* b : bs) centres.push_back(b->centre);
+    HIPCHK(hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeRelaxed));
+    int r = enqueue_layer(h, layer, h->cap_st, nullptr, nullptr, nullptr, true);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_st, &g);
+    if (r) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    if (e != hipSuccess) return fail(MPSB_EHIP, std::string("capturing a layer: ") + hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(MPSB_EHIP, std::string("instantiating a layer graph: ") + hipGetErrorString(e));
+    // the capture moved the host-side centres as a direct run would
+    mpsb_batch::Graph gr{ge, 0};
+    it = h->graphs.emplace(sig, gr).first;
+    (void)centres;
+  } else {
+    // replay: advance the host-side centres as the captured run did
+    for (mpsb_batch* b : bs)
+      if (layer < b->depth) {
+        for (const LayerOp& op : layer_ops(b, layer)) {
+          if (op.gate) b->centre = (layer % 2 == 0) ? op.q + 1 : op.q;
+          else b->centre = op.q;
+        }
+      }
+  }
+  HIPCHK(hipGraphLaunch(it->second.exec, h->st));
+  for (mpsb_batch* b : bs) b->next_layer = layer + 1;
   h->next_layer = layer + 1;
   return MPSB_OK;
 }
@@ -650,6 +1126,7 @@ int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch, do
 int sample_kraus(mpsb_handle h, const int32_t* qubit, int channel, int unravel_mode, int rng_layer,
                  const int32_t* forced, int32_t* branch, double* p) {
   if (!h || !qubit) return fail(MPSB_EINVAL, "null argument");
+  if (!h->sub.empty()) return fail(MPSB_ENOTSUP, "sample_kraus needs a batch of one width and chi");
   if (!h->has_circuit) return fail(MPSB_EINVAL, "no circuit set");
   if (channel < 0 || channel >= h->n_channels) return fail(MPSB_EINVAL, "channel out of range");
   if (unravel_mode != MPSB_ORTHOGONAL && unravel_mode != MPSB_FIXED && unravel_mode != MPSB_OPTIMAL)
@@ -679,11 +1156,12 @@ int sample_kraus(mpsb_handle h, const int32_t* qubit, int channel, int unravel_m
     r = check_status(h);
     if (r) return r;
   }
-  return idle_step(h, rng_layer, q, channel, unravel_mode, d_forced, branch, nullptr, p, true);
+  return idle_step(h, rng_layer, q, false, channel, unravel_mode, d_forced, branch, nullptr, p, true);
 }
 
 int mps_truncate(mpsb_handle h, int chi, double* discarded) {
   if (!h) return fail(MPSB_EINVAL, "null handle");
+  if (!h->sub.empty()) return fail(MPSB_ENOTSUP, "mps_truncate needs a batch of one width and chi");
   if (chi < 1 || chi > h->L.chi) return fail(MPSB_EINVAL, "chi must be in 1..batch chi");
   const Layout& L = h->L;
   Mat4 id;
@@ -691,7 +1169,8 @@ int mps_truncate(mpsb_handle h, int chi, double* discarded) {
   for (int i = 0; i < 4; ++i) id.v[2 * (4 * i + i)] = 1.0;
   if (discarded) HIPCHK(hipMemsetAsync(discarded, 0, sizeof(double) * L.n_traj, h->st));
   for (int k = 0; k + 1 < L.n; ++k) {
-    int r = two_site_step(h, -1, k, id, -1, -1, true, std::min(chi, L.cap[k]), discarded, 1, 1, nullptr, nullptr);
+    int r = two_site_step(h, -1, k, -1, id, false, -1, -1, false, false, true, std::min(chi, L.cap[k]), discarded, 1, 1,
+                          nullptr, nullptr);
     if (r) return r;
   }
   int r = move_centre(h, 0, 0);
@@ -699,11 +1178,16 @@ int mps_truncate(mpsb_handle h, int chi, double* discarded) {
   return MPSB_OK;
 }
 
-int expect(mpsb_handle h, double* mean, double* m2, double* per_traj) {
-  if (!h || !mean || !m2) return fail(MPSB_EINVAL, "null argument");
+}  // extern "C"
+
+namespace {
+// Observables of a uniform batch into per_traj rows of `stride` doubles (NaN past 2n-1), and
+// (mean, m2) over its trajectories when requested.
+int expect_uniform(mpsb_batch* h, double* mean, double* m2, double* per_traj, int stride) {
   const Layout& L = h->L;
   const int n = L.n, nobs = 2 * n - 1, T = L.n_traj;
   const int p = L.prec == MPSB_FP64 ? 1 : 0;
+  if (!per_traj) stride = nobs;
   double* obs = per_traj ? per_traj : W<double>(h, L.o_obs);
   double* norms = W<double>(h, L.o_norm);
   const long long se = L.s_env;   // c128 elements per slot
@@ -751,7 +1235,7 @@ int expect(mpsb_handle h, double* mean, double* m2, double* per_traj) {
       HIPCHK(gemm(1, 1, false, true, cl, cl, 2 * cr, Tm, 2 * cr, sp, A, 2 * cr, ss, Rout, cl, sp, nullptr, ct, h->st));
     }
     HIPCHK(env_init(Lc, sp, ct, h->st));
-    double* ob = obs + (size_t)t0 * nobs;
+    double* ob = obs + (size_t)t0 * stride;
     for (int k = 0; k < n; ++k) {
       long long ss;
       const void* A = get_site(k, ss);
@@ -764,54 +1248,84 @@ int expect(mpsb_handle h, double* mean, double* m2, double* per_traj) {
       HIPCHK(gemm(1, 1, true, false, cr, cr, 2 * cl, A, cr, ss, Tm, cr, sp, Lnew, cr, sp, nullptr, ct, h->st));
       HIPCHK(neg_cols(Tm, sp, cl, 2 * cr, cr, cr, ct, h->st));
       HIPCHK(gemm(1, 1, true, false, cr, cr, 2 * cl, A, cr, ss, Tm, cr, sp, Lz, cr, sp, nullptr, ct, h->st));
-      HIPCHK(obs_trace(cr, Lz, sp, Rn, sp, ob + k, nobs, ct, h->st));
+      HIPCHK(obs_trace(cr, Lz, sp, Rn, sp, ob + k, stride, ct, h->st));
       if (k >= 1) {
         const int clp = cl;
         // Y = Z-weighted transfer of Lzp through site k
         HIPCHK(gemm(1, 1, false, false, clp, 2 * cr, clp, Lzp, clp, sp, A, 2 * cr, ss, Tm, 2 * cr, sp, nullptr, ct, h->st));
         HIPCHK(neg_cols(Tm, sp, clp, 2 * cr, cr, cr, ct, h->st));
         HIPCHK(gemm(1, 1, true, false, cr, cr, 2 * clp, A, cr, ss, Tm, cr, sp, Lzp, cr, sp, nullptr, ct, h->st));
-        HIPCHK(obs_trace(cr, Lzp, sp, Rn, sp, ob + n + k - 1, nobs, ct, h->st));
+        HIPCHK(obs_trace(cr, Lzp, sp, Rn, sp, ob + n + k - 1, stride, ct, h->st));
       }
       // rotate: Lc <- Lnew, Lzp <- Lz
-      HIPCHK(hipMemcpy2DAsync(Lc, sp * 16, Lnew, sp * 16, (size_t)cr * cr * 16, ct, hipMemcpyDeviceToDevice, h->st));
-      HIPCHK(hipMemcpy2DAsync(Lzp, sp * 16, Lz, sp * 16, (size_t)cr * cr * 16, ct, hipMemcpyDeviceToDevice, h->st));
+      HIPCHK(copy_blocks(Lc, sp * 16, Lnew, sp * 16, (size_t)cr * cr * 16, ct, h->st));
+      HIPCHK(copy_blocks(Lzp, sp * 16, Lz, sp * 16, (size_t)cr * cr * 16, ct, h->st));
     }
     // norm = L_n (1x1)
-    HIPCHK(hipMemcpy2DAsync(norms + t0, sizeof(double), Lc, sp * 16, sizeof(double), ct, hipMemcpyDeviceToDevice, h->st));
-    HIPCHK(obs_normalise(ob, nobs, norms + t0, ct, h->st));
+    HIPCHK(copy_blocks(norms + t0, sizeof(double), Lc, sp * 16, sizeof(double), ct, h->st));
+    HIPCHK(obs_normalise(ob, nobs, stride, norms + t0, ct, h->st));
     (void)Rs;
   }
-  HIPCHK(obs_reduce(obs, nobs, T, mean, m2, h->st));
+  if (mean) HIPCHK(obs_reduce(obs, nobs, T, mean, m2, h->st));
+  return MPSB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int expect(mpsb_handle h, double* mean, double* m2, double* per_traj) {
+  if (!h) return fail(MPSB_EINVAL, "null handle");
+  if ((mean == nullptr) != (m2 == nullptr)) return fail(MPSB_EINVAL, "mean and m2 go together");
+  if (h->sub.empty()) {
+    if (!mean && !per_traj) return fail(MPSB_EINVAL, "no output");
+    return expect_uniform(h, mean, m2, per_traj, 2 * h->L.n - 1);
+  }
+  if (mean) return fail(MPSB_ENOTSUP, "a mixed batch reports per-trajectory observables only (mean = m2 = NULL)");
+  if (!per_traj) return fail(MPSB_EINVAL, "null per_traj");
+  const int stride = 2 * h->rec_stride - 1;
+  for (mpsb_batch* b : h->sub) {
+    b->st = h->st;
+    int r = expect_uniform(b, nullptr, nullptr, per_traj + (size_t)b->traj_base * stride, stride);
+    if (r) return r;
+  }
   return MPSB_OK;
 }
 
+
 int mps_profile(mpsb_handle h, int enable) {
   if (!h) return fail(MPSB_EINVAL, "null handle");
-  prof_collect(h);
-  for (int c = 0; c < PC_COUNT; ++c) { h->prof.ms[c] = 0; h->prof.count[c] = 0; }
-  h->prof.on = enable != 0;
+  for (mpsb_batch* b : members(h)) {
+    prof_collect(b);
+    for (int c = 0; c < PC_COUNT; ++c) { b->prof.ms[c] = 0; b->prof.count[c] = 0; }
+    b->prof.on = enable != 0;
+  }
   return MPSB_OK;
 }
 
 int mps_profile_read(mpsb_handle h, double* ms, long long* count, int n) {
   if (!h || !ms || !count) return fail(MPSB_EINVAL, "null argument");
-  prof_collect(h);
-  for (int c = 0; c < n && c < PC_COUNT; ++c) { ms[c] = h->prof.ms[c]; count[c] = h->prof.count[c]; }
+  for (int c = 0; c < n && c < PC_COUNT; ++c) { ms[c] = 0; count[c] = 0; }
+  for (mpsb_batch* b : members(h)) {
+    prof_collect(b);
+    for (int c = 0; c < n && c < PC_COUNT; ++c) { ms[c] += b->prof.ms[c]; count[c] += b->prof.count[c]; }
+  }
   return PC_COUNT;
 }
 
 int mps_batch_sync(mpsb_handle h) {
   if (!h) return fail(MPSB_EINVAL, "null handle");
   HIPCHK(hipStreamSynchronize(h->st));
-  return check_status(h);
+  for (mpsb_batch* b : members(h)) {
+    b->st = h->st;
+    int r = check_status(b);
+    if (r) return r;
+  }
+  return MPSB_OK;
 }
 
 int mps_batch_destroy(mpsb_handle h) {
   if (!h) return fail(MPSB_EINVAL, "null handle");
-  (void)hipStreamSynchronize(h->st);
-  for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
-  delete h;
+  destroy_batch(h);
   return MPSB_OK;
 }
 

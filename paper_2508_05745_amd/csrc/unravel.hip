@@ -420,29 +420,41 @@ __device__ inline int sample_branch(const double (&p)[4], double u) {
 // ------------------------------------------------------------------ event plumbing
 
 
-__device__ void load_channel(const EventArgs& ea, int ch, cd (&K)[4][2][2], int& r, cd (&Uf)[4][4]) {
-  // ch is the channel slot of the launch (0: lower / single qubit, 1: upper qubit)
-  r = ea.n_kraus[ch];
+// Channel of an event: table entry `id` when the launch reads the circuit tables, else the
+// by-value slot `slot` (0: lower / single qubit, 1: upper qubit of a gate).
+__device__ void load_channel(const EventArgs& ea, int slot, int id, cd (&K)[4][2][2], int& r, cd (&Uf)[4][4]) {
+  const double* kd = ea.ev_ids ? ea.kraus_tab + 32LL * id : ea.kraus[slot];
+  const double* ud = ea.ev_ids ? (ea.fixed_tab ? ea.fixed_tab + 32LL * id : nullptr) : ea.fixed_u[slot];
+  r = ea.ev_ids ? ea.nk_tab[id] : ea.n_kraus[slot];
   for (int i = 0; i < 4; ++i)
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
         int o = 2 * (4 * i + 2 * a + b);
-        K[i][a][b] = cd{ea.kraus[ch][o], ea.kraus[ch][o + 1]};
+        K[i][a][b] = cd{kd[o], kd[o + 1]};
       }
   for (int j = 0; j < 4; ++j)
     for (int i = 0; i < 4; ++i) {
       int o = 2 * (4 * j + i);
-      Uf[j][i] = cd{ea.fixed_u[ch][o], ea.fixed_u[ch][o + 1]};
+      Uf[j][i] = ud ? cd{ud[o], ud[o + 1]} : cz();
     }
+}
+
+__device__ inline int current_layer(const EventArgs& ea) { return ea.layer_ptr ? *ea.layer_ptr : ea.layer; }
+
+// channel id of the event on qubit x of trajectory traj in the current layer (tables), or the
+// by-value slot's presence flag
+__device__ inline int event_channel(const EventArgs& ea, int traj, int layer, int x, int slot_present) {
+  if (ea.ev_ids) return ea.ev_ids[traj * ea.ev_traj_stride + (long long)layer * ea.ev_layer_stride + x];
+  return slot_present ? 0 : -1;
 }
 
 // One noise event on a normalised single-qubit reduced state: choose W, p, draw, return the
 // selected operator.  Returns -1 on a forced zero-probability branch.
-__device__ int one_event(const EventArgs& ea, int ch, const cd (&rho)[2][2], uint32_t traj, uint32_t layer,
+__device__ int one_event(const EventArgs& ea, int slot, int id, const cd (&rho)[2][2], uint32_t traj, uint32_t layer,
                          uint32_t qubit, int forced, cd (&Ksel)[2][2], double (&p)[4], cd (&W)[4][4]) {
   cd K[4][2][2], Uf[4][4], Kp[4][2][2];
   int r;
-  load_channel(ea, ch, K, r, Uf);
+  load_channel(ea, slot, id, K, r, Uf);
   double conc;
   choose_mixing(ea.mode, rho, K, r, Uf, W, conc);
   mixed_ops(K, r, W, rho, Kp, p);
@@ -451,7 +463,7 @@ __device__ int one_event(const EventArgs& ea, int ch, const cd (&rho)[2][2], uin
     j = forced;
     if (!(p[j] > 0.0)) return -1;
   } else {
-    j = sample_branch(p, event_uniform(ea.seed, traj, layer, qubit));
+    j = sample_branch(p, event_uniform(ea.seed, (uint32_t)(ea.traj_base + traj), layer, qubit));
   }
   double inv = 1.0 / sqrt(p[j]);
   for (int a = 0; a < 2; ++a)
@@ -477,9 +489,10 @@ __device__ void write_record(const EventArgs& ea, int traj, int qubit, int j, co
 // lower and upper qubit; writes kops[traj] = {Ks, Kt} (normalised by 1/sqrt(p)).
 __global__ __launch_bounds__(64) void k_gate_events(EventArgs ea, const double* __restrict__ partial, int n_tiles, int q, int has_s, int has_t,
                               double* __restrict__ kops, int* __restrict__ status) {
-  const int ch_s = has_s ? 0 : -1, ch_t = has_t ? 1 : -1;
   int traj = blockIdx.x * blockDim.x + threadIdx.x;
   if (traj >= ea.n_traj) return;
+  const int layer = current_layer(ea);
+  const int ch_s = event_channel(ea, traj, layer, q, has_s), ch_t = event_channel(ea, traj, layer, q + 1, has_t);
   cd rho[4][4];
   for (int x = 0; x < 16; ++x) rho[x >> 2][x & 3] = cz();
   const double* pp = partial + (long long)traj * n_tiles * 32;
@@ -498,7 +511,7 @@ __global__ __launch_bounds__(64) void k_gate_events(EventArgs ea, const double* 
     cd rs[2][2];
     for (int s = 0; s < 2; ++s)
       for (int s2 = 0; s2 < 2; ++s2) rs[s][s2] = rho[2 * s][2 * s2] + rho[2 * s + 1][2 * s2 + 1];
-    int j = one_event(ea, ch_s, rs, traj, ea.layer, q, -1, Ks, p, W);
+    int j = one_event(ea, 0, ch_s, rs, traj, layer, q, -1, Ks, p, W);
     if (j < 0) { atomicOr(status, 2); j = 0; }
     write_record(ea, traj, q, j, W);
     // rho <- (Ks x I) rho (Ks x I)^dag  (Ks already carries 1/sqrt(p))
@@ -523,7 +536,7 @@ __global__ __launch_bounds__(64) void k_gate_events(EventArgs ea, const double* 
     double tt = rt[0][0].re + rt[1][1].re;
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) rt[a][b] = (1.0 / tt) * rt[a][b];
-    int j = one_event(ea, ch_t, rt, traj, ea.layer, q + 1, -1, Kt, p, W);
+    int j = one_event(ea, 1, ch_t, rt, traj, layer, q + 1, -1, Kt, p, W);
     if (j < 0) { atomicOr(status, 2); j = 0; }
     write_record(ea, traj, q + 1, j, W);
   }
@@ -543,6 +556,13 @@ __global__ __launch_bounds__(64) void k_site_event(EventArgs ea, const double* _
                              double* __restrict__ kops, double* __restrict__ p_out, int* __restrict__ status) {
   int traj = blockIdx.x * blockDim.x + threadIdx.x;
   if (traj >= ea.n_traj) return;
+  const int layer = current_layer(ea);
+  const int id = event_channel(ea, traj, layer, q, 1);
+  double* ko = kops + (long long)traj * 16;
+  if (id < 0) {   // no event on this trajectory: identity
+    for (int x = 0; x < 16; ++x) ko[x] = (x == 0 || x == 6 || x == 8 || x == 14) ? 1.0 : 0.0;
+    return;
+  }
   cd rho[2][2];
   const double* r = rho1 + traj * 8;
   for (int x = 0; x < 4; ++x) rho[x >> 1][x & 1] = cd{r[2 * x], r[2 * x + 1]};
@@ -553,7 +573,7 @@ __global__ __launch_bounds__(64) void k_site_event(EventArgs ea, const double* _
   double p[4];
   cd W[4][4];
   int f = forced ? forced[traj] : -1;
-  int j = one_event(ea, ch, rho, traj, ea.layer, q, f, Ks, p, W);
+  int j = one_event(ea, ch, id, rho, traj, layer, q, f, Ks, p, W);
   if (j < 0) {
     atomicOr(status, 2);
     Ks[0][0] = cd{1, 0}; Ks[0][1] = cz(); Ks[1][0] = cz(); Ks[1][1] = cd{1, 0};
@@ -562,7 +582,6 @@ __global__ __launch_bounds__(64) void k_site_event(EventArgs ea, const double* _
   write_record(ea, traj, q, j, W);
   if (p_out)
     for (int jj = 0; jj < 4; ++jj) p_out[traj * 4 + jj] = p[jj];
-  double* ko = kops + (long long)traj * 16;
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) {
       ko[2 * (2 * a + b)] = Ks[a][b].re;
@@ -586,7 +605,7 @@ __global__ __launch_bounds__(64) void k_site_event_check(EventArgs ea, const dou
   for (int x = 0; x < 4; ++x) rho[x >> 1][x & 1] = (1.0 / tr) * rho[x >> 1][x & 1];
   cd K[4][2][2], Uf[4][4], Kp[4][2][2], W[4][4];
   int rr;
-  load_channel(ea, ch, K, rr, Uf);
+  load_channel(ea, ch, 0, K, rr, Uf);
   double conc, p[4];
   choose_mixing(ea.mode, rho, K, rr, Uf, W, conc);
   mixed_ops(K, rr, W, rho, Kp, p);

@@ -142,6 +142,93 @@ def brickwork(n: int, depth: int, seed: int, channel: np.ndarray, idle_noise: bo
                    name=name)
 
 
+@dataclasses.dataclass
+class MixedCircuit:
+    """Per-trajectory brickwork circuits over a shared gate pool (trajectories of different
+    widths, depths, bond dimensions and noise strengths in one batch).  Arrays are padded to
+    the widest trajectory n and the deepest one depth; trajectories are ordered so that
+    equal (width, chi) are consecutive."""
+    n: int
+    depth: int
+    gates: np.ndarray       # pool [n_gates][4][4] c128
+    gate_id: np.ndarray     # [n_traj][depth][n // 2] int32, -1 = identity
+    channels: np.ndarray    # [n_channels][4][2][2]
+    n_kraus: np.ndarray
+    events: np.ndarray      # [n_traj][depth][n] int32, -1 = none
+    widths: np.ndarray      # [n_traj]
+    depths: np.ndarray
+    chis: np.ndarray
+    name: str = ""
+
+    @property
+    def n_traj(self) -> int:
+        return int(self.widths.shape[0])
+
+    def trajectory_circuit(self, t: int) -> Circuit:
+        """The uniform circuit of trajectory t on its own width and depth."""
+        w, d = int(self.widths[t]), int(self.depths[t])
+        gates = np.zeros((d, w // 2, 4, 4), dtype=np.complex128)
+        for l in range(d):
+            for i, q in enumerate(layer_pairs(w, l)):
+                gates[l, i] = self.gates[self.gate_id[t, l, i]]
+        ev = self.events[t, :d, :w].copy()
+        used = sorted(set(int(x) for x in ev.ravel() if x >= 0))
+        remap = {c: i for i, c in enumerate(used)}
+        ev2 = np.vectorize(lambda x: remap.get(int(x), -1))(ev).astype(np.int32) if ev.size else ev
+        tab = self.channels[used] if used else np.zeros((0, 4, 2, 2), dtype=np.complex128)
+        nk = self.n_kraus[used] if used else np.zeros(0, dtype=np.int32)
+        return Circuit(n=w, depth=d, gates=gates, channels=tab, n_kraus=nk, events=ev2, name=f"{self.name}[{t}]")
+
+
+def mixed_brickwork(n_traj: int, seed: int, widths=(24, 64), depths=(16, 32), chis=(16, 32, 64, 128),
+                    p_range=(0.005, 0.03), pool_size: int = 1 << 16, name: str = "") -> MixedCircuit:
+    """Each trajectory its own Haar brickwork circuit: width ~ U{widths}, depth ~ U{depths},
+    chi ~ U(chis), depolarizing p ~ U[p_range] on both qubits after every gate; gates are
+    drawn by index from a pool of ``pool_size`` Haar gates.  Trajectories are sorted by
+    (chi, width) so that equal shapes are consecutive."""
+    rng = np.random.default_rng(seed)
+    w = rng.integers(widths[0], widths[1] + 1, size=n_traj)
+    d = rng.integers(depths[0], depths[1] + 1, size=n_traj)
+    c = rng.choice(np.asarray(chis), size=n_traj)
+    p = rng.uniform(p_range[0], p_range[1], size=n_traj)
+    order = np.lexsort((w, c))
+    w, d, c, p = w[order], d[order], c[order], p[order]
+    pool = haar_unitaries(pool_size, seed + 1)
+    nmax, dmax = int(w.max()), int(d.max())
+    ids = rng.integers(0, pool_size, size=(n_traj, dmax, nmax // 2)).astype(np.int32)
+    gate_id = np.full((n_traj, dmax, nmax // 2), -1, dtype=np.int32)
+    events = np.full((n_traj, dmax, nmax), -1, dtype=np.int32)
+    for l in range(dmax):
+        par = l % 2
+        slots = np.arange(nmax // 2)
+        q_lo = par + 2 * slots
+        for t in range(n_traj):
+            if l >= d[t]:
+                continue
+            ok = q_lo + 1 < w[t]
+            gate_id[t, l, slots[ok]] = ids[t, l, slots[ok]]
+            events[t, l, q_lo[ok]] = t
+            events[t, l, q_lo[ok] + 1] = t
+    tab, nk = _pad_channels([depolarizing(float(x)) for x in p])
+    return MixedCircuit(n=nmax, depth=dmax, gates=pool, gate_id=gate_id, channels=tab, n_kraus=nk,
+                        events=events, widths=w.astype(np.int32), depths=d.astype(np.int32),
+                        chis=c.astype(np.int32), name=name)
+
+
+def config_mixed(n_traj: int = 16384) -> "MixedWorkload":
+    """16384 trajectories, each its own circuit: width 24..64, depth 16..32, chi in
+    {16, 32, 64, 128}, depolarizing p in [0.005, 0.03], gates from a pool of 2^16."""
+    mc = mixed_brickwork(n_traj, seed=1003, name="mixed_w24-64_d16-32")
+    return MixedWorkload(mc, seed=2003, name=f"mixed-w24-64-d16-32-chi16-128-{n_traj}traj")
+
+
+@dataclasses.dataclass
+class MixedWorkload:
+    circuit: MixedCircuit
+    seed: int
+    name: str
+
+
 def noiseless_copy(c: Circuit) -> Circuit:
     """Same gates, no noise events."""
     return dataclasses.replace(c, events=np.full_like(c.events, -1))

@@ -30,9 +30,10 @@ class MpsbError(RuntimeError):
 
 
 class _Circuit(ctypes.Structure):
-    _fields_ = [("depth", ctypes.c_int), ("gates", ctypes.c_void_p), ("n_channels", ctypes.c_int),
+    _fields_ = [("depth", ctypes.c_int), ("gates", ctypes.c_void_p), ("n_gates", ctypes.c_int),
+                ("gate_id", ctypes.c_void_p), ("n_channels", ctypes.c_int),
                 ("kraus", ctypes.c_void_p), ("n_kraus", ctypes.c_void_p), ("events", ctypes.c_void_p),
-                ("unravel_mode", ctypes.c_int), ("fixed_u", ctypes.c_void_p)]
+                ("events_per_traj", ctypes.c_int), ("unravel_mode", ctypes.c_int), ("fixed_u", ctypes.c_void_p)]
 
 
 def lib():
@@ -45,10 +46,13 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
         L.mps_last_error.restype = ctypes.c_char_p
-        L.mps_batch_plan.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
-        L.mps_batch_create.argtypes = [i32, i32, i32, i32, u64, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
-        L.mps_batch_set_circuit.argtypes = [vp, ctypes.POINTER(_Circuit)]
-        L.mps_circuit_validate.argtypes = [i32, ctypes.POINTER(_Circuit)]
+        L.mps_batch_plan.argtypes = [i32, vp, vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.mps_batch_create.argtypes = [i32, vp, vp, i32, u64, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
+        L.mps_circuit_bytes.argtypes = [vp, ctypes.POINTER(_Circuit), ctypes.POINTER(sz)]
+        L.mps_batch_set_circuit.argtypes = [vp, ctypes.POINTER(_Circuit), vp, sz]
+        L.mps_circuit_validate.argtypes = [i32, vp, ctypes.POINTER(_Circuit)]
+        L.mps_batch_set_graphs.argtypes = [vp, i32]
+        L.mps_batch_set_autotune.argtypes = [vp, i32]
         L.apply_layer.argtypes = [vp, i32, vp, vp, vp]
         L.sample_kraus.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
         L.mps_truncate.argtypes = [vp, i32, vp]
@@ -87,14 +91,20 @@ def _dev(x, dtype):
 
 
 class CircuitArrays:
-    """Host arrays of an inputs.Circuit in the layout the C ABI expects."""
+    """Host arrays of a circuit in the layout the C ABI expects: an inputs.Circuit (one
+    circuit shared by all trajectories), or an inputs.MixedCircuit (gate pool, per-trajectory
+    gate ids and events)."""
 
     def __init__(self, circuit, mode: int = OPTIMAL, fixed_u: Optional[np.ndarray] = None):
+        pooled = hasattr(circuit, "gate_id")
         self.n = circuit.n
         self.gates = np.ascontiguousarray(circuit.gates.astype(np.complex128)).view(np.float64)
+        self.n_gates = circuit.gates.shape[0] if pooled else 0
+        self.gate_id = np.ascontiguousarray(circuit.gate_id.astype(np.int32)) if pooled else None
         self.kraus = np.ascontiguousarray(circuit.channels.astype(np.complex128)).view(np.float64)
         self.n_kraus = np.ascontiguousarray(circuit.n_kraus.astype(np.int32))
         self.events = np.ascontiguousarray(circuit.events.astype(np.int32))
+        self.events_per_traj = 1 if pooled else 0
         self.depth = circuit.depth
         self.mode = mode
         if fixed_u is not None:
@@ -108,47 +118,79 @@ class CircuitArrays:
         c = _Circuit()
         c.depth = self.depth
         c.gates = self.gates.ctypes.data
+        c.n_gates = self.n_gates
+        c.gate_id = self.gate_id.ctypes.data if self.gate_id is not None else None
         c.n_channels = self.n_kraus.shape[0]
         c.kraus = self.kraus.ctypes.data
         c.n_kraus = self.n_kraus.ctypes.data
         c.events = self.events.ctypes.data
+        c.events_per_traj = self.events_per_traj
         c.unravel_mode = self.mode
         c.fixed_u = self.fixed_u.ctypes.data if self.fixed_u is not None else None
         return c
 
 
-def plan(n_traj: int, n_qubits: int, chi: int, precision: int):
-    s, w = ctypes.c_size_t(), ctypes.c_size_t()
-    _check(lib().mps_batch_plan(n_traj, n_qubits, chi, precision, ctypes.byref(s), ctypes.byref(w)))
-    return s.value, w.value
+def _shape_arrays(n_traj: int, n_qubits, chi):
+    w = np.ascontiguousarray(np.broadcast_to(np.asarray(n_qubits, dtype=np.int32), (n_traj,)))
+    c = np.ascontiguousarray(np.broadcast_to(np.asarray(chi, dtype=np.int32), (n_traj,)))
+    return w, c
 
 
-def validate_circuit(circuit, mode: int = OPTIMAL, fixed_u=None):
+def plan(n_traj: int, n_qubits, chi, precision: int):
+    """(state_bytes, work_bytes); n_qubits and chi are ints or per-trajectory arrays."""
+    w, c = _shape_arrays(n_traj, n_qubits, chi)
+    s, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().mps_batch_plan(n_traj, w.ctypes.data, c.ctypes.data, precision, ctypes.byref(s),
+                                ctypes.byref(wb)))
+    return s.value, wb.value
+
+
+def validate_circuit(circuit, mode: int = OPTIMAL, fixed_u=None, n_traj: int = 1, widths=None):
     ca = CircuitArrays(circuit, mode, fixed_u)
     st = ca.struct()
-    _check(lib().mps_circuit_validate(circuit.n, ctypes.byref(st)))
+    w = np.ascontiguousarray(np.broadcast_to(np.asarray(circuit.n if widths is None else widths, dtype=np.int32),
+                                             (n_traj,)))
+    _check(lib().mps_circuit_validate(n_traj, w.ctypes.data, ctypes.byref(st)))
 
 
 class Batch:
-    """A batch of MPS trajectories living in caller (torch) device buffers."""
+    """A batch of MPS trajectories living in caller (torch) device buffers.  n_qubits and
+    chi are ints (uniform batch) or per-trajectory arrays (mixed batch: equal shapes must be
+    consecutive)."""
 
-    def __init__(self, n_traj: int, n_qubits: int, chi: int, precision: int = FP64, seed: int = 0):
+    def __init__(self, n_traj: int, n_qubits, chi, precision: int = FP64, seed: int = 0):
         import torch
-        self.n_traj, self.n, self.chi, self.precision = n_traj, n_qubits, chi, precision
-        sb, wb = plan(n_traj, n_qubits, chi, precision)
+        self.widths, self.chis = _shape_arrays(n_traj, n_qubits, chi)
+        self.n_traj, self.precision = n_traj, precision
+        self.n = int(self.widths.max())
+        self.chi = int(self.chis.max())
+        self.mixed = bool((self.widths != self.widths[0]).any() or (self.chis != self.chis[0]).any())
+        sb, wb = plan(n_traj, self.widths, self.chis, precision)
         self.state = torch.empty(sb, dtype=torch.uint8, device="cuda")
         self.work = torch.empty(wb, dtype=torch.uint8, device="cuda")
         h = ctypes.c_void_p()
-        _check(lib().mps_batch_create(n_traj, n_qubits, chi, precision, ctypes.c_uint64(seed),
-                                      _ptr(self.state), sb, _ptr(self.work), wb, _stream(),
-                                      ctypes.byref(h)))
+        _check(lib().mps_batch_create(n_traj, self.widths.ctypes.data, self.chis.ctypes.data, precision,
+                                      ctypes.c_uint64(seed), _ptr(self.state), sb, _ptr(self.work), wb,
+                                      _stream(), ctypes.byref(h)))
         self.h = h
         self._circ = None
+        self._cbuf = None
 
     def set_circuit(self, circuit, mode: int = OPTIMAL, fixed_u=None):
-        self._circ = CircuitArrays(circuit, mode, fixed_u)
-        st = self._circ.struct()
-        _check(lib().mps_batch_set_circuit(self.h, ctypes.byref(st)))
+        import torch
+        ca = CircuitArrays(circuit, mode, fixed_u)
+        st = ca.struct()
+        nb = ctypes.c_size_t()
+        _check(lib().mps_circuit_bytes(self.h, ctypes.byref(st), ctypes.byref(nb)))
+        buf = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
+        _check(lib().mps_batch_set_circuit(self.h, ctypes.byref(st), _ptr(buf), nb.value))
+        self._circ, self._cbuf = ca, buf
+
+    def set_graphs(self, enable: bool):
+        _check(lib().mps_batch_set_graphs(self.h, int(bool(enable))))
+
+    def set_autotune(self, enable: bool):
+        _check(lib().mps_batch_set_autotune(self.h, int(bool(enable))))
 
     def apply_layer(self, layer: int, discarded=None, branch=None, w_record=None):
         _check(lib().apply_layer(self.h, layer, _ptr(discarded), _ptr(branch), _ptr(w_record)))
@@ -164,12 +206,16 @@ class Batch:
         _check(lib().mps_truncate(self.h, chi, _ptr(discarded)))
 
     def expect(self, per_traj: bool = True):
-        """(mean, m2, per_traj) of <Z_i> (n) then <Z_i Z_i+1> (n-1), float64 CUDA tensors."""
+        """(mean, m2, per_traj) of <Z_i> (n) then <Z_i Z_i+1> (n-1), float64 CUDA tensors.
+        A mixed batch returns (None, None, per_traj [n_traj][2W-1], NaN-padded)."""
         import torch
         nobs = 2 * self.n - 1
+        pt = torch.empty((self.n_traj, nobs), dtype=torch.float64, device="cuda") if (per_traj or self.mixed) else None
+        if self.mixed:
+            _check(lib().expect(self.h, None, None, _ptr(pt)))
+            return None, None, pt
         mean = torch.empty(nobs, dtype=torch.float64, device="cuda")
         m2 = torch.empty(nobs, dtype=torch.float64, device="cuda")
-        pt = torch.empty((self.n_traj, nobs), dtype=torch.float64, device="cuda") if per_traj else None
         _check(lib().expect(self.h, _ptr(mean), _ptr(m2), _ptr(pt)))
         return mean, m2, pt
 

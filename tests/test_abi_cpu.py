@@ -73,3 +73,48 @@ def test_circuit_validation():
     with pytest.raises(M.MpsbError):
         M.validate_circuit(c, M.FIXED, 2 * np.eye(4))
     M.validate_circuit(c, M.FIXED, np.eye(4))
+
+
+def test_mixed_plan_is_the_sum_of_its_runs():
+    w = np.array([10, 10, 12, 12, 12, 12], dtype=np.int32)
+    c = np.array([8, 8, 8, 8, 16, 16], dtype=np.int32)
+    s, wb = M.plan(6, w, c, M.FP32_BULK)
+    parts = [M.plan(2, 10, 8, M.FP32_BULK), M.plan(2, 12, 8, M.FP32_BULK), M.plan(2, 12, 16, M.FP32_BULK)]
+    al = lambda x: (x + 255) // 256 * 256
+    assert s == sum(al(p[0]) for p in parts) and wb == sum(al(p[1]) for p in parts)
+    # a uniform batch given as arrays plans exactly as the scalar form
+    assert M.plan(5, np.full(5, 10), np.full(5, 8), M.FP64) == M.plan(5, 10, 8, M.FP64)
+
+
+def test_pooled_circuit_validation():
+    mc = I.mixed_brickwork(12, seed=7, widths=(6, 9), depths=(3, 5), chis=(4, 8), pool_size=32)
+    M.validate_circuit(mc, n_traj=mc.n_traj, widths=mc.widths)
+    bad = I.MixedCircuit(**{**mc.__dict__, "gate_id": mc.gate_id.copy()})
+    bad.gate_id[0, 0, 0] = 32
+    with pytest.raises(M.MpsbError) as e:
+        M.validate_circuit(bad, n_traj=mc.n_traj, widths=mc.widths)
+    assert e.value.code == M.EINVAL
+    bad2 = I.MixedCircuit(**{**mc.__dict__, "gates": mc.gates.copy()})
+    bad2.gates[3] *= 1.01
+    with pytest.raises(M.MpsbError) as e:
+        M.validate_circuit(bad2, n_traj=mc.n_traj, widths=mc.widths)
+    assert e.value.code == M.EINVAL
+    bad3 = I.MixedCircuit(**{**mc.__dict__, "events": mc.events.copy()})
+    bad3.events[2, 1, 0] = mc.channels.shape[0]
+    with pytest.raises(M.MpsbError) as e:
+        M.validate_circuit(bad3, n_traj=mc.n_traj, widths=mc.widths)
+    assert e.value.code == M.EINVAL
+
+
+def test_mixed_trajectory_circuit_matches_the_tables():
+    mc = I.mixed_brickwork(8, seed=3, widths=(5, 9), depths=(2, 4), chis=(4,), pool_size=16)
+    for t in range(mc.n_traj):
+        c = mc.trajectory_circuit(t)
+        assert c.n == mc.widths[t] and c.depth == mc.depths[t]
+        for l in range(c.depth):
+            for i, q in enumerate(c.pairs(l)):
+                assert np.array_equal(c.gates[l, i], mc.gates[mc.gate_id[t, l, i]])
+                assert c.events[l, q] >= 0 and c.events[l, q + 1] >= 0
+        # past the trajectory's width / depth: identity and no events
+        assert (mc.gate_id[t, c.depth:] == -1).all() and (mc.events[t, c.depth:] == -1).all()
+        assert (mc.events[t, :, c.n:] == -1).all()

@@ -1,0 +1,122 @@
+"""Whole-layer HIP graphs and mixed batches.
+
+* Graph replay: with graphs on, a layer signature's first occurrence runs directly, the
+  second is captured and later ones replay the graph; the state buffers must equal those of
+  a run with graphs off, bit for bit, after every layer (eager torch work and device
+  synchronisations between the replays).
+* Mixed batches (trajectories of different widths, depths, bond dimensions and noise
+  strengths, gates from a shared pool): every trajectory, replayed by the oracle on its own
+  circuit with the GPU's recorded mixings, matches branch for branch and in its
+  observables; the graph-replayed run (no records) gives the recorded run's observables bit
+  for bit.
+"""
+import numpy as np
+import pytest
+
+from oracle import mps as omps
+from oracle import sv as osv
+from paper_2508_05745_amd import inputs as I
+
+from gpu_util import gram_truncation_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_graph_replays_match_direct_runs(prec):
+    import torch
+
+    from paper_2508_05745_amd import mpsb as M
+    c = I.brickwork(10, 8, seed=41, channel=I.depolarizing(0.05), idle_noise=True)
+    a = M.Batch(64, c.n, 16, prec, 5)
+    b = M.Batch(64, c.n, 16, prec, 5)
+    a.set_circuit(c, M.OPTIMAL)
+    b.set_circuit(c, M.OPTIMAL)
+    b.set_graphs(False)
+    for l in range(c.depth):
+        a.apply_layer(l)
+        b.apply_layer(l)
+        # eager work between replays
+        x = torch.randn(1 << 20, device="cuda")
+        _ = (x * x).sum().item()
+        torch.cuda.synchronize()
+        assert torch.equal(a.state, b.state), l
+    ma, _, pa = a.expect()
+    mb, _, pb = b.expect()
+    assert torch.equal(pa, pb)
+    a.sync()
+    b.sync()
+    a.close()
+    b.close()
+
+
+def _run_mixed(mc, seed, prec, record, verbose=False):
+    import torch
+
+    from paper_2508_05745_amd import mpsb as M
+    b = M.Batch(mc.n_traj, mc.widths, mc.chis, prec, seed)
+    b.set_circuit(mc, M.OPTIMAL)
+    T, W = mc.n_traj, mc.n
+    w = torch.zeros((T, W, 4, 4), dtype=torch.complex128, device="cuda") if record else None
+    br = torch.zeros((T, W), dtype=torch.int32, device="cuda") if record else None
+    ws, brs = [], []
+    for l in range(mc.depth):
+        b.apply_layer(l, branch=br, w_record=w)
+        if verbose:
+            print(f"layer {l} queued", flush=True)
+        if record:
+            ws.append(w.cpu().numpy())
+            brs.append(br.cpu().numpy())
+    _, _, pt = b.expect()
+    b.sync()
+    out = dict(per_traj=pt.cpu().numpy(), w=ws, branch=brs)
+    b.close()
+    return out
+
+
+def _replay_mixed(mc, seed, out, t, tol0, u):
+    c = mc.trajectory_circuit(t)
+    ws, js = [], []
+    for l in range(c.depth):
+        for kind, q in osv.sweep_ops(c, l):
+            for x in osv.event_qubits(c, l, kind, q):
+                ws.append(out["w"][l][t, x].T.copy())
+                js.append(int(out["branch"][l][t, x]))
+    rp = osv.Replay(ws)
+    rec, spectra = [], []
+    m, _ = omps.trajectory(c, int(mc.chis[t]), t, seed, mode=3, record=rec, replay=rp, spectra=spectra)
+    zi, zz = omps.z_expectations(m)
+    ref = np.concatenate([zi, zz])
+    assert js == [r["j"] for r in rec], t
+    assert rp.max_incomplete < 1e-10 and rp.max_gap < (1e-9 if u < 1e-10 else 1e-4), (t, rp.max_gap)
+    got = out["per_traj"][t]
+    nobs = 2 * c.n - 1
+    assert np.isnan(got[nobs:]).all()
+    err = np.abs(got[:nobs] - ref).max()
+    tol = max(tol0, gram_truncation_bound(spectra, int(mc.chis[t]), u))
+    print(f"traj {t} (width {c.n}, depth {c.depth}, chi {mc.chis[t]}): max |d<O>| {err:.1e}, tol {tol:.1e}",
+          flush=True)
+    assert err < tol, (t, err, tol)
+
+
+@pytest.mark.parametrize("prec,tol,u", [(1, 1e-10, 2.0 ** -53), (0, 1e-4, 2.0 ** -24)])
+def test_mixed_batch_replay_and_graphs(prec, tol, u):
+    mc = I.mixed_brickwork(40, seed=11, widths=(5, 10), depths=(3, 7), chis=(4, 8, 16), pool_size=64)
+    rec = _run_mixed(mc, 23, prec, True)
+    for t in range(mc.n_traj):
+        _replay_mixed(mc, 23, rec, t, tol, u)
+    fast = _run_mixed(mc, 23, prec, False)
+    assert np.array_equal(np.nan_to_num(fast["per_traj"], nan=7.0), np.nan_to_num(rec["per_traj"], nan=7.0))
+
+
+def test_mixed_workload_sampled():
+    """The mixed-batch workload's distributions (chi 16..128, depolarizing 0.005..0.03,
+    2^16-gate pool) with widths 24..32 and depths 16..20 at 256 trajectories, FP32-bulk;
+    one sampled trajectory of every chi class replayed by the oracle."""
+    mc = I.mixed_brickwork(256, seed=1003, widths=(24, 32), depths=(16, 20))
+    rec = _run_mixed(mc, 2003, 0, True, verbose=True)
+    chis = mc.chis
+    sample = [int(np.flatnonzero(chis == c)[0]) for c in (16, 32, 64, 128)]
+    for t in sample:
+        _replay_mixed(mc, 2003, rec, t, 1e-4, 2.0 ** -24)
+    assert np.isfinite(rec["per_traj"][:, 0]).all()
