@@ -587,7 +587,7 @@ hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long
   switch (phase) {
     case 0:
       if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 8, 4, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
-      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 4, 4, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
+      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 4, 4, 256>), dim3(batch), dim3(256), 0, st, n, (c64d*)A, sA, ws, sW);
       else hipLaunchKernelGGL((k_tridiag<512, 4, 2, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
       break;
     case 1:
