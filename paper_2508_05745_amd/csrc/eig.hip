@@ -274,7 +274,7 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
                                                 double* __restrict__ evals, long long sE, double* __restrict__ kept_sum) {
   __shared__ double sd[EMAX], se[EMAX], se2[EMAX];
   __shared__ double red[ET / 64];
-  __shared__ double s_bounds[2];
+  __shared__ double s_bounds[3];
   double* W = ws + blockIdx.x * sW;
   double* d = W;
   c64d* ec = (c64d*)(W + n);
@@ -318,9 +318,15 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
     hi += 2 * DBL_EPSILON * nrm + 1e-300;
     s_bounds[0] = lo;
     s_bounds[1] = hi;
+    double dmax = 0;
+    for (int i = 0; i < n; ++i) dmax = fmax(dmax, sd[i]);
+    s_bounds[2] = dmax;   // lambda_max >= the largest diagonal entry
   }
   __syncthreads();
   const double glo = s_bounds[0], ghi = s_bounds[1];
+  // an eigenvalue whose bracket lies below zero_tol * (lower bound of lambda_max) is dropped
+  // whatever its exact value, so its bisection stops there
+  const double cut_lb = zero_tol * s_bounds[2];
   const double tnorm = fmax(fabs(glo), fabs(ghi));
   double emax2 = 0;
   for (int i = 0; i + 1 < n; ++i) emax2 = fmax(emax2, se2[i]);
@@ -332,7 +338,9 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
     double lo = glo, hi = ghi;
     for (int it = 0; it < 200; ++it) {
       double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin || mid <= lo || mid >= hi) break;
+      if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin || mid <= lo || mid >= hi ||
+          hi <= cut_lb)
+        break;
       if (sturm_count(n, sd, se2, mid, pivmin) <= idx) lo = mid; else hi = mid;
     }
     ev[k] = 0.5 * (lo + hi);
@@ -587,7 +595,7 @@ hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long
   switch (phase) {
     case 0:
       if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 8, 4, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
-      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 4, 4, 256>), dim3(batch), dim3(256), 0, st, n, (c64d*)A, sA, ws, sW);
+      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 6, 4, 256>), dim3(batch), dim3(256), 0, st, n, (c64d*)A, sA, ws, sW);
       else hipLaunchKernelGGL((k_tridiag<512, 4, 2, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
       break;
     case 1:
