@@ -583,7 +583,183 @@ __global__ __launch_bounds__(ET) void k_backtransform(int n, int keep, const c64
   }
 }
 
-size_t heev_ws_doubles(int n, int keep) { return (size_t)6 * n + (size_t)6 * n * keep + 64; }
+// ---------------------------------------------------------------------------- E3 (MFMA)
+// Panel form of the back-transformation on FP64 16x16x4 MFMAs.  E3a computes, once per
+// matrix, the compact-WY factor T of every block of 16 reflectors (I - V T V^dag =
+// H_j0 ... H_j0+nb-1) from S = V^dag V into the workspace.  E3b gives each workgroup a panel
+// of 16 eigenvector columns: the panel Z = diag(omega) X[:, panel] stays in LDS while the
+// blocks are applied from the last to the first (W = V^dag Z, W <- T W, Z -= V W), V read
+// from the matrix as MFMA operands (the panels of one matrix share it in L2: workgroups are
+// numbered so that they run on one XCD); the panel is written out once.
+// MFMA lane layout (f64 16x16x4): A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+// D[i][j] in lane j + 16 (i % 4), register i / 4.
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+__device__ inline v4d_t mfma64(double a, double b, v4d_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// workspace per matrix: d, e, trace, omega, X and the inverse-iteration arrays (6 n + 6 n keep
+// doubles), then the T factors (2 * 16 * 16 doubles per block of 16 reflectors)
+__host__ __device__ inline size_t bt_tfac_offset(int n, int keep) { return (size_t)6 * n + (size_t)6 * n * keep + 64; }
+
+__global__ __launch_bounds__(256) void k_bt_tfac(int n, const c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
+                                                 long long sW, int keep) {
+  __shared__ double Sp[4][2][16][16];
+  __shared__ c64d Sv[16][16];
+  __shared__ c64d Tm[16][16];
+  const c64d* A = Ag + blockIdx.x * sA;
+  double* W = ws + blockIdx.x * sW;
+  c64d* Tout = (c64d*)(W + bt_tfac_offset(n, keep));
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int nref = n - 2;
+  const int nblk = nref > 0 ? (nref + 15) / 16 : 0;
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int j0 = 16 * blk, nb = min(16, nref - j0);
+    // S[a][b] = sum_i conj(V[i][a]) V[i][b]; lane r16 + 16 kq holds V[row][r16] for both operands
+    v4d_t sr = {0, 0, 0, 0}, si = {0, 0, 0, 0};
+    for (int i0 = j0 + 1 + 4 * wv; i0 < n; i0 += 16) {
+      const int row = i0 + kq;
+      c64d v = {0, 0};
+      if (row < n && r16 < nb && row > j0 + r16) v = A[(long long)row * n + j0 + r16];
+      sr = mfma64(v.re, v.re, sr);
+      sr = mfma64(v.im, v.im, sr);
+      si = mfma64(v.re, v.im, si);
+      si = mfma64(-v.im, v.re, si);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Sp[wv][0][kq + 4 * r][r16] = sr[r];
+      Sp[wv][1][kq + 4 * r][r16] = si[r];
+    }
+    __syncthreads();
+    {
+      const int a = tid >> 4, b = tid & 15;
+      Sv[a][b] = c64d{Sp[0][0][a][b] + Sp[1][0][a][b] + Sp[2][0][a][b] + Sp[3][0][a][b],
+                      Sp[0][1][a][b] + Sp[1][1][a][b] + Sp[2][1][a][b] + Sp[3][1][a][b]};
+      Tm[a][b] = c64d{0, 0};
+    }
+    __syncthreads();
+    for (int jj = 0; jj < nb; ++jj) {
+      if (tid < jj) {
+        const int a = tid;
+        c64d s = {0, 0};
+        for (int b = a; b < jj; ++b) s = s + Tm[a][b] * Sv[b][jj];
+        Tm[a][jj] = -2.0 * s;
+      }
+      if (tid == 0) Tm[jj][jj] = c64d{2.0, 0.0};
+      __syncthreads();
+    }
+    Tout[(long long)blk * 256 + tid] = Tm[tid >> 4][tid & 15];
+    __syncthreads();
+  }
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* __restrict__ Ag, long long sA,
+                                                  const double* __restrict__ ws, long long sW, c64d* __restrict__ Zg,
+                                                  long long sZ, int n_panels) {
+  __shared__ double Zr[NMAX][17], Zi[NMAX][17];
+  __shared__ double Wp[4][2][16][16];
+  __shared__ double Wr[16][17], Wi[16][17];
+  __shared__ c64d Tl[16][16];
+  // XCD-aware numbering: the panels of a matrix are consecutive logical ids on one XCD
+  const int G = gridDim.x, w = blockIdx.x;
+  const int q8 = G >> 3, r8 = G & 7, x8 = w & 7;
+  const int L = x8 * q8 + min(x8, r8) + (w >> 3);
+  const int mat = L / n_panels, panel = L - mat * n_panels;
+  const c64d* A = Ag + mat * sA;
+  const double* W = ws + mat * sW;
+  const c64d* om = (const c64d*)(W + 4 * n);
+  const double* X = W + 6 * n;
+  const c64d* Tg = (const c64d*)(W + bt_tfac_offset(n, keep));
+  c64d* Z = Zg + mat * sZ;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int c0 = panel * 16, pc = min(16, keep - c0);
+  for (int e = tid; e < n * 16; e += 256) {
+    const int r = e >> 4, c = e & 15;
+    const double x = c < pc ? X[(long long)r * keep + c0 + c] : 0.0;
+    Zr[r][c] = om[r].re * x;
+    Zi[r][c] = om[r].im * x;
+  }
+  __syncthreads();
+  const int nref = n - 2;
+  const int nblk = nref > 0 ? (nref + 15) / 16 : 0;
+  for (int blk = nblk - 1; blk >= 0; --blk) {
+    const int j0 = 16 * blk, nb = min(16, nref - j0);
+    Tl[tid >> 4][tid & 15] = Tg[(long long)blk * 256 + tid];
+    // W[a][c] = sum_rows conj(V[row][a]) Z[row][c]; the waves split the rows
+    v4d_t wr = {0, 0, 0, 0}, wi = {0, 0, 0, 0};
+    for (int i0 = j0 + 1 + 4 * wv; i0 < n; i0 += 16) {
+      const int row = i0 + kq;
+      c64d v = {0, 0};
+      double zr = 0, zi = 0;
+      if (row < n) {
+        if (r16 < nb && row > j0 + r16) v = A[(long long)row * n + j0 + r16];
+        zr = Zr[row][r16];
+        zi = Zi[row][r16];
+      }
+      wr = mfma64(v.re, zr, wr);
+      wr = mfma64(v.im, zi, wr);
+      wi = mfma64(v.re, zi, wi);
+      wi = mfma64(-v.im, zr, wi);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Wp[wv][0][kq + 4 * r][r16] = wr[r];
+      Wp[wv][1][kq + 4 * r][r16] = wi[r];
+    }
+    __syncthreads();
+    {
+      const int a = tid >> 4, c = tid & 15;
+      Wr[a][c] = Wp[0][0][a][c] + Wp[1][0][a][c] + Wp[2][0][a][c] + Wp[3][0][a][c];
+      Wi[a][c] = Wp[0][1][a][c] + Wp[1][1][a][c] + Wp[2][1][a][c] + Wp[3][1][a][c];
+    }
+    __syncthreads();
+    {
+      // W <- T W (T upper triangular)
+      const int a = tid >> 4, c = tid & 15;
+      double tr = 0, ti = 0;
+      for (int b = a; b < nb; ++b) {
+        const c64d t = Tl[a][b];
+        tr += t.re * Wr[b][c] - t.im * Wi[b][c];
+        ti += t.re * Wi[b][c] + t.im * Wr[b][c];
+      }
+      __syncthreads();
+      Wr[a][c] = tr;
+      Wi[a][c] = ti;
+    }
+    __syncthreads();
+    // Z -= V W over 16-row tiles (rows <= j0 get zero from the masked V)
+    for (int rt = (j0 + 1) / 16 + wv; 16 * rt < n; rt += 4) {
+      const int r0 = 16 * rt;
+      v4d_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 0; k0 < 16; k0 += 4) {
+        const int a = k0 + kq, row = r0 + r16;
+        c64d v = {0, 0};
+        if (row < n && a < nb && row > j0 + a) v = A[(long long)row * n + j0 + a];
+        const double br = Wr[a][r16], bi = Wi[a][r16];
+        dr = mfma64(v.re, br, dr);
+        dr = mfma64(-v.im, bi, dr);
+        di = mfma64(v.re, bi, di);
+        di = mfma64(v.im, br, di);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + kq + 4 * r;
+        if (row < n) {
+          Zr[row][r16] -= dr[r];
+          Zi[row][r16] -= di[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * 16; e += 256) {
+    const int r = e >> 4, c = e & 15;
+    if (c < pc) Z[(long long)r * keep + c0 + c] = c64d{Zr[r][c], Zi[r][c]};
+  }
+}
+
+size_t heev_ws_doubles(int n, int keep) { return bt_tfac_offset(n, keep) + (size_t)((n + 15) / 16) * 512; }
 size_t heev_gws_doubles(int keep) { return (size_t)keep * keep + 64; }
 
 hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long long sA, double* ws, long long sW,
@@ -603,10 +779,20 @@ hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long
       break;
     case 2:
       break;   // (reserved)
-    default:
-      if (n <= 256) hipLaunchKernelGGL((k_backtransform<256, 16>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
-      else hipLaunchKernelGGL((k_backtransform<512, 8>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
+    default: {
+      if (n <= 128 || n > 256) {   // blocked LDS form
+        if (n <= 256) hipLaunchKernelGGL((k_backtransform<256, 16>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
+        else hipLaunchKernelGGL((k_backtransform<512, 8>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
+        break;
+      }
+      // 128 < n <= 256: MFMA panel form (T factors, then 16-column panels)
+      hipLaunchKernelGGL(k_bt_tfac, dim3(batch), dim3(256), 0, st, n, (const c64d*)A, sA, ws, sW, keep);
+      const int np = (keep + 15) / 16;
+      const long long blocks = (long long)np * batch;
+      if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_bt_panel<256>), dim3((unsigned)blocks), dim3(256), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np);
       break;
+    }
   }
   return hipGetLastError();
 }

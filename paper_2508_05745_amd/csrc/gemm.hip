@@ -104,46 +104,6 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const cplx<TA
   }
 }
 
-template <typename TA, typename TB, typename TACC, typename TC>
-static hipError_t gemm_dispatch(bool ca, bool cb, int M, int N, int K, const void* A, int lda,
-                                long long sA, const void* B, int ldb, long long sB, void* C,
-                                int ldc, long long sC, const double* alpha, int batch,
-                                hipStream_t st) {
-  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch);
-  auto a = (const cplx<TA>*)A;
-  auto b = (const cplx<TB>*)B;
-  auto c = (cplx<TC>*)C;
-  if (!ca && !cb) hipLaunchKernelGGL((k_gemm<TA, TB, TACC, TC, false, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
-  else if (ca && !cb) hipLaunchKernelGGL((k_gemm<TA, TB, TACC, TC, true, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
-  else if (!ca && cb) hipLaunchKernelGGL((k_gemm<TA, TB, TACC, TC, false, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
-  else hipLaunchKernelGGL((k_gemm<TA, TB, TACC, TC, true, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
-  return hipGetLastError();
-}
-
-hipError_t gemm(int prec_in, int prec_out, bool ca, bool cb, int M, int N, int K, const void* A,
-                int lda, long long sA, const void* B, int ldb, long long sB, void* C, int ldc,
-                long long sC, const double* alpha, int batch, hipStream_t st) {
-  if (prec_in == 0 && prec_out == 0)
-    return gemm_dispatch<float, float, float, float>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
-  if (prec_in == 0 && prec_out == 1)
-    return gemm_dispatch<float, float, float, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
-  return gemm_dispatch<double, double, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
-}
-
-// ============================================================================ theta
-// theta[(a,s),(t,b)] = sum_c C[a][s][c] B[c][t][b]; then per (a,b) the 4 values over (s,t)
-// are mixed by the gate G[s't'][st] and written in place of theta (row 2a+s', column
-// t' chi_r + b), and the two-site reduced density matrix
-//   rho[x][y] = sum_{a,b} thetaG[x][a,b] conj(thetaG[y][a,b]),  x = 2s'+t'
-// is accumulated per tile (FP64) into partial[traj][tile][16] c128.
-// Tile: 32 values of a (64 rows) x 32 values of b for both t (64 columns), 4 waves of 64.
-// Each wave owns 16 values of a x 16 values of b and all four (s,t) blocks, so the gate mix
-// and the RDM stay in registers.  Complex products are four real 16x16x4 MFMAs (re*re,
-// -im*im, re*im, im*re) per (s,t) block and k-step of 4.
-// Lane layout of the 16x16x4 MFMAs: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k; the
-// result D[i][j] sits in lane j + 16 (i / 4), register i % 4 for the f32 instruction and in
-// lane j + 16 (i % 4), register i / 4 for the f64 one (checked on the device).
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // the 4x4 gate of trajectory traj (uniform over the workgroup)
@@ -173,6 +133,144 @@ template <> struct MfmaAcc<double> {
   static __device__ inline int row(int lane_hi, int reg) { return lane_hi + 4 * reg; }
 };
 
+// MFMA form of the generic GEMM: the same 64 x 64 block tile and LDS staging; each of the
+// 4 waves owns a 32 x 32 quadrant as 2 x 2 MFMA sub-tiles of 16 x 16, complex products as four
+// real 16x16x4 MFMAs (f32 for FP32 inputs, f64 for FP64 inputs) per k-step of 4.
+template <typename TA, typename TB, typename TACC, typename TC, bool CA, bool CB>
+__global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cplx<TA>* __restrict__ A,
+                                                   int lda, long long sA, const cplx<TB>* __restrict__ B,
+                                                   int ldb, long long sB, cplx<TC>* __restrict__ C, int ldc,
+                                                   long long sC, const double* __restrict__ alpha) {
+  using Mf = MfmaAcc<TACC>;
+  using V = typename Mf::V;
+  __shared__ TACC As_re[GB_K][GB_M + 4], As_im[GB_K][GB_M + 4];
+  __shared__ TACC Bs_re[GB_K][GB_N + 4], Bs_im[GB_K][GB_N + 4];
+  const int bz = blockIdx.z;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wa = wv >> 1, wb = wv & 1, r16 = lane & 15, kq = lane >> 4;
+  V acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc_re[i][j] = V{0, 0, 0, 0};
+      acc_im[i][j] = V{0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < K; k0 += GB_K) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int e = tid + 256 * r;
+      int mm, kk;
+      if (!CA) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
+      int m = m0 + mm, k = k0 + kk;
+      cplx<TA> v = {0, 0};
+      if (m < M && k < K) {
+        if (!CA) v = A[(long long)m * lda + k];
+        else { v = A[(long long)k * lda + m]; v.im = -v.im; }
+      }
+      As_re[kk][mm] = (TACC)v.re;
+      As_im[kk][mm] = (TACC)v.im;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int e = tid + 256 * r;
+      int nn, kk;
+      if (!CB) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
+      int n = n0 + nn, k = k0 + kk;
+      cplx<TB> v = {0, 0};
+      if (n < N && k < K) {
+        if (!CB) v = B[(long long)k * ldb + n];
+        else { v = B[(long long)n * ldb + k]; v.im = -v.im; }
+      }
+      Bs_re[kk][nn] = (TACC)v.re;
+      Bs_im[kk][nn] = (TACC)v.im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < GB_K / 4; ++k4) {
+      const int kk = 4 * k4 + kq;
+      TACC ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As_re[kk][32 * wa + 16 * i + r16];
+        ai[i] = As_im[kk][32 * wa + 16 * i + r16];
+        br[i] = Bs_re[kk][32 * wb + 16 * i + r16];
+        bi[i] = Bs_im[kk][32 * wb + 16 * i + r16];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = Mf::mac(ar[i], br[j], acc_re[i][j]);
+          acc_re[i][j] = Mf::mac(-ai[i], bi[j], acc_re[i][j]);
+          acc_im[i][j] = Mf::mac(ar[i], bi[j], acc_im[i][j]);
+          acc_im[i][j] = Mf::mac(ai[i], br[j], acc_im[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  const double al = alpha ? alpha[bz] : 1.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + 32 * wb + 16 * j + r16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 32 * wa + 16 * i + Mf::row(kq, r);
+        if (m >= M || n >= N) continue;
+        cplx<TC> o;
+        o.re = (TC)(al * (double)acc_re[i][j][r]);
+        o.im = (TC)(al * (double)acc_im[i][j][r]);
+        C[(long long)m * ldc + n] = o;
+      }
+    }
+}
+
+template <typename TA, typename TB, typename TACC, typename TC>
+static hipError_t gemm_dispatch(bool ca, bool cb, int M, int N, int K, const void* A, int lda,
+                                long long sA, const void* B, int ldb, long long sB, void* C,
+                                int ldc, long long sC, const double* alpha, int batch,
+                                hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch);
+  auto a = (const cplx<TA>*)A;
+  auto b = (const cplx<TB>*)B;
+  auto c = (cplx<TC>*)C;
+  if (!ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
+  else if (ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
+  else if (!ca && cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
+  else hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
+  return hipGetLastError();
+}
+
+hipError_t gemm(int prec_in, int prec_out, bool ca, bool cb, int M, int N, int K, const void* A,
+                int lda, long long sA, const void* B, int ldb, long long sB, void* C, int ldc,
+                long long sC, const double* alpha, int batch, hipStream_t st) {
+  if (prec_in == 0 && prec_out == 0)
+    return gemm_dispatch<float, float, float, float>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
+  if (prec_in == 0 && prec_out == 1)
+    return gemm_dispatch<float, float, float, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
+  return gemm_dispatch<double, double, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
+}
+
+// ============================================================================ theta
+// theta[(a,s),(t,b)] = sum_c C[a][s][c] B[c][t][b]; then per (a,b) the 4 values over (s,t)
+// are mixed by the gate G[s't'][st] and written in place of theta (row 2a+s', column
+// t' chi_r + b), and the two-site reduced density matrix
+//   rho[x][y] = sum_{a,b} thetaG[x][a,b] conj(thetaG[y][a,b]),  x = 2s'+t'
+// is accumulated per tile (FP64) into partial[traj][tile][16] c128.
+// Tile: 32 values of a (64 rows) x 32 values of b for both t (64 columns), 4 waves of 64.
+// Each wave owns 16 values of a x 16 values of b and all four (s,t) blocks, so the gate mix
+// and the RDM stay in registers.  Complex products are four real 16x16x4 MFMAs (re*re,
+// -im*im, re*im, im*re) per (s,t) block and k-step of 4.
+// Lane layout of the 16x16x4 MFMAs: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k; the
+// result D[i][j] sits in lane j + 16 (i / 4), register i % 4 for the f32 instruction and in
+// lane j + 16 (i % 4), register i / 4 for the f64 one (checked on the device).
 template <typename T>
 __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, const cplx<T>* __restrict__ Cs,
                                                     const cplx<T>* __restrict__ Bs, long long s_traj,

@@ -42,27 +42,70 @@ __global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int o
   double dmax = 0;
   for (int w = 0; w < HT / 64; ++w) dmax = fmax(dmax, red[w]);
   const double cut = tol * dmax;
-  // right-looking Cholesky E = R^dag R
-  for (int c = 0; c < n; ++c) {
-    __syncthreads();   // previous trailing update complete
-    const double p = R[pk(c, c, n)].re;
-    const bool keep = p > cut && p > 0.0;
-    const double r = keep ? sqrt(p) : 0.0;
-    __syncthreads();   // everyone has read the pivot before row c is rewritten
-    for (int k = c + tid; k < n; k += HT) {
-      c64d v = R[pk(c, k, n)];
-      R[pk(c, k, n)] = keep ? (k == c ? c64d{r, 0.0} : c64d{v.re / r, v.im / r}) : c64d{0, 0};
-    }
-    if (tid == 0) piv[c] = r;
-    __syncthreads();
-    if (keep) {
-      // E[i][k] -= conj(R[c][i]) R[c][k], c < i <= k: all pairs in parallel
-      const int m = n - c - 1;
-      for (int e = tid; e < m * m; e += HT) {
-        const int i = c + 1 + e / m, k = c + 1 + e % m;
-        if (i > k) continue;
-        R[pk(i, k, n)] = R[pk(i, k, n)] - cmulc(R[pk(c, i, n)], R[pk(c, k, n)]);
+  // blocked right-looking Cholesky E = R^dag R: panels of CB rows are factored column by
+  // column (updates confined to the panel), then the trailing upper triangle takes the
+  // rank-CB update in 4 x 4 register tiles
+  constexpr int CB = 8;
+  for (int c0 = 0; c0 < n; c0 += CB) {
+    const int cb = min(CB, n - c0);
+    for (int c = c0; c < c0 + cb; ++c) {
+      __syncthreads();   // previous updates complete
+      const double p = R[pk(c, c, n)].re;
+      const bool keep = p > cut && p > 0.0;
+      const double r = keep ? sqrt(p) : 0.0;
+      __syncthreads();   // everyone has read the pivot before row c is rewritten
+      for (int k = c + tid; k < n; k += HT) {
+        c64d v = R[pk(c, k, n)];
+        R[pk(c, k, n)] = keep ? (k == c ? c64d{r, 0.0} : c64d{v.re / r, v.im / r}) : c64d{0, 0};
       }
+      if (tid == 0) piv[c] = r;
+      __syncthreads();
+      // rows c+1 .. c0+cb-1 of the panel: E[i][k] -= conj(R[c][i]) R[c][k], i <= k
+      if (keep) {
+        const int rows = c0 + cb - (c + 1), m = n - (c + 1);
+        for (int e = tid; e < rows * m; e += HT) {
+          const int i = c + 1 + e / m, k = c + 1 + e % m;
+          if (k >= i) R[pk(i, k, n)] = R[pk(i, k, n)] - cmulc(R[pk(c, i, n)], R[pk(c, k, n)]);
+        }
+      }
+    }
+    __syncthreads();
+    // trailing update, rows and columns >= t0 = c0 + cb, upper triangle in 4 x 4 tiles
+    const int t0 = c0 + cb, m = n - t0;
+    if (m <= 0) continue;
+    const int nt = (m + 3) / 4, ntiles = nt * (nt + 1) / 2;
+    for (int t = tid; t < ntiles; t += HT) {
+      // tile (ti, tk), tk >= ti, linear index t = tk (tk + 1) / 2 + ti
+      int tk = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+      while (tk * (tk + 1) / 2 > t) --tk;
+      while ((tk + 1) * (tk + 2) / 2 <= t) ++tk;
+      const int ti = t - tk * (tk + 1) / 2;
+      const int i0 = t0 + 4 * ti, k0 = t0 + 4 * tk;
+      c64d acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = c64d{0, 0};
+      for (int c = c0; c < t0; ++c) {
+        if (!(piv[c] > 0.0)) continue;
+        c64d ri[4], rk[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          ri[a] = (i0 + a < n) ? R[pk(c, i0 + a, n)] : c64d{0, 0};
+          rk[a] = (k0 + a < n) ? R[pk(c, k0 + a, n)] : c64d{0, 0};
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = acc[a][b] + cmulc(ri[a], rk[b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = i0 + a, k = k0 + b;
+          if (i < n && k < n && k >= i) R[pk(i, k, n)] = R[pk(i, k, n)] - acc[a][b];
+        }
     }
   }
   __syncthreads();
