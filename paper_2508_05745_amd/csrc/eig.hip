@@ -656,10 +656,12 @@ template <int NMAX>
 __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* __restrict__ Ag, long long sA,
                                                   const double* __restrict__ ws, long long sW, c64d* __restrict__ Zg,
                                                   long long sZ, int n_panels) {
-  __shared__ double Zr[NMAX][17], Zi[NMAX][17];
-  __shared__ double Wp[4][2][16][16];
-  __shared__ double Wr[16][17], Wi[16][17];
-  __shared__ c64d Tl[16][16];
+  // 80 KB of LDS so that two panels share a CU: the panel (rows of 16 doubles read 4 rows at
+  // a time: conflict-free without padding), the partial W of waves 1-3 (wave 0 reduces in
+  // registers) and the reduced W
+  __shared__ double Zr[NMAX][16], Zi[NMAX][16];
+  __shared__ double Wp[3][2][16][16];
+  __shared__ double Wr[16][16], Wi[16][16];
   // XCD-aware numbering: the panels of a matrix are consecutive logical ids on one XCD
   const int G = gridDim.x, w = blockIdx.x;
   const int q8 = G >> 3, r8 = G & 7, x8 = w & 7;
@@ -684,41 +686,56 @@ __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* _
   const int nblk = nref > 0 ? (nref + 15) / 16 : 0;
   for (int blk = nblk - 1; blk >= 0; --blk) {
     const int j0 = 16 * blk, nb = min(16, nref - j0);
-    Tl[tid >> 4][tid & 15] = Tg[(long long)blk * 256 + tid];
-    // W[a][c] = sum_rows conj(V[row][a]) Z[row][c]; the waves split the rows
-    v4d_t wr = {0, 0, 0, 0}, wi = {0, 0, 0, 0};
-    for (int i0 = j0 + 1 + 4 * wv; i0 < n; i0 += 16) {
-      const int row = i0 + kq;
-      c64d v = {0, 0};
-      double zr = 0, zi = 0;
-      if (row < n) {
-        if (r16 < nb && row > j0 + r16) v = A[(long long)row * n + j0 + r16];
-        zr = Zr[row][r16];
-        zi = Zi[row][r16];
+    // W[a][c] = sum_rows conj(V[row][a]) Z[row][c]; the waves split the rows, two
+    // independent accumulator chains per wave (rows i0 and i0 + 16)
+    v4d_t wr0 = {0, 0, 0, 0}, wi0 = {0, 0, 0, 0}, wr1 = {0, 0, 0, 0}, wi1 = {0, 0, 0, 0};
+    for (int i0 = j0 + 1 + 4 * wv; i0 < n; i0 += 32) {
+      const int row0 = i0 + kq, row1 = i0 + 16 + kq;
+      c64d v0 = {0, 0}, v1 = {0, 0};
+      double zr0 = 0, zi0 = 0, zr1 = 0, zi1 = 0;
+      if (row0 < n) {
+        if (r16 < nb && row0 > j0 + r16) v0 = A[(long long)row0 * n + j0 + r16];
+        zr0 = Zr[row0][r16];
+        zi0 = Zi[row0][r16];
       }
-      wr = mfma64(v.re, zr, wr);
-      wr = mfma64(v.im, zi, wr);
-      wi = mfma64(v.re, zi, wi);
-      wi = mfma64(-v.im, zr, wi);
+      if (row1 < n) {
+        if (r16 < nb && row1 > j0 + r16) v1 = A[(long long)row1 * n + j0 + r16];
+        zr1 = Zr[row1][r16];
+        zi1 = Zi[row1][r16];
+      }
+      wr0 = mfma64(v0.re, zr0, wr0);
+      wr1 = mfma64(v1.re, zr1, wr1);
+      wi0 = mfma64(v0.re, zi0, wi0);
+      wi1 = mfma64(v1.re, zi1, wi1);
+      wr0 = mfma64(v0.im, zi0, wr0);
+      wr1 = mfma64(v1.im, zi1, wr1);
+      wi0 = mfma64(-v0.im, zr0, wi0);
+      wi1 = mfma64(-v1.im, zr1, wi1);
     }
+    if (wv > 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      Wp[wv][0][kq + 4 * r][r16] = wr[r];
-      Wp[wv][1][kq + 4 * r][r16] = wi[r];
+      for (int r = 0; r < 4; ++r) {
+        Wp[wv - 1][0][kq + 4 * r][r16] = wr0[r] + wr1[r];
+        Wp[wv - 1][1][kq + 4 * r][r16] = wi0[r] + wi1[r];
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = kq + 4 * r;
+        Wr[a][r16] = wr0[r] + wr1[r] + Wp[0][0][a][r16] + Wp[1][0][a][r16] + Wp[2][0][a][r16];
+        Wi[a][r16] = wi0[r] + wi1[r] + Wp[0][1][a][r16] + Wp[1][1][a][r16] + Wp[2][1][a][r16];
+      }
     }
     __syncthreads();
     {
+      // W <- T W (T upper triangular, read from the workspace)
       const int a = tid >> 4, c = tid & 15;
-      Wr[a][c] = Wp[0][0][a][c] + Wp[1][0][a][c] + Wp[2][0][a][c] + Wp[3][0][a][c];
-      Wi[a][c] = Wp[0][1][a][c] + Wp[1][1][a][c] + Wp[2][1][a][c] + Wp[3][1][a][c];
-    }
-    __syncthreads();
-    {
-      // W <- T W (T upper triangular)
-      const int a = tid >> 4, c = tid & 15;
+      const c64d* Tb = Tg + (long long)blk * 256 + a * 16;
       double tr = 0, ti = 0;
       for (int b = a; b < nb; ++b) {
-        const c64d t = Tl[a][b];
+        const c64d t = Tb[b];
         tr += t.re * Wr[b][c] - t.im * Wi[b][c];
         ti += t.re * Wi[b][c] + t.im * Wr[b][c];
       }
@@ -738,8 +755,8 @@ __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* _
         if (row < n && a < nb && row > j0 + a) v = A[(long long)row * n + j0 + a];
         const double br = Wr[a][r16], bi = Wi[a][r16];
         dr = mfma64(v.re, br, dr);
-        dr = mfma64(-v.im, bi, dr);
         di = mfma64(v.re, bi, di);
+        dr = mfma64(-v.im, bi, dr);
         di = mfma64(v.im, br, di);
       }
 #pragma unroll

@@ -115,46 +115,62 @@ __global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int o
       c64d v = k >= i ? R[pk(i, k, n)] : c64d{0, 0};
       Ro[(long long)i * n + k] = cplx<T>{(T)v.re, (T)v.im};
     }
-  // triangular solves, one wave per vector; lane owns entries lane + 64 s
-  constexpr int SL = NMAX / 64;
+  // triangular solves, one wave per group of VG vectors solved together (independent chains
+  // share the broadcasts of R); lane owns entries lane + 64 s
+  constexpr int SL = NMAX / 64, VG = 4;
   const int nvec = other;
-  for (int vidx = wv; vidx < nvec; vidx += HT / 64) {
-    c64d x[SL];
-    // load the vector: L->R: row vidx of C (length n, contiguous); R->L: column vidx of C,
+  for (int v0 = VG * wv; v0 < nvec; v0 += VG * (HT / 64)) {
+    c64d x[VG][SL];
+    // load the vectors: L->R: row vidx of C (length n, contiguous); R->L: column vidx of C,
     // conjugated (C^dag row), stride `other`
 #pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      const int k = lane + 64 * s;
-      cplx<T> v = {0, 0};
-      if (k < n) v = left_to_right ? Cj[(long long)vidx * n + k] : Cj[(long long)k * other + vidx];
-      x[s] = left_to_right ? c64d{(double)v.re, (double)v.im} : c64d{(double)v.re, -(double)v.im};
-    }
+    for (int g = 0; g < VG; ++g)
+#pragma unroll
+      for (int s = 0; s < SL; ++s) {
+        const int k = lane + 64 * s, vidx = v0 + g;
+        cplx<T> v = {0, 0};
+        if (k < n && vidx < nvec) v = left_to_right ? Cj[(long long)vidx * n + k] : Cj[(long long)k * other + vidx];
+        x[g][s] = left_to_right ? c64d{(double)v.re, (double)v.im} : c64d{(double)v.re, -(double)v.im};
+      }
     // solve q R = x: q_k = (x_k - sum_{i<k} q_i R[i][k]) / R[k][k], column-oriented updates
     for (int k = 0; k < n; ++k) {
       const int owner = k & 63, slot = k >> 6;
-      c64d xk = {0, 0};
-#pragma unroll
-      for (int s = 0; s < SL; ++s)
-        if (s == slot) xk = x[s];
-      xk.re = __shfl(xk.re, owner, 64);
-      xk.im = __shfl(xk.im, owner, 64);
       const double rkk = piv[k];
-      const c64d qk = rkk > 0 ? c64d{xk.re / rkk, xk.im / rkk} : c64d{0, 0};
+      const double inv = rkk > 0 ? 1.0 / rkk : 0.0;
+      c64d qk[VG];
+#pragma unroll
+      for (int g = 0; g < VG; ++g) {
+        c64d xk = {0, 0};
+#pragma unroll
+        for (int s = 0; s < SL; ++s)
+          if (s == slot) xk = x[g][s];
+        xk.re = __shfl(xk.re, owner, 64);
+        xk.im = __shfl(xk.im, owner, 64);
+        qk[g] = c64d{xk.re * inv, xk.im * inv};
+      }
 #pragma unroll
       for (int s = 0; s < SL; ++s) {
         const int j = lane + 64 * s;
-        if (j == k) x[s] = qk;
-        else if (j > k && j < n && rkk > 0) x[s] = x[s] - qk * R[pk(k, j, n)];
+        if (j == k) {
+#pragma unroll
+          for (int g = 0; g < VG; ++g) x[g][s] = qk[g];
+        } else if (j > k && j < n && rkk > 0) {
+          const c64d rkj = R[pk(k, j, n)];
+#pragma unroll
+          for (int g = 0; g < VG; ++g) x[g][s] = x[g][s] - qk[g] * rkj;
+        }
       }
     }
 #pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      const int k = lane + 64 * s;
-      if (k < n) {
-        if (left_to_right) Cj[(long long)vidx * n + k] = cplx<T>{(T)x[s].re, (T)x[s].im};
-        else Cj[(long long)k * other + vidx] = cplx<T>{(T)x[s].re, (T)(-x[s].im)};
+    for (int g = 0; g < VG; ++g)
+#pragma unroll
+      for (int s = 0; s < SL; ++s) {
+        const int k = lane + 64 * s, vidx = v0 + g;
+        if (k < n && vidx < nvec) {
+          if (left_to_right) Cj[(long long)vidx * n + k] = cplx<T>{(T)x[g][s].re, (T)x[g][s].im};
+          else Cj[(long long)k * other + vidx] = cplx<T>{(T)x[g][s].re, (T)(-x[g][s].im)};
+        }
       }
-    }
   }
 }
 
