@@ -251,18 +251,35 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
 }
 
 // ---------------------------------------------------------------------------- E2
-// Sturm count: number of eigenvalues of the real symmetric tridiagonal (d, e) below x.
-__device__ inline int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  cnt += q < 0;
+// Sturm counts: numbers of eigenvalues of the real symmetric tridiagonal (d, e) below x1 and
+// below x2, from the pivots of the LDL^T factorisations of T - x (two independent chains
+// interleaved).  1/q is the hardware reciprocal refined by one Newton step (relative error
+// below 2^-50, a perturbation of e^2 of that order); pivots below pivmin are replaced by
+// -pivmin.
+__device__ inline double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  return fma(r, fma(-q, r, 1.0), r);
+}
+
+__device__ inline void sturm_count2(int n, const double* d, const double* e2, double x1, double x2, double pivmin,
+                                    int& c1, int& c2) {
+  int n1 = 0, n2 = 0;
+  double q1 = d[0] - x1, q2 = d[0] - x2;
+  if (fabs(q1) < pivmin) q1 = -pivmin;
+  if (fabs(q2) < pivmin) q2 = -pivmin;
+  n1 += q1 < 0;
+  n2 += q2 < 0;
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0;
+    const double di = d[i], ei = e2[i - 1];
+    q1 = fma(-ei, recip(q1), di - x1);
+    q2 = fma(-ei, recip(q2), di - x2);
+    if (fabs(q1) < pivmin) q1 = -pivmin;
+    if (fabs(q2) < pivmin) q2 = -pivmin;
+    n1 += q1 < 0;
+    n2 += q2 < 0;
   }
-  return cnt;
+  c1 = n1;
+  c2 = n2;
 }
 
 __device__ inline uint32_t hash32(uint32_t x) {
@@ -335,13 +352,19 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
   // ---- bisection for the keep largest eigenvalues
   for (int k = tid; k < keep; k += ET) {
     const int idx = n - 1 - k;   // ascending index
+    // trisection: count(lo) <= idx < count(hi) is kept
     double lo = glo, hi = ghi;
-    for (int it = 0; it < 200; ++it) {
-      double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin || mid <= lo || mid >= hi ||
+    for (int it = 0; it < 140; ++it) {
+      const double w = hi - lo;
+      const double m1 = lo + w * (1.0 / 3.0), m2 = lo + w * (2.0 / 3.0);
+      if (w <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin || m1 <= lo || m2 >= hi || m2 <= m1 ||
           hi <= cut_lb)
         break;
-      if (sturm_count(n, sd, se2, mid, pivmin) <= idx) lo = mid; else hi = mid;
+      int c1, c2;
+      sturm_count2(n, sd, se2, m1, m2, pivmin, c1, c2);
+      if (c1 > idx) hi = m1;
+      else if (c2 > idx) { lo = m1; hi = m2; }
+      else lo = m2;
     }
     ev[k] = 0.5 * (lo + hi);
   }
@@ -401,23 +424,28 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
         }
       }
       U0[(long long)(n - 1) * keep + k] = (cd != 0.0) ? cd : tiny;
-      for (int i = 0; i < n; ++i)
-        X[(long long)i * keep + k] = 0.5 + (hash32((uint32_t)(i * 7919 + k * 104729 + 17)) >> 8) * (1.0 / 16777216.0);
+      // two solves: the first from a pseudo-random right-hand side generated on the fly, the
+      // second from the first's result scaled by 1 / max|y| while it is read; the 2-norm of the
+      // last solve is accumulated as it is written
+      double sc = 1.0, nn2 = 0.0;
       for (int itr = 0; itr < 2; ++itr) {
         if (itr > 0) {
+          double xcur = X[k] * sc;
           for (int i = 0; i + 1 < n; ++i) {
             const long long o = (long long)i * keep + k;
-            double xi = X[o], xn = X[o + keep];
+            double xi = xcur, xn = X[o + keep] * sc;
             if (PV[o] != 0.0) { double tmp = xi; xi = xn; xn = tmp; }
             xn -= L[o] * xi;
             X[o] = xi;
-            X[o + keep] = xn;
+            xcur = xn;
           }
+          X[(long long)(n - 1) * keep + k] = xcur;
         }
         double y1 = 0.0, y2 = 0.0, mx = 0.0;
+        nn2 = 0.0;
         for (int i = n - 1; i >= 0; --i) {
           const long long o = (long long)i * keep + k;
-          double v = X[o];
+          double v = itr == 0 ? 0.5 + (hash32((uint32_t)(i * 7919 + k * 104729 + 17)) >> 8) * (1.0 / 16777216.0) : X[o];
           if (i + 1 < n) v -= U1[o] * y1;
           if (i + 2 < n) v -= U2[o] * y2;
           const double y = v / U0[o];
@@ -425,9 +453,9 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
           y2 = y1;
           y1 = y;
           mx = fmax(mx, fabs(y));
+          nn2 += y * y;
         }
-        const double sc = (mx > 0) ? 1.0 / mx : 1.0;
-        for (int i = 0; i < n; ++i) X[(long long)i * keep + k] *= sc;
+        sc = (mx > 0) ? 1.0 / mx : 1.0;
         // orthogonalise against the previous (finished, unit) members of the cluster
         for (int p = k0; p < k; ++p) {
           double dot = 0;
@@ -435,10 +463,12 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
           for (int i = 0; i < n; ++i) X[(long long)i * keep + k] -= dot * X[(long long)i * keep + p];
         }
         if (itr == 0) continue;   // the unit 2-norm is only needed for the final vector
-        double nn2 = 0;
-        for (int r = 0; r < n; ++r) {
-          const double y = X[(long long)r * keep + k];
-          nn2 += y * y;
+        if (k > k0) {   // the orthogonalisation changed the vector
+          nn2 = 0;
+          for (int r = 0; r < n; ++r) {
+            const double y = X[(long long)r * keep + k];
+            nn2 += y * y;
+          }
         }
         const double inv = nn2 > 0 ? 1.0 / sqrt(nn2) : 0.0;
         for (int i = 0; i < n; ++i) X[(long long)i * keep + k] *= inv;

@@ -487,9 +487,13 @@ __device__ void write_record(const EventArgs& ea, int traj, int qubit, int j, co
 
 // Gate events: reduce the theta tiles' RDM partials (fixed order), then the events of the
 // lower and upper qubit; writes kops[traj] = {Ks, Kt} (normalised by 1/sqrt(p)).
+constexpr int EV_SPREAD = 16;
 __global__ __launch_bounds__(64) void k_gate_events(EventArgs ea, const double* __restrict__ partial, int n_tiles, int q, int has_s, int has_t,
                               double* __restrict__ kops, int* __restrict__ status) {
-  int traj = blockIdx.x * blockDim.x + threadIdx.x;
+  // EV_SPREAD trajectories per wave (one lane each, the other lanes idle): the per-lane work
+  // is long and latency-bound, so spreading the waves over more CUs shortens the launch
+  if (threadIdx.x % (64 / EV_SPREAD)) return;
+  int traj = blockIdx.x * EV_SPREAD + threadIdx.x / (64 / EV_SPREAD);
   if (traj >= ea.n_traj) return;
   const int layer = current_layer(ea);
   const int ch_s = event_channel(ea, traj, layer, q, has_s), ch_t = event_channel(ea, traj, layer, q + 1, has_t);
@@ -657,7 +661,7 @@ hipError_t launch_unravel_opt(int batch, const double* rho_q, const double* krau
 
 hipError_t launch_gate_events(const EventArgs& ea, const double* partial, int n_tiles, int q, int has_s, int has_t,
                               double* kops, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_gate_events, dim3((ea.n_traj + 63) / 64), dim3(64), 0, st, ea, partial, n_tiles, q, has_s, has_t,
+  hipLaunchKernelGGL(k_gate_events, dim3((ea.n_traj + EV_SPREAD - 1) / EV_SPREAD), dim3(64), 0, st, ea, partial, n_tiles, q, has_s, has_t,
                      kops, status);
   return hipGetLastError();
 }
