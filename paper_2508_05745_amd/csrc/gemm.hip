@@ -255,6 +255,8 @@ hipError_t gemm(int prec_in, int prec_out, bool ca, bool cb, int M, int N, int K
     return gemm_dispatch<float, float, float, float>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
   if (prec_in == 0 && prec_out == 1)
     return gemm_dispatch<float, float, float, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
+  if (prec_in == 0 && prec_out == 2)   // c64 operands, FP64 accumulation and output
+    return gemm_dispatch<float, float, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
   return gemm_dispatch<double, double, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
 }
 

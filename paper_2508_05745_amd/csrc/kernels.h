@@ -44,7 +44,8 @@ struct GateRef {
   const int* layer;
 };
 
-// prec: 0 = complex64 storage / FP32 arithmetic, 1 = complex128 / FP64
+// prec: 0 = complex64 storage / FP32 arithmetic, 1 = complex128 / FP64; gemm prec_out 2 =
+// c128 output with FP64 accumulation of c64 operands
 hipError_t gemm(int prec_in, int prec_out, bool conj_a, bool conj_b, int M, int N, int K, const void* A, int lda,
                 long long sA, const void* B, int ldb, long long sB, void* C, int ldc, long long sC,
                 const double* alpha, int batch, hipStream_t st);

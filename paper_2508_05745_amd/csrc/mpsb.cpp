@@ -35,7 +35,9 @@ static int fail(int code, const std::string& msg) {
 
 namespace {
 
-constexpr double ZERO_TOL_FP64 = 1e-26;   // relative drop threshold of Gram eigenvalues
+// Relative drop thresholds of Gram eigenvalues (truncation) and Cholesky pivots (centre hops):
+// directions below them are represented by zero vectors.
+constexpr double ZERO_TOL_FP64 = 1e-26;
 constexpr double ZERO_TOL_FP32 = 1e-13;
 
 struct Layout {
@@ -303,7 +305,9 @@ int hop_right(mpsb_batch* h, int j) {
   double* gram = W<double>(h, L.o_gram);
   {
     ProfSec s(h, PC_HOPGEMM);
-    HIPCHK(gemm(p, 1, true, false, cr, cr, 2 * cl, Cj, cr, L.s_traj, Cj, cr, L.s_traj, gram, cr, L.s_gram, nullptr, T, h->st));
+    // FP64 accumulation also in FP32-bulk: Q = C R^-1 is orthonormal only if R comes from an
+    // accurate Gram, and FP32 sums leave its small pivots at rounding-noise level
+    HIPCHK(gemm(p, 2, true, false, cr, cr, 2 * cl, Cj, cr, L.s_traj, Cj, cr, L.s_traj, gram, cr, L.s_gram, nullptr, T, h->st));
   }
   if (cr <= 128) {
     ProfSec sh(h, PC_HOPEIG);
@@ -342,7 +346,7 @@ int hop_left(mpsb_batch* h, int j) {
   double* gram = W<double>(h, L.o_gram);
   {
     ProfSec s(h, PC_HOPGEMM);
-    HIPCHK(gemm(p, 1, false, true, cl, cl, 2 * cr, Cj, 2 * cr, L.s_traj, Cj, 2 * cr, L.s_traj, gram, cl, L.s_gram, nullptr, T, h->st));
+    HIPCHK(gemm(p, 2, false, true, cl, cl, 2 * cr, Cj, 2 * cr, L.s_traj, Cj, 2 * cr, L.s_traj, gram, cl, L.s_gram, nullptr, T, h->st));
   }
   char* tmp = W<char>(h, L.o_tmp);
   if (cl <= 128) {

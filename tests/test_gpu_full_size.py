@@ -73,6 +73,31 @@ def test_benchmark_workload_chi128_timed_layers():
     _check_statistics(a, b, wl.n_traj)
 
 
+def test_benchmark_workload_saturated_fp32_vs_fp64():
+    """The benchmark's timed layers with saturated bonds (layers 0-9, chi = 128 reached at
+    layer 7): the FP32-bulk and FP64 trajectory averages of all 199 observables agree within
+    their combined statistical error (independent optimal unravellings of the same channel
+    give the same average state)."""
+    import torch
+
+    from paper_2508_05745_amd import mpsb as M
+    wl = I.config_wide(chi=128, n_traj=2048)
+    c = wl.circuit
+    res = {}
+    for prec in (1, 0):
+        b = M.Batch(wl.n_traj, c.n, wl.chi, prec, wl.seed)
+        b.set_circuit(c, M.OPTIMAL)
+        for l in range(10):
+            b.apply_layer(l)
+        mean, m2, _ = b.expect(per_traj=False)
+        b.sync()
+        res[prec] = dict(mean=mean.cpu().numpy(), m2=m2.cpu().numpy())
+        b.close()
+        torch.cuda.empty_cache()
+        print(f"precision {prec} done", flush=True)
+    _check_statistics(res[1], res[0], wl.n_traj)
+
+
 @pytest.mark.parametrize("prec", [1, 0])
 def test_saturated_chi128(prec):
     """20 qubits, depth 12: the middle bonds reach and are truncated at chi = 128, so the
