@@ -193,8 +193,8 @@ int expect(mpsb_handle h, double* mean, double* m2, double* per_traj);
  * (all phases), 7 eigenvector back-transformation (n <= 256), 8 recomposition, 9 centre-hop
  * contractions, 10 idle-qubit events, 11 observables, 12 tridiagonalisation (n <= 128),
  * 13 tridiagonalisation (256 < n <= 512), 14 back-transformation (256 < n <= 512).  Classes
- * 4, 12, 13, 7 and 14 each time a single kernel instance (phases 4/12/13, 5, 7/14 are those of
- * the truncation eigensolver). */
+ * 4, 12 and 13 each time a single kernel instance (phases 4/12/13, 5, 7/14 are those of the
+ * truncation eigensolver). */
 int mps_profile(mpsb_handle h, int enable);
 int mps_profile_read(mpsb_handle h, double* ms, long long* count, int n);
 

@@ -827,17 +827,19 @@ hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long
     case 2:
       break;   // (reserved)
     default: {
-      if (n <= 128 || n > 256) {   // blocked LDS form
-        if (n <= 256) hipLaunchKernelGGL((k_backtransform<256, 16>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
-        else hipLaunchKernelGGL((k_backtransform<512, 8>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
+      if (n <= 128) {   // blocked LDS form
+        hipLaunchKernelGGL((k_backtransform<256, 16>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
         break;
       }
-      // 128 < n <= 256: MFMA panel form (T factors, then 16-column panels)
+      // 128 < n <= 512: MFMA panel form (T factors, then 16-column panels)
       hipLaunchKernelGGL(k_bt_tfac, dim3(batch), dim3(256), 0, st, n, (const c64d*)A, sA, ws, sW, keep);
       const int np = (keep + 15) / 16;
       const long long blocks = (long long)np * batch;
       if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_bt_panel<256>), dim3((unsigned)blocks), dim3(256), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np);
+      if (n <= 256)
+        hipLaunchKernelGGL((k_bt_panel<256>), dim3((unsigned)blocks), dim3(256), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np);
+      else
+        hipLaunchKernelGGL((k_bt_panel<512>), dim3((unsigned)blocks), dim3(256), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np);
       break;
     }
   }
