@@ -46,6 +46,7 @@ __device__ inline double block_sum(double v, double* red) {
 template <int NMAX, int NB, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
                                                 long long sW) {
+  static_assert(RB >= 1 && RB <= 16 && (RB & (RB - 1)) == 0, "row blocks are a power of two");
   __shared__ c64d Vt[NB][NMAX], Wt[NB][NMAX];
   __shared__ c64d su[NMAX], sp[NMAX];
   __shared__ c64d part[NT / 64][NMAX];
@@ -108,6 +109,9 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) colacc[s] = c64d{0, 0};
       for (int i0 = wv * RB; i0 < m; i0 += (NT / 64) * RB) {
+        // slots past the block's last row hold no element of the lower triangle: skipped
+        // (wave-uniform), so the work follows the triangle rather than NMAX
+        const int ns = (min(i0 + RB, m) - 1) / 64 + 1;
         c64d av[RB][SLOTS];
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
@@ -116,41 +120,49 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
 #pragma unroll
           for (int s = 0; s < SLOTS; ++s) {
             const int kk = lane + 64 * s;
-            av[rr][s] = (i < m && kk <= i) ? row[kk] : c64d{0, 0};
+            av[rr][s] = (s < ns && i < m && kk <= i) ? row[kk] : c64d{0, 0};
           }
         }
-        double pr[RB], pim[RB];
+        double rs[2 * RB];   // row sums: re and im of each row of the block
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
           const int i = i0 + rr;
           const c64d ui = i < m ? su[i] : c64d{0, 0};
-          pr[rr] = 0;
-          pim[rr] = 0;
+          double pr = 0, pim = 0;
 #pragma unroll
           for (int s = 0; s < SLOTS; ++s) {
-            const int kk = lane + 64 * s;
-            const c64d a = av[rr][s];
-            const c64d uk = su[kk < m ? kk : 0];
-            pr[rr] += a.re * uk.re - a.im * uk.im;
-            pim[rr] += a.re * uk.im + a.im * uk.re;
-            if (kk < i) {
-              colacc[s].re += a.re * ui.re + a.im * ui.im;
-              colacc[s].im += a.re * ui.im - a.im * ui.re;
+            if (s < ns) {
+              const int kk = lane + 64 * s;
+              const c64d a = av[rr][s];
+              const c64d uk = su[kk < m ? kk : 0];
+              pr += a.re * uk.re - a.im * uk.im;
+              pim += a.re * uk.im + a.im * uk.re;
+              if (kk < i) {
+                colacc[s].re += a.re * ui.re + a.im * ui.im;
+                colacc[s].im += a.re * ui.im - a.im * ui.re;
+              }
             }
           }
+          rs[2 * rr] = pr;
+          rs[2 * rr + 1] = pim;
         }
+        // reduce-scatter butterfly over the 2 RB sums: each exchange halves the values a lane
+        // carries, so lane group g = lane / (32 / RB) ends with the full sum of value g
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
+        for (int h = RB, off = 32; h >= 1; h >>= 1, off >>= 1) {
+          const bool up = (lane & off) != 0;
 #pragma unroll
-          for (int rr = 0; rr < RB; ++rr) {
-            pr[rr] += __shfl_down(pr[rr], off, 64);
-            pim[rr] += __shfl_down(pim[rr], off, 64);
+          for (int q = 0; q < h; ++q) {
+            const double send = up ? rs[q] : rs[q + h];
+            const double keep = up ? rs[q + h] : rs[q];
+            rs[q] = keep + __shfl_xor(send, off, 64);
           }
         }
-        if (lane == 0) {
 #pragma unroll
-          for (int rr = 0; rr < RB; ++rr)
-            if (i0 + rr < m) sp[i0 + rr] = c64d{pr[rr], pim[rr]};
+        for (int off = 16 / RB; off >= 1; off >>= 1) rs[0] += __shfl_xor(rs[0], off, 64);
+        if ((lane & (32 / RB - 1)) == 0) {
+          const int g = lane / (32 / RB);
+          if (i0 + (g >> 1) < m) ((double*)&sp[i0 + (g >> 1)])[g & 1] = rs[0];
         }
       }
 #pragma unroll
@@ -201,6 +213,7 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
     // SLOTS columns per lane register-blocked
     const int t0 = j0 + jb;
     for (int r0 = t0 + wv * RB; r0 < n; r0 += (NT / 64) * RB) {
+      const int ns = (min(r0 + RB, n) - 1 - t0) / 64 + 1;   // slots with columns <= last row
       c64d acc[RB][SLOTS];
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr)
@@ -216,14 +229,17 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
         }
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
-          const int c = min(t0 + lane + 64 * s, n - 1);
-          vc[s] = conj(Vt[kk][c]);
-          wc[s] = conj(Wt[kk][c]);
+          if (s < ns) {
+            const int c = min(t0 + lane + 64 * s, n - 1);
+            vc[s] = conj(Vt[kk][c]);
+            wc[s] = conj(Wt[kk][c]);
+          }
         }
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr)
 #pragma unroll
-          for (int s = 0; s < SLOTS; ++s) acc[rr][s] = acc[rr][s] + vr[rr] * wc[s] + wr[rr] * vc[s];
+          for (int s = 0; s < SLOTS; ++s)
+            if (s < ns) acc[rr][s] = acc[rr][s] + vr[rr] * wc[s] + wr[rr] * vc[s];
       }
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) {
@@ -233,7 +249,7 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           const int c = t0 + lane + 64 * s;
-          if (c <= r) row[c] = row[c] - 2.0 * acc[rr][s];
+          if (s < ns && c <= r) row[c] = row[c] - 2.0 * acc[rr][s];
         }
       }
     }
