@@ -23,11 +23,58 @@ namespace mpsb {
 constexpr int ET = 256;           // threads per workgroup
 constexpr int EMAX = 512;         // largest matrix dimension
 
+// Cross-lane moves of doubles on the VALU, without the LDS crossbar: DPP within rows of 16
+// lanes (quad_perm 0xB1 = lane ^ 1, 0x4E = lane ^ 2, row_half_mirror 0x141 = 7 - lane within
+// 8, row_ror:8 0x128 = lane ^ 8) and the CDNA4 permlane swaps across rows.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// lanes 32..63 of a trade places with lanes 0..31 of b (permlane32_swap)
+__device__ inline void swap_halves(double& a, double& b) {
+  const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ia, (unsigned)ib, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ia >> 32), (unsigned)(ib >> 32), false, false);
+  a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+
+// the odd 16-lane rows of a trade places with the even rows of b (permlane16_swap)
+__device__ inline void swap_rows(double& a, double& b) {
+  const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ia, (unsigned)ib, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ia >> 32), (unsigned)(ib >> 32), false, false);
+  a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+
+// sum over the sub-groups of 8 lanes (lane & ~7), in every lane
+__device__ inline double oct_sum(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  return x + dpp_f64<0x141>(x);
+}
+
+// sum over the 64 lanes, in every lane
+__device__ inline double wave_sum(double x) {
+  double y = x;
+  swap_halves(x, y);
+  x += y;
+  y = x;
+  swap_rows(x, y);
+  x += y;
+  x += dpp_f64<0x128>(x);
+  return oct_sum(x);
+}
+
 template <int NT = ET>
 __device__ inline double block_sum(double v, double* red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  v = wave_sum(v);
   __syncthreads();
   if (lane == 0) red[wv] = v;
   __syncthreads();
@@ -46,7 +93,7 @@ __device__ inline double block_sum(double v, double* red) {
 template <int NMAX, int NB, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
                                                 long long sW) {
-  static_assert(RB >= 1 && RB <= 16 && (RB & (RB - 1)) == 0, "row blocks are a power of two");
+  static_assert(RB == 2 || RB == 4, "row blocks of 2 or 4 rows");
   __shared__ c64d Vt[NB][NMAX], Wt[NB][NMAX];
   __shared__ c64d su[NMAX], sp[NMAX];
   __shared__ c64d part[NT / 64][NMAX];
@@ -147,19 +194,26 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
           rs[2 * rr + 1] = pim;
         }
         // reduce-scatter butterfly over the 2 RB sums: each exchange halves the values a lane
-        // carries, so lane group g = lane / (32 / RB) ends with the full sum of value g
+        // carries (lanes 32..63, then odd rows, then lanes 8..15 of a row take the upper
+        // half), so lane group g = lane / (32 / RB) ends with the full sum of value g
 #pragma unroll
-        for (int h = RB, off = 32; h >= 1; h >>= 1, off >>= 1) {
-          const bool up = (lane & off) != 0;
-#pragma unroll
-          for (int q = 0; q < h; ++q) {
-            const double send = up ? rs[q] : rs[q + h];
-            const double keep = up ? rs[q + h] : rs[q];
-            rs[q] = keep + __shfl_xor(send, off, 64);
-          }
+        for (int q = 0; q < RB; ++q) {
+          swap_halves(rs[q], rs[q + RB]);
+          rs[q] += rs[q + RB];
         }
 #pragma unroll
-        for (int off = 16 / RB; off >= 1; off >>= 1) rs[0] += __shfl_xor(rs[0], off, 64);
+        for (int q = 0; q < RB / 2; ++q) {
+          swap_rows(rs[q], rs[q + RB / 2]);
+          rs[q] += rs[q + RB / 2];
+        }
+        if constexpr (RB == 4) {
+          const bool up = (lane & 8) != 0;
+          const double send = up ? rs[0] : rs[1];
+          rs[0] = (up ? rs[1] : rs[0]) + dpp_f64<0x128>(send);
+        } else {
+          rs[0] += dpp_f64<0x128>(rs[0]);
+        }
+        rs[0] = oct_sum(rs[0]);
         if ((lane & (32 / RB - 1)) == 0) {
           const int g = lane / (32 / RB);
           if (i0 + (g >> 1) < m) ((double*)&sp[i0 + (g >> 1)])[g & 1] = rs[0];
@@ -181,11 +235,8 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
           cr += v.re * u.re + v.im * u.im;
           ci += v.re * u.im - v.im * u.re;
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          cr += __shfl_down(cr, off, 64);
-          ci += __shfl_down(ci, off, 64);
-        }
+        cr = wave_sum(cr);
+        ci = wave_sum(ci);
         if (lane == 0) cdot[dd] = c64d{cr, ci};   // even: V^dag u, odd: W^dag u
       }
       __syncthreads();
