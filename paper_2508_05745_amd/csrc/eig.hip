@@ -90,13 +90,20 @@ __device__ inline double block_sum(double v, double* red) {
 // trailing matrix (the matrix-vector product), and the panel's rank-2NB update is applied
 // once at the end of the panel.  The panel vectors live in LDS (column-major by vector, so
 // that lanes read consecutive rows).  u_j is kept in column j below the diagonal.
-template <int NMAX, int NB, int RB, int NT>
-__global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
+// One workgroup per matrix runs a chain of dependent steps per column, so the time per
+// matrix is set by latency rather than by HBM bandwidth: the row sums of the matrix-vector
+// product are reduced on the VALU (permlane swaps and DPP, no LDS round trips), column slots
+// past the trailing triangle are skipped, and WPE > 1 trades registers per wave for more
+// waves per SIMD (two 512-thread workgroups per CU for n <= 256).
+template <int NMAX, int NB, int RB, int NT, int WPE = 1>
+__global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
                                                 long long sW) {
   static_assert(RB == 2 || RB == 4, "row blocks of 2 or 4 rows");
   __shared__ c64d Vt[NB][NMAX], Wt[NB][NMAX];
   __shared__ c64d su[NMAX], sp[NMAX];
-  __shared__ c64d part[NT / 64][NMAX];
+  // column parts of the waves: waves NPART.. add theirs into part[wv - NPART] in a second step
+  constexpr int NPART = NT / 64 > 4 ? 4 : NT / 64;
+  __shared__ c64d part[NPART][NMAX];
   __shared__ c64d cdot[2 * NB];
   __shared__ double red[NT / 64];
   c64d* A = Ag + blockIdx.x * sA;
@@ -152,42 +159,58 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
       // p = (lower-stored Hermitian A22) u: row parts by waves (RB rows at a time, loads
       // issued together), column parts accumulated in registers (lane owns columns
       // lane + 64 s)
-      c64d colacc[SLOTS];
+      // u at the lane's columns: held in registers across the pass when there are at most 4
+      // slots, read from LDS otherwise (register budget of the n <= 512 instance)
+      constexpr bool UK_REG = SLOTS <= 4 && NT <= 256;
+      c64d colacc[SLOTS], ukv[UK_REG ? SLOTS : 1];
 #pragma unroll
-      for (int s = 0; s < SLOTS; ++s) colacc[s] = c64d{0, 0};
-      for (int i0 = wv * RB; i0 < m; i0 += (NT / 64) * RB) {
-        // slots past the block's last row hold no element of the lower triangle: skipped
-        // (wave-uniform), so the work follows the triangle rather than NMAX
-        const int ns = (min(i0 + RB, m) - 1) / 64 + 1;
-        c64d av[RB][SLOTS];
+      for (int s = 0; s < SLOTS; ++s) {
+        const int kk = lane + 64 * s;
+        colacc[s] = c64d{0, 0};
+        if constexpr (UK_REG) ukv[s] = su[kk < m ? kk : 0];
+      }
+      // Row blocks of RB rows, NT / 64 * RB apart for a wave.  Slots past a block's last row
+      // hold no element of the lower triangle and are skipped (wave-uniform), so the work
+      // follows the triangle rather than NMAX.
+      auto load_block = [&](c64d (&buf)[RB][SLOTS], int ib) {
+        const int ns = (min(ib + RB, m) - 1) / 64 + 1;
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
-          const int i = i0 + rr;
+          const int i = ib + rr;
           const c64d* row = A + (long long)(j + 1 + i) * n + (j + 1);
 #pragma unroll
           for (int s = 0; s < SLOTS; ++s) {
             const int kk = lane + 64 * s;
-            av[rr][s] = (s < ns && i < m && kk <= i) ? row[kk] : c64d{0, 0};
+            buf[rr][s] = (s < ns && i < m && kk <= i) ? row[kk] : c64d{0, 0};
           }
         }
+      };
+      auto mul_block = [&](const c64d (&buf)[RB][SLOTS], int ib) {
+        const int ns = (min(ib + RB, m) - 1) / 64 + 1;
         double rs[2 * RB];   // row sums: re and im of each row of the block
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
-          const int i = i0 + rr;
+          const int i = ib + rr;
           const c64d ui = i < m ? su[i] : c64d{0, 0};
           double pr = 0, pim = 0;
 #pragma unroll
           for (int s = 0; s < SLOTS; ++s) {
             if (s < ns) {
               const int kk = lane + 64 * s;
-              const c64d a = av[rr][s];
-              const c64d uk = su[kk < m ? kk : 0];
-              pr += a.re * uk.re - a.im * uk.im;
-              pim += a.re * uk.im + a.im * uk.re;
-              if (kk < i) {
-                colacc[s].re += a.re * ui.re + a.im * ui.im;
-                colacc[s].im += a.re * ui.im - a.im * ui.re;
-              }
+              const c64d a = buf[rr][s];
+              c64d uk;
+              if constexpr (UK_REG) uk = ukv[s];
+              else uk = su[kk < m ? kk : 0];
+              pr = fma(a.re, uk.re, pr);
+              pr = fma(-a.im, uk.im, pr);
+              pim = fma(a.re, uk.im, pim);
+              pim = fma(a.im, uk.re, pim);
+              // strictly lower elements also act on row kk through A[kk][i] = conj(A[i][kk])
+              const double cr = kk < i ? a.re : 0.0, ci = kk < i ? a.im : 0.0;
+              colacc[s].re = fma(cr, ui.re, colacc[s].re);
+              colacc[s].re = fma(ci, ui.im, colacc[s].re);
+              colacc[s].im = fma(cr, ui.im, colacc[s].im);
+              colacc[s].im = fma(-ci, ui.re, colacc[s].im);
             }
           }
           rs[2 * rr] = pr;
@@ -216,13 +239,20 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
         rs[0] = oct_sum(rs[0]);
         if ((lane & (32 / RB - 1)) == 0) {
           const int g = lane / (32 / RB);
-          if (i0 + (g >> 1) < m) ((double*)&sp[i0 + (g >> 1)])[g & 1] = rs[0];
+          if (ib + (g >> 1) < m) ((double*)&sp[ib + (g >> 1)])[g & 1] = rs[0];
         }
+      };
+      for (int i0 = wv * RB; i0 < m; i0 += (NT / 64) * RB) {
+        c64d av[RB][SLOTS];
+        load_block(av, i0);
+        mul_block(av, i0);
       }
+      if (wv < NPART) {
 #pragma unroll
-      for (int s = 0; s < SLOTS; ++s) {
-        const int kk = lane + 64 * s;
-        if (kk < m) part[wv][kk] = colacc[s];
+        for (int s = 0; s < SLOTS; ++s) {
+          const int kk = lane + 64 * s;
+          if (kk < m) part[wv][kk] = colacc[s];
+        }
       }
       // dot products of the panel vectors with u (rows j+1..n-1)
       for (int dd = wv; dd < 2 * k; dd += NT / 64) {
@@ -240,10 +270,21 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
         if (lane == 0) cdot[dd] = c64d{cr, ci};   // even: V^dag u, odd: W^dag u
       }
       __syncthreads();
+      if constexpr (NT / 64 > NPART) {
+        static_assert(NT / 64 <= 2 * NPART, "at most two waves per part row");
+        if (wv >= NPART) {
+#pragma unroll
+          for (int s = 0; s < SLOTS; ++s) {
+            const int kk = lane + 64 * s;
+            if (kk < m) part[wv - NPART][kk] = part[wv - NPART][kk] + colacc[s];
+          }
+        }
+        __syncthreads();
+      }
       for (int i = tid; i < m; i += NT) {
         c64d p = sp[i];
 #pragma unroll
-        for (int w = 0; w < NT / 64; ++w) p = p + part[w][i];
+        for (int w = 0; w < NPART; ++w) p = p + part[w][i];
         const int r = j + 1 + i;
         for (int kk = 0; kk < k; ++kk) {
           c64d corr = Vt[kk][r] * cdot[2 * kk + 1] + Wt[kk][r] * cdot[2 * kk];
@@ -265,32 +306,50 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
     const int t0 = j0 + jb;
     for (int r0 = t0 + wv * RB; r0 < n; r0 += (NT / 64) * RB) {
       const int ns = (min(r0 + RB, n) - 1 - t0) / 64 + 1;   // slots with columns <= last row
-      c64d acc[RB][SLOTS];
+      // with the full register budget (one wave per SIMD and workgroup) the current values are
+      // loaded first, so that their latency overlaps the accumulation; under a tighter budget
+      // (WPE > 1) the other waves on the SIMD cover it
+      constexpr bool PRELOAD = WPE == 1;
+      c64d x[PRELOAD ? RB : 1][SLOTS], acc[RB][SLOTS];
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr)
+      for (int rr = 0; rr < RB; ++rr) {
+        const int r = r0 + rr;
+        const c64d* row = A + (long long)r * n;
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) acc[rr][s] = c64d{0, 0};
+        for (int s = 0; s < SLOTS; ++s) {
+          const int c = t0 + lane + 64 * s;
+          if constexpr (PRELOAD) x[rr][s] = (s < ns && r < n && c <= r) ? row[c] : c64d{0, 0};
+          acc[rr][s] = c64d{0, 0};
+        }
+      }
       for (int kk = 0; kk < jb; ++kk) {
-        c64d vr[RB], wr[RB], vc[SLOTS], wc[SLOTS];
+        c64d vr[RB], wr[RB];
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
           const int r = min(r0 + rr, n - 1);
           vr[rr] = Vt[kk][r];
           wr[rr] = Wt[kk][r];
         }
+        // acc += V[r] conj(W[c]) + W[r] conj(V[c]), slot by slot
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           if (s < ns) {
             const int c = min(t0 + lane + 64 * s, n - 1);
-            vc[s] = conj(Vt[kk][c]);
-            wc[s] = conj(Wt[kk][c]);
+            const c64d vc = Vt[kk][c], wc = Wt[kk][c];
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+              c64d& q = acc[rr][s];
+              q.re = fma(vr[rr].re, wc.re, q.re);
+              q.re = fma(vr[rr].im, wc.im, q.re);
+              q.im = fma(vr[rr].im, wc.re, q.im);
+              q.im = fma(-vr[rr].re, wc.im, q.im);
+              q.re = fma(wr[rr].re, vc.re, q.re);
+              q.re = fma(wr[rr].im, vc.im, q.re);
+              q.im = fma(wr[rr].im, vc.re, q.im);
+              q.im = fma(-wr[rr].re, vc.im, q.im);
+            }
           }
         }
-#pragma unroll
-        for (int rr = 0; rr < RB; ++rr)
-#pragma unroll
-          for (int s = 0; s < SLOTS; ++s)
-            if (s < ns) acc[rr][s] = acc[rr][s] + vr[rr] * wc[s] + wr[rr] * vc[s];
       }
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) {
@@ -300,7 +359,10 @@ __global__ __launch_bounds__(NT) void k_tridiag(int n, c64d* __restrict__ Ag, lo
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           const int c = t0 + lane + 64 * s;
-          if (s < ns && c <= r) row[c] = row[c] - 2.0 * acc[rr][s];
+          if (s < ns && c <= r) {
+            const c64d xo = PRELOAD ? x[PRELOAD ? rr : 0][s] : row[c];
+            row[c] = c64d{fma(-2.0, acc[rr][s].re, xo.re), fma(-2.0, acc[rr][s].im, xo.im)};
+          }
         }
       }
     }
@@ -884,8 +946,8 @@ hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long
   (void)sG;
   switch (phase) {
     case 0:
-      if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 8, 4, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
-      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 6, 4, 256>), dim3(batch), dim3(256), 0, st, n, (c64d*)A, sA, ws, sW);
+      if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 8, 2, 512, 4>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
+      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 6, 2, 512, 4>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
       else hipLaunchKernelGGL((k_tridiag<512, 4, 2, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
       break;
     case 1:
