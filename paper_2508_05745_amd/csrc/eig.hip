@@ -398,6 +398,7 @@ __device__ inline void sturm_count2(int n, const double* d, const double* e2, do
   if (fabs(q2) < pivmin) q2 = -pivmin;
   n1 += q1 < 0;
   n2 += q2 < 0;
+#pragma unroll 4
   for (int i = 1; i < n; ++i) {
     const double di = d[i], ei = e2[i - 1];
     q1 = fma(-ei, recip(q1), di - x1);
@@ -419,6 +420,7 @@ __device__ inline uint32_t hash32(uint32_t x) {
 __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol, double* __restrict__ ws, long long sW,
                                                 double* __restrict__ evals, long long sE, double* __restrict__ kept_sum) {
   __shared__ double sd[EMAX], se[EMAX], se2[EMAX];
+  __shared__ c64d sph[EMAX];   // phases of the subdiagonal
   __shared__ double red[ET / 64];
   __shared__ double s_bounds[3];
   double* W = ws + blockIdx.x * sW;
@@ -436,20 +438,19 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
 
   for (int i = tid; i < n; i += ET) {
     sd[i] = d[i];
-    double a = (i + 1 < n) ? sqrt(norm2(ec[i])) : 0.0;
+    const c64d e = (i + 1 < n) ? ec[i] : c64d{0.0, 0.0};
+    double a = (i + 1 < n) ? sqrt(norm2(e)) : 0.0;
     se[i] = a;
     se2[i] = a * a;
+    sph[i] = a > 0 ? c64d{e.re / a, e.im / a} : c64d{1.0, 0.0};
   }
   __syncthreads();
   if (tid == 0) {
     c64d w = {1.0, 0.0};
     om[0] = w;
+#pragma unroll 8
     for (int i = 0; i + 1 < n; ++i) {
-      double a = se[i];
-      if (a > 0) {
-        c64d ph = {ec[i].re / a, ec[i].im / a};
-        w = w * ph;
-      }
+      if (se[i] > 0) w = w * sph[i];
       om[i + 1] = w;
     }
     double lo = 1e300, hi = -1e300, emax2 = 0;
@@ -531,10 +532,10 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
       double cd = sd[0] - sig, cs = (n > 1) ? se[0] : 0.0;
       for (int i = 0; i + 1 < n; ++i) {
         const double sub = se[i], nd = sd[i + 1] - sig, ns = (i + 2 < n) ? se[i + 1] : 0.0;
-        const long long o = (long long)i * keep + k;
+        const int o = i * keep + k;   // < 2^17
         if (fabs(cd) >= fabs(sub)) {
           double l = (cd != 0.0) ? sub / cd : 0.0;
-          U0[o] = (cd != 0.0) ? cd : tiny;
+          U0[o] = 1.0 / ((cd != 0.0) ? cd : tiny);
           U1[o] = cs;
           U2[o] = 0.0;
           L[o] = l;
@@ -543,7 +544,7 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
           cs = ns;
         } else {
           double l = cd / sub;
-          U0[o] = sub;
+          U0[o] = 1.0 / sub;
           U1[o] = nd;
           U2[o] = ns;
           L[o] = l;
@@ -552,37 +553,73 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
           cs = -l * ns;
         }
       }
-      U0[(long long)(n - 1) * keep + k] = (cd != 0.0) ? cd : tiny;
+      U0[(long long)(n - 1) * keep + k] = 1.0 / ((cd != 0.0) ? cd : tiny);
       // two solves: the first from a pseudo-random right-hand side generated on the fly, the
       // second from the first's result scaled by 1 / max|y| while it is read; the 2-norm of the
-      // last solve is accumulated as it is written
+      // last solve is accumulated as it is written.  U0 holds the reciprocal pivots, and the
+      // factors are loaded CH steps at a time, so that the dependent chain of a solve waits
+      // for memory once per chunk rather than once per step.
+      constexpr int CH = 4;
       double sc = 1.0, nn2 = 0.0;
       for (int itr = 0; itr < 2; ++itr) {
         if (itr > 0) {
           double xcur = X[k] * sc;
-          for (int i = 0; i + 1 < n; ++i) {
-            const long long o = (long long)i * keep + k;
-            double xi = xcur, xn = X[o + keep] * sc;
-            if (PV[o] != 0.0) { double tmp = xi; xi = xn; xn = tmp; }
-            xn -= L[o] * xi;
-            X[o] = xi;
-            xcur = xn;
+          for (int ib = 0; ib + 1 < n; ib += CH) {
+            double xa[CH], pa[CH], la[CH];
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+              const int i = ib + q;
+              if (i + 1 < n) {
+                const int o = i * keep + k;   // < 2^17
+                xa[q] = X[o + keep];
+                pa[q] = PV[o];
+                la[q] = L[o];
+              }
+            }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+              const int i = ib + q;
+              if (i + 1 < n) {
+                double xi = xcur, xn = xa[q] * sc;
+                if (pa[q] != 0.0) { double tmp = xi; xi = xn; xn = tmp; }
+                xn -= la[q] * xi;
+                X[i * keep + k] = xi;
+                xcur = xn;
+              }
+            }
           }
           X[(long long)(n - 1) * keep + k] = xcur;
         }
         double y1 = 0.0, y2 = 0.0, mx = 0.0;
         nn2 = 0.0;
-        for (int i = n - 1; i >= 0; --i) {
-          const long long o = (long long)i * keep + k;
-          double v = itr == 0 ? 0.5 + (hash32((uint32_t)(i * 7919 + k * 104729 + 17)) >> 8) * (1.0 / 16777216.0) : X[o];
-          if (i + 1 < n) v -= U1[o] * y1;
-          if (i + 2 < n) v -= U2[o] * y2;
-          const double y = v / U0[o];
-          X[o] = y;
-          y2 = y1;
-          y1 = y;
-          mx = fmax(mx, fabs(y));
-          nn2 += y * y;
+        for (int ib = n - 1; ib >= 0; ib -= CH) {
+          double xa[CH], u0[CH], u1[CH], u2[CH];
+#pragma unroll
+          for (int q = 0; q < CH; ++q) {
+            const int i = ib - q;
+            if (i >= 0) {
+              const int o = i * keep + k;   // < 2^17
+              xa[q] = itr == 0 ? 0.5 + (hash32((uint32_t)(i * 7919 + k * 104729 + 17)) >> 8) * (1.0 / 16777216.0) : X[o];
+              u0[q] = U0[o];
+              u1[q] = U1[o];
+              u2[q] = U2[o];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < CH; ++q) {
+            const int i = ib - q;
+            if (i >= 0) {
+              double v = xa[q];
+              if (i + 1 < n) v -= u1[q] * y1;
+              if (i + 2 < n) v -= u2[q] * y2;
+              const double y = v * u0[q];
+              X[i * keep + k] = y;
+              y2 = y1;
+              y1 = y;
+              mx = fmax(mx, fabs(y));
+              nn2 += y * y;
+            }
+          }
         }
         sc = (mx > 0) ? 1.0 / mx : 1.0;
         // orthogonalise against the previous (finished, unit) members of the cluster

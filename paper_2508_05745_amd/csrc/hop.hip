@@ -150,6 +150,7 @@ __global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int o
       }
 #pragma unroll
       for (int s = 0; s < SL; ++s) {
+        if (64 * s + 63 < k) continue;   // slot already solved (wave-uniform)
         const int j = lane + 64 * s;
         if (j == k) {
 #pragma unroll
