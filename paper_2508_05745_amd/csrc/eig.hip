@@ -304,15 +304,18 @@ __global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ A
     // A[r][c] -= 2 sum_k (V[r][k] conj(W[c][k]) + W[r][k] conj(V[c][k])), RB rows per wave and
     // SLOTS columns per lane register-blocked
     const int t0 = j0 + jb;
-    for (int r0 = t0 + wv * RB; r0 < n; r0 += (NT / 64) * RB) {
-      const int ns = (min(r0 + RB, n) - 1 - t0) / 64 + 1;   // slots with columns <= last row
-      // with the full register budget (one wave per SIMD and workgroup) the current values are
-      // loaded first, so that their latency overlaps the accumulation; under a tighter budget
-      // (WPE > 1) the other waves on the SIMD cover it
-      constexpr bool PRELOAD = WPE == 1;
-      c64d x[PRELOAD ? RB : 1][SLOTS], acc[RB][SLOTS];
+    // rows per wave in the trailing update: RB, except for the small instance under a tight
+    // register budget, where one row per wave leaves room to load ahead (measured faster)
+    constexpr int RBT = (WPE > 1 && NMAX <= 128) ? 1 : RB;
+    for (int r0 = t0 + wv * RBT; r0 < n; r0 += (NT / 64) * RBT) {
+      const int ns = (min(r0 + RBT, n) - 1 - t0) / 64 + 1;   // slots with columns <= last row
+      // the current values are loaded first, so that their latency overlaps the accumulation,
+      // where the registers allow it (full budget, or one row per wave); otherwise the other
+      // waves on the SIMD cover it
+      constexpr bool PRELOAD = WPE == 1 || RBT == 1;
+      c64d x[PRELOAD ? RBT : 1][SLOTS], acc[RBT][SLOTS];
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) {
+      for (int rr = 0; rr < RBT; ++rr) {
         const int r = r0 + rr;
         const c64d* row = A + (long long)r * n;
 #pragma unroll
@@ -323,9 +326,9 @@ __global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ A
         }
       }
       for (int kk = 0; kk < jb; ++kk) {
-        c64d vr[RB], wr[RB];
+        c64d vr[RBT], wr[RBT];
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr) {
+        for (int rr = 0; rr < RBT; ++rr) {
           const int r = min(r0 + rr, n - 1);
           vr[rr] = Vt[kk][r];
           wr[rr] = Wt[kk][r];
@@ -337,7 +340,7 @@ __global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ A
             const int c = min(t0 + lane + 64 * s, n - 1);
             const c64d vc = Vt[kk][c], wc = Wt[kk][c];
 #pragma unroll
-            for (int rr = 0; rr < RB; ++rr) {
+            for (int rr = 0; rr < RBT; ++rr) {
               c64d& q = acc[rr][s];
               q.re = fma(vr[rr].re, wc.re, q.re);
               q.re = fma(vr[rr].im, wc.im, q.re);
@@ -352,7 +355,7 @@ __global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ A
         }
       }
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) {
+      for (int rr = 0; rr < RBT; ++rr) {
         const int r = r0 + rr;
         if (r >= n) continue;
         c64d* row = A + (long long)r * n;

@@ -140,7 +140,7 @@ template <typename TA, typename TB, typename TACC, typename TC, bool CA, bool CB
 __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cplx<TA>* __restrict__ A,
                                                    int lda, long long sA, const cplx<TB>* __restrict__ B,
                                                    int ldb, long long sB, cplx<TC>* __restrict__ C, int ldc,
-                                                   long long sC, const double* __restrict__ alpha) {
+                                                   long long sC, const double* __restrict__ alpha, int lower) {
   using Mf = MfmaAcc<TACC>;
   using V = typename Mf::V;
   __shared__ TACC As_re[GB_K][GB_M + 4], As_im[GB_K][GB_M + 4];
@@ -150,6 +150,9 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cp
   B += bz * sB;
   C += bz * sC;
   const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
+  // lower: only the tiles holding elements on or below the diagonal are computed (the upper
+  // triangle of a Hermitian product that is read from its lower triangle alone)
+  if (lower && n0 >= m0 + GB_M) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wa = wv >> 1, wb = wv & 1, r16 = lane & 15, kq = lane >> 4;
   V acc_re[2][2], acc_im[2][2];
@@ -235,29 +238,30 @@ template <typename TA, typename TB, typename TACC, typename TC>
 static hipError_t gemm_dispatch(bool ca, bool cb, int M, int N, int K, const void* A, int lda,
                                 long long sA, const void* B, int ldb, long long sB, void* C,
                                 int ldc, long long sC, const double* alpha, int batch,
-                                hipStream_t st) {
+                                hipStream_t st, int lower) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch);
   auto a = (const cplx<TA>*)A;
   auto b = (const cplx<TB>*)B;
   auto c = (cplx<TC>*)C;
-  if (!ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
-  else if (ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
-  else if (!ca && cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
-  else hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha);
+  if (!ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower);
+  else if (ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower);
+  else if (!ca && cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower);
+  else hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower);
   return hipGetLastError();
 }
 
 hipError_t gemm(int prec_in, int prec_out, bool ca, bool cb, int M, int N, int K, const void* A,
                 int lda, long long sA, const void* B, int ldb, long long sB, void* C, int ldc,
-                long long sC, const double* alpha, int batch, hipStream_t st) {
+                long long sC, const double* alpha, int batch, hipStream_t st, bool lower) {
+  const int lo = lower ? 1 : 0;
   if (prec_in == 0 && prec_out == 0)
-    return gemm_dispatch<float, float, float, float>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
+    return gemm_dispatch<float, float, float, float>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo);
   if (prec_in == 0 && prec_out == 1)
-    return gemm_dispatch<float, float, float, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
+    return gemm_dispatch<float, float, float, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo);
   if (prec_in == 0 && prec_out == 2)   // c64 operands, FP64 accumulation and output
-    return gemm_dispatch<float, float, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
-  return gemm_dispatch<double, double, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st);
+    return gemm_dispatch<float, float, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo);
+  return gemm_dispatch<double, double, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo);
 }
 
 // ============================================================================ theta

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int o
     }
   // triangular solves, one wave per group of VG vectors solved together (independent chains
   // share the broadcasts of R); lane owns entries lane + 64 s
-  constexpr int SL = NMAX / 64, VG = 4;
+  constexpr int SL = NMAX / 64, VG = 8;
   const int nvec = other;
   for (int v0 = VG * wv; v0 < nvec; v0 += VG * (HT / 64)) {
     c64d x[VG][SL];

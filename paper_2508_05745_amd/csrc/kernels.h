@@ -45,10 +45,12 @@ struct GateRef {
 };
 
 // prec: 0 = complex64 storage / FP32 arithmetic, 1 = complex128 / FP64; gemm prec_out 2 =
-// c128 output with FP64 accumulation of c64 operands
+// c128 output with FP64 accumulation of c64 operands; lower: only the 64 x 64 output tiles that
+// hold elements on or below the diagonal are written (Hermitian products read from their lower
+// triangle)
 hipError_t gemm(int prec_in, int prec_out, bool conj_a, bool conj_b, int M, int N, int K, const void* A, int lda,
                 long long sA, const void* B, int ldb, long long sB, void* C, int ldc, long long sC,
-                const double* alpha, int batch, hipStream_t st);
+                const double* alpha, int batch, hipStream_t st, bool lower = false);
 hipError_t theta(int prec, int chi_l, int chi_m, int chi_r, const void* Cs, const void* Bs, long long s_traj,
                  void* out, long long s_out, const Mat4& gate, const GateRef& gref, double* partial, int n_traj,
                  hipStream_t st, int variant = -1);

@@ -515,10 +515,11 @@ int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, b
   const int n = left_to_right ? 2 * cl : 2 * cr;
   {
     ProfSec s(h, PC_GRAM);
+    // the eigensolver reads the lower triangle only
     if (left_to_right)
-      HIPCHK(gemm(p, 1, false, true, 2 * cl, 2 * cl, 2 * cr, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cl, L.s_gram, nullptr, T, h->st));
+      HIPCHK(gemm(p, 1, false, true, 2 * cl, 2 * cl, 2 * cr, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cl, L.s_gram, nullptr, T, h->st, true));
     else
-      HIPCHK(gemm(p, 1, true, false, 2 * cr, 2 * cr, 2 * cl, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cr, L.s_gram, nullptr, T, h->st));
+      HIPCHK(gemm(p, 1, true, false, 2 * cr, 2 * cr, 2 * cl, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cr, L.s_gram, nullptr, T, h->st, true));
   }
   const int kk = std::min(keep, D);
   HIPCHK(heev_all(h, n, kk, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
