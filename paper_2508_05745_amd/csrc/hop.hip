@@ -1,19 +1,32 @@
 // Centre hop by Cholesky factorisation of the Gram matrix (LDS-resident, FP64).
 //
 // Left-to-right hop of the orthogonality centre from site j to j+1: C_j (rows (a,s), n = chi_R
-// columns) = Q R with E = C^dag C = R^dag R (upper-triangular R); Q = C R^{-1} replaces C_j in
-// place (row by row, a wave per row) and R is written out for C_{j+1} = R B_{j+1}.
+// columns) = Q R with E = C^dag C = R^dag R (upper-triangular R); R is written out for
+// C_{j+1} = R B_{j+1}, inverted in place in LDS, and Q = C R^{-1} replaces C_j in place.
 // Right-to-left hop from j to j-1: C_j (n = chi_L rows, 2 chi_R columns) = R^dag Q with
-// E = C C^dag = R^dag R; Q = R^{-dag} C replaces C_j (column by column) and R is written out
-// for C_{j-1} = A_{j-1} R^dag.
-// Pivots below tol * max(diag E) are dropped (the row of R and the column of R^{-1} become
-// zero): such directions carry no weight of the state.
+// E = C C^dag = R^dag R; R is written out for C_{j-1} = A_{j-1} R^dag and Q = R^{-dag} C
+// replaces C_j.  The products with R^{-1} run on f64 MFMA over its nonzero triangle (a
+// triangular solve per vector spent most of its time moving broadcasts, not computing).
+// Pivots below tol * max(diag E) are dropped (the row of R and the row and column of R^{-1}
+// become zero): such directions carry no weight of the state.
 #include "common.h"
 #include "kernels.h"
 
 namespace mpsb {
 
 constexpr int HT = 512;
+
+// a double from another lane of the same quad (DPP quad_perm: 0xB1 = lane ^ 1, 0x4E = lane ^ 2)
+template <int CTRL>
+__device__ inline double quad_xor(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+__device__ inline v4d_t mfma64(double a, double b, v4d_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
 __device__ inline int pk(int i, int k, int n) { return i * n - (i * (i - 1)) / 2 + (k - i); }   // packed upper
 
@@ -22,7 +35,8 @@ __global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int o
                                                  long long sE, cplx<T>* __restrict__ C, long long sC,
                                                  cplx<T>* __restrict__ Rout, long long sR, double tol) {
   __shared__ c64d R[NMAX * (NMAX + 1) / 2];
-  __shared__ double piv[NMAX];
+  __shared__ double piv[NMAX], ipiv[NMAX];   // pivots R[c][c] and their inverses (0 if dropped)
+  __shared__ c64d tcol[NMAX];                 // a column of R while it is inverted
   __shared__ double red[HT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const c64d* E = Eg + blockIdx.x * sE;
@@ -58,7 +72,10 @@ __global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int o
         c64d v = R[pk(c, k, n)];
         R[pk(c, k, n)] = keep ? (k == c ? c64d{r, 0.0} : c64d{v.re / r, v.im / r}) : c64d{0, 0};
       }
-      if (tid == 0) piv[c] = r;
+      if (tid == 0) {
+        piv[c] = r;
+        ipiv[c] = keep ? 1.0 / r : 0.0;
+      }
       __syncthreads();
       // rows c+1 .. c0+cb-1 of the panel: E[i][k] -= conj(R[c][i]) R[c][k], i <= k
       if (keep) {
@@ -115,63 +132,122 @@ __global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int o
       c64d v = k >= i ? R[pk(i, k, n)] : c64d{0, 0};
       Ro[(long long)i * n + k] = cplx<T>{(T)v.re, (T)v.im};
     }
-  // triangular solves, one wave per group of VG vectors solved together (independent chains
-  // share the broadcasts of R); lane owns entries lane + 64 s
-  constexpr int SL = NMAX / 64, VG = 8;
-  const int nvec = other;
-  for (int v0 = VG * wv; v0 < nvec; v0 += VG * (HT / 64)) {
-    c64d x[VG][SL];
-    // load the vectors: L->R: row vidx of C (length n, contiguous); R->L: column vidx of C,
-    // conjugated (C^dag row), stride `other`
-#pragma unroll
-    for (int g = 0; g < VG; ++g)
-#pragma unroll
-      for (int s = 0; s < SL; ++s) {
-        const int k = lane + 64 * s, vidx = v0 + g;
-        cplx<T> v = {0, 0};
-        if (k < n && vidx < nvec) v = left_to_right ? Cj[(long long)vidx * n + k] : Cj[(long long)k * other + vidx];
-        x[g][s] = left_to_right ? c64d{(double)v.re, (double)v.im} : c64d{(double)v.re, -(double)v.im};
+  // R^{-1} in place (upper triangle, packed), column by column: column j of the inverse is
+  // -(1 / R[j][j]) Rinv[0:j, 0:j] R[0:j, j]; a dropped pivot gives a zero row and column, so
+  // the products below leave those directions out exactly as the substitution would
+  __syncthreads();   // R has been written out
+  // four lanes per row i (a DPP quad), each with two independent accumulation chains
+  static_assert(HT >= 4 * NMAX, "four lanes per row of the inverse");
+  for (int j = 0; j < n; ++j) {
+    for (int i = tid; i < j; i += HT) tcol[i] = R[pk(i, j, n)];
+    __syncthreads();
+    const double dj = ipiv[j];
+    const int i = tid >> 2, part = tid & 3;
+    double yr0 = 0.0, yi0 = 0.0, yr1 = 0.0, yi1 = 0.0;
+    if (i < j) {
+      const int base = pk(i, i, n) - i;   // Rinv[i][l] = R[base + l], l >= i
+      int l = i + part;
+      for (; l + 4 < j; l += 8) {
+        const c64d a0 = R[base + l], x0 = tcol[l], a1 = R[base + l + 4], x1 = tcol[l + 4];
+        yr0 = fma(a0.re, x0.re, yr0);
+        yr0 = fma(-a0.im, x0.im, yr0);
+        yi0 = fma(a0.re, x0.im, yi0);
+        yi0 = fma(a0.im, x0.re, yi0);
+        yr1 = fma(a1.re, x1.re, yr1);
+        yr1 = fma(-a1.im, x1.im, yr1);
+        yi1 = fma(a1.re, x1.im, yi1);
+        yi1 = fma(a1.im, x1.re, yi1);
       }
-    // solve q R = x: q_k = (x_k - sum_{i<k} q_i R[i][k]) / R[k][k], column-oriented updates
-    for (int k = 0; k < n; ++k) {
-      const int owner = k & 63, slot = k >> 6;
-      const double rkk = piv[k];
-      const double inv = rkk > 0 ? 1.0 / rkk : 0.0;
-      c64d qk[VG];
-#pragma unroll
-      for (int g = 0; g < VG; ++g) {
-        c64d xk = {0, 0};
-#pragma unroll
-        for (int s = 0; s < SL; ++s)
-          if (s == slot) xk = x[g][s];
-        xk.re = __shfl(xk.re, owner, 64);
-        xk.im = __shfl(xk.im, owner, 64);
-        qk[g] = c64d{xk.re * inv, xk.im * inv};
-      }
-#pragma unroll
-      for (int s = 0; s < SL; ++s) {
-        if (64 * s + 63 < k) continue;   // slot already solved (wave-uniform)
-        const int j = lane + 64 * s;
-        if (j == k) {
-#pragma unroll
-          for (int g = 0; g < VG; ++g) x[g][s] = qk[g];
-        } else if (j > k && j < n && rkk > 0) {
-          const c64d rkj = R[pk(k, j, n)];
-#pragma unroll
-          for (int g = 0; g < VG; ++g) x[g][s] = x[g][s] - qk[g] * rkj;
-        }
+      if (l < j) {
+        const c64d a0 = R[base + l], x0 = tcol[l];
+        yr0 = fma(a0.re, x0.re, yr0);
+        yr0 = fma(-a0.im, x0.im, yr0);
+        yi0 = fma(a0.re, x0.im, yi0);
+        yi0 = fma(a0.im, x0.re, yi0);
       }
     }
+    double yr = yr0 + yr1, yi = yi0 + yi1;
+    yr += quad_xor<0xB1>(yr);
+    yi += quad_xor<0xB1>(yi);
+    yr += quad_xor<0x4E>(yr);
+    yi += quad_xor<0x4E>(yi);
+    if (i < j && part == 0) R[pk(i, j, n)] = c64d{-dj * yr, -dj * yi};
+    if (tid == 0) R[pk(j, j, n)] = c64d{dj, 0.0};
+    __syncthreads();
+  }
+  // Q = C R^{-1} (L->R, C: other x n, row-major) or Q = R^{-dag} C (R->L, C: n x other), in
+  // place, on f64 MFMA over the nonzero triangle of R^{-1}.  A wave owns 16 rows (L->R) or
+  // 16 columns (R->L) of C with all their output tiles in registers, so it reads those rows /
+  // columns completely before it writes them.  Lane layout (f64 16x16x4): A[i][k] in lane
+  // i + 16 k, B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i % 4), register i / 4.
+  const int i16 = lane & 15, kq = lane >> 4;
+  constexpr int NT16 = NMAX / 16;
+  const int nt = (n + 15) / 16;
+  if (left_to_right) {
+    const int nvt = (other + 15) / 16;
+    for (int vt = wv; vt < nvt; vt += HT / 64) {
+      v4d_t ar[NT16], ai[NT16];
 #pragma unroll
-    for (int g = 0; g < VG; ++g)
+      for (int t = 0; t < NT16; ++t) ar[t] = ai[t] = v4d_t{0, 0, 0, 0};
+      const int v = 16 * vt + i16;
+      for (int l0 = 0; l0 < n; l0 += 4) {
+        const int l = l0 + kq;
+        cplx<T> cv = {0, 0};
+        if (v < other && l < n) cv = Cj[(long long)v * n + l];
+        const double cr = (double)cv.re, ci = (double)cv.im;
 #pragma unroll
-      for (int s = 0; s < SL; ++s) {
-        const int k = lane + 64 * s, vidx = v0 + g;
-        if (k < n && vidx < nvec) {
-          if (left_to_right) Cj[(long long)vidx * n + k] = cplx<T>{(T)x[g][s].re, (T)x[g][s].im};
-          else Cj[(long long)k * other + vidx] = cplx<T>{(T)x[g][s].re, (T)(-x[g][s].im)};
+        for (int t = 0; t < NT16; ++t) {
+          if (t < nt && l0 <= 16 * t + 15) {   // Rinv[l][c] = 0 for l > c
+            const int c = 16 * t + i16;
+            const c64d b = (l < n && c < n && l <= c) ? R[pk(l, c, n)] : c64d{0, 0};
+            ar[t] = mfma64(cr, b.re, ar[t]);
+            ar[t] = mfma64(-ci, b.im, ar[t]);
+            ai[t] = mfma64(cr, b.im, ai[t]);
+            ai[t] = mfma64(ci, b.re, ai[t]);
+          }
         }
       }
+#pragma unroll
+      for (int t = 0; t < NT16; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * vt + kq + 4 * q, c = 16 * t + i16;
+          if (t < nt && row < other && c < n) Cj[(long long)row * n + c] = cplx<T>{(T)ar[t][q], (T)ai[t][q]};
+        }
+    }
+  } else {
+    const int nvt = (other + 15) / 16;
+    for (int vt = wv; vt < nvt; vt += HT / 64) {
+      v4d_t ar[NT16], ai[NT16];
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) ar[t] = ai[t] = v4d_t{0, 0, 0, 0};
+      const int v = 16 * vt + i16;
+      for (int l0 = 0; l0 < n; l0 += 4) {
+        const int l = l0 + kq;
+        cplx<T> cv = {0, 0};
+        if (v < other && l < n) cv = Cj[(long long)l * other + v];
+        const double br = (double)cv.re, bi = (double)cv.im;
+#pragma unroll
+        for (int t = 0; t < NT16; ++t) {
+          if (t < nt && l0 <= 16 * t + 15) {   // conj(Rinv[l][r]) = 0 for l > r
+            const int r = 16 * t + i16;
+            const c64d a = (l < n && r < n && l <= r) ? R[pk(l, r, n)] : c64d{0, 0};
+            // A[r][l] = conj(Rinv[l][r])
+            ar[t] = mfma64(a.re, br, ar[t]);
+            ar[t] = mfma64(a.im, bi, ar[t]);
+            ai[t] = mfma64(a.re, bi, ai[t]);
+            ai[t] = mfma64(-a.im, br, ai[t]);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT16; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * t + kq + 4 * q, col = 16 * vt + i16;
+          if (t < nt && r < n && col < other) Cj[(long long)r * other + col] = cplx<T>{(T)ar[t][q], (T)ai[t][q]};
+        }
+    }
   }
 }
 
