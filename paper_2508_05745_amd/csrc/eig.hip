@@ -859,7 +859,7 @@ __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* _
   // a time: conflict-free without padding), the partial W of waves 1-3 (wave 0 reduces in
   // registers) and the reduced W
   __shared__ double Zr[NMAX][16], Zi[NMAX][16];
-  __shared__ double Wp[3][2][16][16];
+  __shared__ __align__(16) double Wp[3][2][16][16];   // partial W sums, then this block's T factor
   __shared__ double Wr[16][16], Wi[16][16];
   // XCD-aware numbering: the panels of a matrix are consecutive logical ids on one XCD
   const int G = gridDim.x, w = blockIdx.x;
@@ -885,37 +885,45 @@ __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* _
   const int nblk = nref > 0 ? (nref + 15) / 16 : 0;
   for (int blk = nblk - 1; blk >= 0; --blk) {
     const int j0 = 16 * blk, nb = min(16, nref - j0);
-    // W[a][c] = sum_rows conj(V[row][a]) Z[row][c]; the waves split the rows, two
-    // independent accumulator chains per wave (rows i0 and i0 + 16)
-    v4d_t wr0 = {0, 0, 0, 0}, wi0 = {0, 0, 0, 0}, wr1 = {0, 0, 0, 0}, wi1 = {0, 0, 0, 0};
-    for (int i0 = j0 + 1 + 4 * wv; i0 < n; i0 += 32) {
-      const int row0 = i0 + kq, row1 = i0 + 16 + kq;
-      c64d v0 = {0, 0}, v1 = {0, 0};
-      double zr0 = 0, zi0 = 0, zr1 = 0, zi1 = 0;
-      if (row0 < n) {
-        if (r16 < nb && row0 > j0 + r16) v0 = A[(long long)row0 * n + j0 + r16];
-        zr0 = Zr[row0][r16];
-        zi0 = Zi[row0][r16];
+    // this block's T factor, one element per thread: loaded now, so that its latency is hidden
+    // behind the W accumulation, and put into LDS once the partial W sums are consumed
+    const c64d tfac = Tg[(long long)blk * 256 + tid];
+    // W[a][c] = sum_rows conj(V[row][a]) Z[row][c]; the waves split the rows, four
+    // independent accumulator chains per wave (rows i0, i0 + 16, i0 + 32, i0 + 48)
+    v4d_t wr[4], wi[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) wr[h] = wi[h] = v4d_t{0, 0, 0, 0};
+    for (int i0 = j0 + 1 + 4 * wv; i0 < n; i0 += 64) {
+      c64d v[4];
+      double zr[4], zi[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int row = i0 + 16 * h + kq;
+        v[h] = c64d{0, 0};
+        zr[h] = zi[h] = 0;
+        if (row < n) {
+          if (r16 < nb && row > j0 + r16) v[h] = A[(long long)row * n + j0 + r16];
+          zr[h] = Zr[row][r16];
+          zi[h] = Zi[row][r16];
+        }
       }
-      if (row1 < n) {
-        if (r16 < nb && row1 > j0 + r16) v1 = A[(long long)row1 * n + j0 + r16];
-        zr1 = Zr[row1][r16];
-        zi1 = Zi[row1][r16];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        wr[h] = mfma64(v[h].re, zr[h], wr[h]);
+        wi[h] = mfma64(v[h].re, zi[h], wi[h]);
       }
-      wr0 = mfma64(v0.re, zr0, wr0);
-      wr1 = mfma64(v1.re, zr1, wr1);
-      wi0 = mfma64(v0.re, zi0, wi0);
-      wi1 = mfma64(v1.re, zi1, wi1);
-      wr0 = mfma64(v0.im, zi0, wr0);
-      wr1 = mfma64(v1.im, zi1, wr1);
-      wi0 = mfma64(-v0.im, zr0, wi0);
-      wi1 = mfma64(-v1.im, zr1, wi1);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        wr[h] = mfma64(v[h].im, zi[h], wr[h]);
+        wi[h] = mfma64(-v[h].im, zr[h], wi[h]);
+      }
     }
+    const v4d_t wr0 = (wr[0] + wr[1]) + (wr[2] + wr[3]), wi0 = (wi[0] + wi[1]) + (wi[2] + wi[3]);
     if (wv > 0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        Wp[wv - 1][0][kq + 4 * r][r16] = wr0[r] + wr1[r];
-        Wp[wv - 1][1][kq + 4 * r][r16] = wi0[r] + wi1[r];
+        Wp[wv - 1][0][kq + 4 * r][r16] = wr0[r];
+        Wp[wv - 1][1][kq + 4 * r][r16] = wi0[r];
       }
     }
     __syncthreads();
@@ -923,18 +931,21 @@ __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* _
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = kq + 4 * r;
-        Wr[a][r16] = wr0[r] + wr1[r] + Wp[0][0][a][r16] + Wp[1][0][a][r16] + Wp[2][0][a][r16];
-        Wi[a][r16] = wi0[r] + wi1[r] + Wp[0][1][a][r16] + Wp[1][1][a][r16] + Wp[2][1][a][r16];
+        Wr[a][r16] = wr0[r] + Wp[0][0][a][r16] + Wp[1][0][a][r16] + Wp[2][0][a][r16];
+        Wi[a][r16] = wi0[r] + Wp[0][1][a][r16] + Wp[1][1][a][r16] + Wp[2][1][a][r16];
       }
     }
     __syncthreads();
+    // the partial sums have been read: their space holds T for the product below
+    c64d* Ts = (c64d*)&Wp[0][0][0][0];
+    Ts[tid] = tfac;
+    __syncthreads();
     {
-      // W <- T W (T upper triangular, read from the workspace)
+      // W <- T W (T upper triangular)
       const int a = tid >> 4, c = tid & 15;
-      const c64d* Tb = Tg + (long long)blk * 256 + a * 16;
       double tr = 0, ti = 0;
       for (int b = a; b < nb; ++b) {
-        const c64d t = Tb[b];
+        const c64d t = Ts[a * 16 + b];
         tr += t.re * Wr[b][c] - t.im * Wi[b][c];
         ti += t.re * Wi[b][c] + t.im * Wr[b][c];
       }
