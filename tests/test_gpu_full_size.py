@@ -107,6 +107,16 @@ def test_saturated_chi128(prec):
     _check_replays(c, 128, 2006, out, prec, f"prec{prec}")
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_saturated_chi24(prec):
+    """Bond capacity 24, not a multiple of the 16-wide MFMA tiles: the centre hops (n = 24,
+    24 x 48 and 48 x 24 centre tensors), the truncation Grams (m = 48) and the theta tiles all
+    run on partial tiles once the middle bonds saturate."""
+    c = I.brickwork(12, 10, seed=1024, channel=I.depolarizing(0.02))
+    out = run_gpu_sampled(c, 24, 64, 2024, prec, 3, c.depth, [0, 63])
+    _check_replays(c, 24, 2024, out, prec, f"chi24 prec{prec}")
+
+
 @pytest.mark.parametrize("prec,n_traj", [(0, 2048), (1, 1024)])
 def test_wide_chi256_first_layer(prec, n_traj):
     wl = I.config_wide(chi=256, n_traj=n_traj)
