@@ -482,11 +482,42 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
   for (int i = 0; i + 1 < n; ++i) emax2 = fmax(emax2, se2[i]);
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
 
+  // ---- shared multisection: the counts below 2 ET points (the Gershgorin ends and a
+  // geometric grid between the zero-weight cut and the upper end, where the kept eigenvalues
+  // of a Gram matrix lie), one Sturm pass with two points per thread; every eigenvalue then
+  // starts its trisection from the tightest bracket of the grid
+  __shared__ double gx[2 * ET];
+  __shared__ int gc[2 * ET];
+  {
+    constexpr int NPT = 2 * ET;
+    const double top = ghi, bot = fmax(cut_lb, top * 1e-300);
+    const double lr = (top > bot && bot > 0) ? log(top / bot) : 0.0;
+    double x[2];
+    for (int h = 0; h < 2; ++h) {
+      const int p = 2 * tid + h;
+      if (p == 0) x[h] = glo;
+      else if (p == NPT - 1 || !(lr > 0)) x[h] = ghi;
+      else x[h] = fmin(ghi, fmax(glo, bot * exp(lr * (double)(p - 1) / (double)(NPT - 2))));
+    }
+    int c0, c1;
+    sturm_count2(n, sd, se2, x[0], x[1], pivmin, c0, c1);
+    gx[2 * tid] = x[0];
+    gx[2 * tid + 1] = x[1];
+    gc[2 * tid] = c0;
+    gc[2 * tid + 1] = c1;
+  }
+  __syncthreads();
+
   // ---- bisection for the keep largest eigenvalues
   for (int k = tid; k < keep; k += ET) {
     const int idx = n - 1 - k;   // ascending index
-    // trisection: count(lo) <= idx < count(hi) is kept
+    // trisection: count(lo) <= idx < count(hi) is kept; start from the grid points (ascending,
+    // counts nondecreasing) that bracket idx most tightly
     double lo = glo, hi = ghi;
+    for (int p = 0; p < 2 * ET; ++p) {
+      if (gc[p] <= idx) lo = fmax(lo, gx[p]);
+      else hi = fmin(hi, gx[p]);
+    }
     for (int it = 0; it < 140; ++it) {
       const double w = hi - lo;
       const double m1 = lo + w * (1.0 / 3.0), m2 = lo + w * (2.0 / 3.0);
