@@ -163,36 +163,57 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cp
       acc_re[i][j] = V{0, 0, 0, 0};
       acc_im[i][j] = V{0, 0, 0, 0};
     }
-  for (int k0 = 0; k0 < K; k0 += GB_K) {
+  // the next k-slice is loaded into registers while the current one is multiplied from LDS
+  cplx<TA> pa[4];
+  cplx<TB> pb[4];
+  auto load_slice = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int e = tid + 256 * r;
+      const int e = tid + 256 * r;
       int mm, kk;
       if (!CA) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
-      int m = m0 + mm, k = k0 + kk;
+      const int m = m0 + mm, k = k0 + kk;
       cplx<TA> v = {0, 0};
       if (m < M && k < K) {
         if (!CA) v = A[(long long)m * lda + k];
         else { v = A[(long long)k * lda + m]; v.im = -v.im; }
       }
-      As_re[kk][mm] = (TACC)v.re;
-      As_im[kk][mm] = (TACC)v.im;
+      pa[r] = v;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int e = tid + 256 * r;
+      const int e = tid + 256 * r;
       int nn, kk;
       if (!CB) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
-      int n = n0 + nn, k = k0 + kk;
+      const int n = n0 + nn, k = k0 + kk;
       cplx<TB> v = {0, 0};
       if (n < N && k < K) {
         if (!CB) v = B[(long long)k * ldb + n];
         else { v = B[(long long)n * ldb + k]; v.im = -v.im; }
       }
-      Bs_re[kk][nn] = (TACC)v.re;
-      Bs_im[kk][nn] = (TACC)v.im;
+      pb[r] = v;
+    }
+  };
+  load_slice(0);
+  for (int k0 = 0; k0 < K; k0 += GB_K) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int mm, kk;
+      if (!CA) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
+      As_re[kk][mm] = (TACC)pa[r].re;
+      As_im[kk][mm] = (TACC)pa[r].im;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int nn, kk;
+      if (!CB) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
+      Bs_re[kk][nn] = (TACC)pb[r].re;
+      Bs_im[kk][nn] = (TACC)pb[r].im;
     }
     __syncthreads();
+    if (k0 + GB_K < K) load_slice(k0 + GB_K);
 #pragma unroll
     for (int k4 = 0; k4 < GB_K / 4; ++k4) {
       const int kk = 4 * k4 + kq;
