@@ -244,12 +244,12 @@ def main():
         return
     if args.mixed:
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU", "n_gpus": args.gpus}))
+            print(json.dumps({"error": "this library runs on one GPU", "n_gpus": args.gpus}))
             sys.exit(2)
         bench_mixed(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding (disjoint "
+        print(json.dumps({"error": "this library runs on one GPU; multi-GPU sharding (disjoint "
                                    "trajectory ranges) is designed but not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)

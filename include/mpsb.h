@@ -34,7 +34,7 @@ extern "C" {
 #define MPSB_EINVAL -1  /* bad shape or argument, non-unitary gate                     */
 #define MPSB_ENOMEM -2  /* caller buffer too small / sizes beyond the supported maxima  */
 #define MPSB_EHIP -3    /* a HIP runtime call failed                                   */
-#define MPSB_ENOTSUP -4 /* combination not supported by this build                      */
+#define MPSB_ENOTSUP -4 /* combination not supported by this library                    */
 #define MPSB_ENUM -5    /* non-finite value, or a forced branch with zero probability  */
 #define MPSB_EKRAUS -6  /* Kraus set not trace preserving (sum K^dag K != I)            */
 
