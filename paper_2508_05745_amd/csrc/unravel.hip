@@ -28,44 +28,68 @@ using cd = c64d;
 __device__ inline cd cz() { return cd{0.0, 0.0}; }
 __device__ inline double cabs_(cd a) { return sqrt(norm2(a)); }
 
-// cyclic Jacobi eigen-decomposition of a real symmetric n x n matrix (n <= 8), in place:
-// on exit a holds the eigenvalues on its diagonal, v the eigenvectors (columns).
+// cyclic Jacobi eigen-decomposition of a real symmetric n x n matrix (n <= NMAX), in place:
+// on exit a holds the eigenvalues on its diagonal, v the eigenvectors (columns).  The sweeps run
+// on local copies with every index fixed at compile time (pairs and rows unrolled over NMAX,
+// n as a guard), so that the matrices stay in registers rather than in per-lane scratch.
 template <int NMAX>
-__device__ void jacobi_sym(int n, double (&a)[NMAX][NMAX], double (&v)[NMAX][NMAX]) {
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) v[i][j] = (i == j) ? 1.0 : 0.0;
+__device__ void jacobi_sym(int n, double (&a_io)[NMAX][NMAX], double (&v_io)[NMAX][NMAX]) {
+  double a[NMAX][NMAX], v[NMAX][NMAX];
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+      a[i][j] = (i < n && j < n) ? a_io[i][j] : 0.0;
+      v[i][j] = (i == j) ? 1.0 : 0.0;
+    }
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0, tot = 0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i)
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j) {
         tot += a[i][j] * a[i][j];
         if (i != j) off += a[i][j] * a[i][j];
       }
     if (off <= 1e-34 * tot || off == 0.0) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        double apq = a[p][q];
-        if (apq == 0.0) continue;
-        double zeta = (a[q][q] - a[p][p]) / (2.0 * apq);
-        double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int k = 0; k < n; ++k) {
-          double akp = a[k][p], akq = a[k][q];
-          a[k][p] = c * akp - s * akq;
-          a[k][q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          double apk = a[p][k], aqk = a[q][k];
-          a[p][k] = c * apk - s * aqk;
-          a[q][k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          double vkp = v[k][p], vkq = v[k][q];
-          v[k][p] = c * vkp - s * vkq;
-          v[k][q] = s * vkp + c * vkq;
+#pragma unroll
+    for (int p = 0; p < NMAX - 1; ++p)
+#pragma unroll
+      for (int q = p + 1; q < NMAX; ++q) {
+        const double apq = a[p][q];
+        if (q < n && apq != 0.0) {
+          double zeta = (a[q][q] - a[p][p]) / (2.0 * apq);
+          double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
+          for (int k = 0; k < NMAX; ++k) {
+            double akp = a[k][p], akq = a[k][q];
+            a[k][p] = c * akp - s * akq;
+            a[k][q] = s * akp + c * akq;
+          }
+#pragma unroll
+          for (int k = 0; k < NMAX; ++k) {
+            double apk = a[p][k], aqk = a[q][k];
+            a[p][k] = c * apk - s * aqk;
+            a[q][k] = s * apk + c * aqk;
+          }
+#pragma unroll
+          for (int k = 0; k < NMAX; ++k) {
+            double vkp = v[k][p], vkq = v[k][q];
+            v[k][p] = c * vkp - s * vkq;
+            v[k][q] = s * vkp + c * vkq;
+          }
         }
       }
   }
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j)
+      if (i < n && j < n) {
+        a_io[i][j] = a[i][j];
+        v_io[i][j] = v[i][j];
+      }
 }
 
 __device__ inline int first_argmax_c(const cd* a, int n, int stride) {
