@@ -145,12 +145,17 @@ __device__ void optimal_mixing(const cd (&rho)[2][2], const cd (&K)[4][2][2], in
   cd V[4][4];
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? cd{1.0, 0.0} : cz();
+  // (pairs unrolled with r as a guard, so that ph and V keep compile-time indices)
   for (int sweep = 0; sweep < 30; ++sweep) {
     bool rotated = false;
-    for (int i = 0; i < r - 1; ++i)
-      for (int j = i + 1; j < r; ++j) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 4; ++j) {
+        if (j >= r) continue;
         double al = 0, be = 0;
         cd ga = cz();
+#pragma unroll
         for (int c = 0; c < 4; ++c) {
           al += norm2(ph[c][i]);
           be += norm2(ph[c][j]);
@@ -163,6 +168,7 @@ __device__ void optimal_mixing(const cd (&rho)[2][2], const cd (&K)[4][2][2], in
         double zeta = (be - al) / (2.0 * g);
         double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
           cd ai = ph[k][i], aj = eph * ph[k][j];
           ph[k][i] = c * ai - s * aj;
@@ -191,10 +197,19 @@ __device__ void optimal_mixing(const cd (&rho)[2][2], const cd (&K)[4][2][2], in
     if (sig[ord[i]] > 1e-12 * smax) rank++;
   cd v[4][4];    // [component][k], k < rank
   cd Vs[4][4];   // sorted V columns
+#pragma unroll
   for (int k = 0; k < 4; ++k)
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
-      v[c][k] = (k < rank) ? ph[c][ord[k]] : cz();
-      Vs[c][k] = V[c][ord[k]];
+      cd pv = cz(), vv = cz();
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (ord[k] == t) {
+          pv = ph[c][t];
+          vv = V[c][t];
+        }
+      v[c][k] = (k < rank) ? pv : cz();
+      Vs[c][k] = vv;
     }
   // tau = v^dag v~  (rank x rank)
   cd tau[4][4];
