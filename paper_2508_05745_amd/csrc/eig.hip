@@ -882,13 +882,15 @@ __global__ __launch_bounds__(256) void k_bt_tfac(int n, const c64d* __restrict__
   }
 }
 
-template <int NMAX>
-__global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* __restrict__ Ag, long long sA,
+template <int NMAX, int BNT>
+__global__ __launch_bounds__(BNT, BNT / 128) void k_bt_panel(int n, int keep, const c64d* __restrict__ Ag, long long sA,
                                                   const double* __restrict__ ws, long long sW, c64d* __restrict__ Zg,
                                                   long long sZ, int n_panels) {
   // 80 KB of LDS so that two panels share a CU: the panel (rows of 16 doubles read 4 rows at
-  // a time: conflict-free without padding), the partial W of waves 1-3 (wave 0 reduces in
-  // registers) and the reduced W
+  // a time: conflict-free without padding), three slots of partial W (and, while W is folded,
+  // the W arrays as a fourth) and the reduced W
+  static_assert(BNT == 256 || BNT == 512, "four or eight waves");
+  constexpr int NW = BNT / 64;
   __shared__ double Zr[NMAX][16], Zi[NMAX][16];
   __shared__ __align__(16) double Wp[3][2][16][16];   // partial W sums, then this block's T factor
   __shared__ double Wr[16][16], Wi[16][16];
@@ -905,7 +907,7 @@ __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* _
   c64d* Z = Zg + mat * sZ;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r16 = lane & 15, kq = lane >> 4;
   const int c0 = panel * 16, pc = min(16, keep - c0);
-  for (int e = tid; e < n * 16; e += 256) {
+  for (int e = tid; e < n * 16; e += BNT) {
     const int r = e >> 4, c = e & 15;
     const double x = c < pc ? X[(long long)r * keep + c0 + c] : 0.0;
     Zr[r][c] = om[r].re * x;
@@ -916,19 +918,21 @@ __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* _
   const int nblk = nref > 0 ? (nref + 15) / 16 : 0;
   for (int blk = nblk - 1; blk >= 0; --blk) {
     const int j0 = 16 * blk, nb = min(16, nref - j0);
-    // this block's T factor, one element per thread: loaded now, so that its latency is hidden
-    // behind the W accumulation, and put into LDS once the partial W sums are consumed
-    const c64d tfac = Tg[(long long)blk * 256 + tid];
-    // W[a][c] = sum_rows conj(V[row][a]) Z[row][c]; the waves split the rows, four
-    // independent accumulator chains per wave (rows i0, i0 + 16, i0 + 32, i0 + 48)
-    v4d_t wr[4], wi[4];
+    // this block's T factor, one element per thread of the first 256: loaded now, so that its
+    // latency is hidden behind the W accumulation, and put into LDS once the partial W sums
+    // are consumed
+    const c64d tfac = tid < 256 ? Tg[(long long)blk * 256 + tid] : c64d{0, 0};
+    // W[a][c] = sum_rows conj(V[row][a]) Z[row][c]; groups of four waves take chunks of 16 NCH
+    // rows, NCH independent accumulator chains per wave (rows i0, i0 + 16, ...)
+    constexpr int NCH = NW == 8 ? 2 : 4;   // accumulator chains per wave (register budget)
+    v4d_t wr[NCH], wi[NCH];
 #pragma unroll
-    for (int h = 0; h < 4; ++h) wr[h] = wi[h] = v4d_t{0, 0, 0, 0};
-    for (int i0 = j0 + 1 + 4 * wv; i0 < n; i0 += 64) {
-      c64d v[4];
-      double zr[4], zi[4];
+    for (int h = 0; h < NCH; ++h) wr[h] = wi[h] = v4d_t{0, 0, 0, 0};
+    for (int i0 = j0 + 1 + 4 * (wv & 3) + 16 * NCH * (wv >> 2); i0 < n; i0 += 4 * NCH * NW) {
+      c64d v[NCH];
+      double zr[NCH], zi[NCH];
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
+      for (int h = 0; h < NCH; ++h) {
         const int row = i0 + 16 * h + kq;
         v[h] = c64d{0, 0};
         zr[h] = zi[h] = 0;
@@ -939,18 +943,57 @@ __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* _
         }
       }
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
+      for (int h = 0; h < NCH; ++h) {
         wr[h] = mfma64(v[h].re, zr[h], wr[h]);
         wi[h] = mfma64(v[h].re, zi[h], wi[h]);
       }
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
+      for (int h = 0; h < NCH; ++h) {
         wr[h] = mfma64(v[h].im, zi[h], wr[h]);
         wi[h] = mfma64(-v[h].im, zr[h], wi[h]);
       }
     }
-    const v4d_t wr0 = (wr[0] + wr[1]) + (wr[2] + wr[3]), wi0 = (wi[0] + wi[1]) + (wi[2] + wi[3]);
-    if (wv > 0) {
+    v4d_t wr0, wi0;
+    if constexpr (NCH == 4) {
+      wr0 = (wr[0] + wr[1]) + (wr[2] + wr[3]);
+      wi0 = (wi[0] + wi[1]) + (wi[2] + wi[3]);
+    } else {
+      wr0 = wr[0] + wr[1];
+      wi0 = wi[0] + wi[1];
+    }
+    if constexpr (NW == 8) {
+      // first fold: waves 4-7 hand their sums to waves 0-3 (slots Wp[0..2] and the W arrays,
+      // which the previous block no longer reads)
+      if (wv >= 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = kq + 4 * r;
+          if (wv < 7) {
+            Wp[wv - 4][0][a][r16] = wr0[r];
+            Wp[wv - 4][1][a][r16] = wi0[r];
+          } else {
+            Wr[a][r16] = wr0[r];
+            Wi[a][r16] = wi0[r];
+          }
+        }
+      }
+      __syncthreads();
+      if (wv < 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = kq + 4 * r;
+          if (wv < 3) {
+            wr0[r] += Wp[wv][0][a][r16];
+            wi0[r] += Wp[wv][1][a][r16];
+          } else {
+            wr0[r] += Wr[a][r16];
+            wi0[r] += Wi[a][r16];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (wv > 0 && wv < 4) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         Wp[wv - 1][0][kq + 4 * r][r16] = wr0[r];
@@ -969,24 +1012,28 @@ __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* _
     __syncthreads();
     // the partial sums have been read: their space holds T for the product below
     c64d* Ts = (c64d*)&Wp[0][0][0][0];
-    Ts[tid] = tfac;
+    if (tid < 256) Ts[tid] = tfac;
     __syncthreads();
     {
-      // W <- T W (T upper triangular)
-      const int a = tid >> 4, c = tid & 15;
+      // W <- T W (T upper triangular), one (a, c) per thread of the first 256
+      const int a = (tid >> 4) & 15, c = tid & 15;
       double tr = 0, ti = 0;
-      for (int b = a; b < nb; ++b) {
-        const c64d t = Ts[a * 16 + b];
-        tr += t.re * Wr[b][c] - t.im * Wi[b][c];
-        ti += t.re * Wi[b][c] + t.im * Wr[b][c];
+      if (tid < 256) {
+        for (int b = a; b < nb; ++b) {
+          const c64d t = Ts[a * 16 + b];
+          tr += t.re * Wr[b][c] - t.im * Wi[b][c];
+          ti += t.re * Wi[b][c] + t.im * Wr[b][c];
+        }
       }
       __syncthreads();
-      Wr[a][c] = tr;
-      Wi[a][c] = ti;
+      if (tid < 256) {
+        Wr[a][c] = tr;
+        Wi[a][c] = ti;
+      }
     }
     __syncthreads();
     // Z -= V W over 16-row tiles (rows <= j0 get zero from the masked V)
-    for (int rt = (j0 + 1) / 16 + wv; 16 * rt < n; rt += 4) {
+    for (int rt = (j0 + 1) / 16 + wv; 16 * rt < n; rt += NW) {
       const int r0 = 16 * rt;
       v4d_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
 #pragma unroll
@@ -1011,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_bt_panel(int n, int keep, const c64d* _
     }
     __syncthreads();
   }
-  for (int e = tid; e < n * 16; e += 256) {
+  for (int e = tid; e < n * 16; e += BNT) {
     const int r = e >> 4, c = e & 15;
     if (c < pc) Z[(long long)r * keep + c0 + c] = c64d{Zr[r][c], Zi[r][c]};
   }
@@ -1048,9 +1095,9 @@ hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long
       const long long blocks = (long long)np * batch;
       if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
       if (n <= 256)
-        hipLaunchKernelGGL((k_bt_panel<256>), dim3((unsigned)blocks), dim3(256), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np);
+        hipLaunchKernelGGL((k_bt_panel<256, 512>), dim3((unsigned)blocks), dim3(512), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np);
       else
-        hipLaunchKernelGGL((k_bt_panel<512>), dim3((unsigned)blocks), dim3(256), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np);
+        hipLaunchKernelGGL((k_bt_panel<512, 512>), dim3((unsigned)blocks), dim3(512), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np);
       break;
     }
   }
