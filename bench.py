@@ -57,7 +57,7 @@ def tridiag_bytes(m):
 
 def algorithmic_work(n, chi, layers, n_traj):
     """Algorithmic work of the timed launches, per kernel class: flops for the contractions
-    (theta 32*cl*cm*cr, Gram 64*cl^2*cr (full Hermitian product), recomposition 32 D cl cr),
+    (theta 32*cl*cm*cr, Gram 32*cl^2*cr (the Hermitian half), recomposition 32 D cl cr),
     back-transformation 8 m^2 D, and for the tridiagonalisations both the flops (16/3 m^3)
     and the HBM bytes of `tridiag_bytes` (m = Gram dimension)."""
     cp = caps(n, chi)
@@ -73,7 +73,7 @@ def algorithmic_work(n, chi, layers, n_traj):
             D = cm
             w["theta"] += 32.0 * cl * cm * cr
             m = 2 * cl if par == 0 else 2 * cr
-            w["gram"] += 32.0 * m * cl * cr
+            w["gram"] += 16.0 * m * cl * cr
             cls = next(k for k, (lo, hi) in TRIDIAG.items() if lo <= m <= hi)
             w[cls] += 16.0 / 3.0 * m ** 3
             by[cls] += tridiag_bytes(m)
