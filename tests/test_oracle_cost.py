@@ -9,7 +9,9 @@ from paper_2508_05745_amd import inputs as I
 
 def _u_opt(rho, k):
     w = U.optimal_mixing(rho, k)["W"]
-    return w.T.copy()     # K'_j = sum_i U_ji K_i  <=>  U = W^T
+    u = np.zeros((4, 4), dtype=np.complex128)
+    u[:, : w.shape[0]] = w.T  # K'_j = sum_i U_ji K_i  <=>  U = W^T (zero columns past r)
+    return u
 
 
 def test_generators_are_a_hermitian_basis():
@@ -65,3 +67,41 @@ def test_rho_from_theta_is_reduced_state():
         psi = t.transpose(1, 0, 2, 3).reshape(2, -1)      # target index first
         assert np.allclose(r, psi @ psi.conj().T, atol=1e-15)
         assert abs(np.trace(r) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_renyi2_cost_at_optimum_closed_form(seed):
+    """Every branch of Wootters' decomposition is a pure two-qubit state of concurrence C
+    (appendix on Wootters' optimal decomposition), whose target purity is 1 - C^2/2; so the
+    Renyi-2 cost at the optimal mixing is -log2(1 - C^2/2) (base-2 logarithm), and, the
+    function -log2(1 - c^2/2) being convex and increasing in c, no Haar-random mixing does
+    better."""
+    k = [I.depolarizing(0.03 + 0.04 * seed), I.amplitude_damping(0.1 + 0.1 * seed),
+         I.dephasing(0.05 + 0.1 * seed)][seed % 3]
+    rho = I.random_density_matrices(1, 80 + seed)[0]
+    out = U.optimal_mixing(rho, k)
+    c = out["C"]
+    assert c > 1e-3
+    f = CO.cost(rho, k, _u_opt(rho, k), CO.KIND_RENYI2)
+    assert f == pytest.approx(-np.log2(1 - c * c / 2), rel=1e-11, abs=1e-13)
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(50):
+        assert CO.cost(rho, k, I.haar_unitary(rng, 4), CO.KIND_RENYI2) >= f - 1e-12
+
+
+def test_renyi2_cost_special_values():
+    """Closed values: the identity channel on the maximally mixed qubit leaves one branch
+    of target purity 1/2, so f_R2 = -log2(1/2) = 1 bit and f_lin = 1/2; a pure target state
+    gives pure branches (f = 0) for any mixing."""
+    k = np.eye(2, dtype=np.complex128)[None]
+    rho = np.eye(2, dtype=np.complex128) / 2
+    u = np.eye(4, dtype=np.complex128)
+    assert CO.cost(rho, k, u, CO.KIND_RENYI2) == pytest.approx(1.0, abs=1e-15)
+    assert CO.cost(rho, k, u, CO.KIND_LINEAR) == pytest.approx(0.5, abs=1e-15)
+    pure = np.array([[0.36, 0.48], [0.48, 0.64]], dtype=np.complex128)
+    rng = np.random.default_rng(5)
+    for kk in (I.depolarizing(0.2), I.amplitude_damping(0.3)):
+        for _ in range(5):
+            uu = I.haar_unitary(rng, 4)
+            assert abs(CO.cost(pure, kk, uu, CO.KIND_RENYI2)) < 1e-13
+            assert abs(CO.cost(pure, kk, uu, CO.KIND_LINEAR)) < 1e-13

@@ -71,17 +71,50 @@ def test_norm_preserved_and_truncation_weight():
     assert max(m.bond_dims()) <= 4
 
 
-def test_single_bond_eckart_young():
-    """Truncating one bond: ||psi - P psi||^2 equals the discarded weight."""
-    rng = np.random.default_rng(9)
-    psi = rng.standard_normal(64) + 1j * rng.standard_normal(64)
-    psi /= np.linalg.norm(psi)
-    mat = psi.reshape(8, 8)
-    u, s, vh = np.linalg.svd(mat)
-    d = 3
-    proj = (u[:, :d] * s[:d]) @ vh[:d]
-    eps = np.sum(s[d:] ** 2)
-    assert np.linalg.norm(mat - proj) ** 2 == pytest.approx(eps, abs=1e-14)
+def _truncating_step(n, q, chi, seed):
+    """An entangled n-qubit trajectory state (exact, noisy, several layers), then one
+    gate-step on (q, q+1) twice from the same state and seeds: untruncated (the state before
+    the approximation) and truncated to chi.  Returns (psi_full, psi_trunc, eps)."""
+    import copy
+    c = I.brickwork(n, 8, seed=seed, channel=I.depolarizing(0.05))
+    layer = 7
+    m, _ = mps.trajectory(c, 2 ** n, 0, seed, layers=layer)
+    full, trunc = copy.deepcopy(m), copy.deepcopy(m)
+    eps_full = mps.gate_step(full, layer, q, c, 2 ** n, 0, seed, U.MODE_OPTIMAL)
+    eps = mps.gate_step(trunc, layer, q, c, chi, 0, seed, U.MODE_OPTIMAL)
+    assert eps_full < 1e-14
+    return full.to_vector(), trunc.to_vector(), eps
+
+
+@pytest.mark.parametrize("n,q,chi", [(8, 3, 3), (8, 3, 7), (7, 2, 2), (6, 1, 1)])
+def test_truncation_keeps_top_schmidt_values(n, q, chi):
+    """Truncation (eq. MPS_truncation_error, Eckart-Young): the discarded weight is the sum of
+    the squared Schmidt values of the *full* state across the cut beyond the chi largest
+    (Schmidt values from the SVD of the whole state vector reshaped at the cut, not from the
+    oracle's local two-site tensor), and the truncated state is the renormalised projection:
+    ||psi - sqrt(1 - eps) psi_trunc||^2 = eps and |<psi|psi_trunc>|^2 = 1 - eps."""
+    psi, pt, eps = _truncating_step(n, q, chi, seed=31 + n + chi)
+    s = np.linalg.svd(psi.reshape(2 ** (q + 1), -1), compute_uv=False)
+    assert s[chi] > 1e-3 * s[0]                       # the cut discards real weight
+    assert eps == pytest.approx(float(np.sum(s[chi:] ** 2)), rel=1e-10, abs=1e-15)
+    assert abs(np.linalg.norm(pt) - 1) < 1e-13
+    ov = np.vdot(pt, psi)
+    assert abs(ov) ** 2 == pytest.approx(1 - eps, abs=1e-13)
+    proj = np.sqrt(1 - eps) * pt * (ov / abs(ov))
+    assert np.linalg.norm(psi - proj) ** 2 == pytest.approx(eps, rel=1e-9, abs=1e-15)
+    # the truncated state has Schmidt rank chi across the cut and its Schmidt values are the
+    # kept ones, renormalised
+    st = np.linalg.svd(pt.reshape(2 ** (q + 1), -1), compute_uv=False)
+    assert np.allclose(st[:chi], s[:chi] / np.sqrt(1 - eps), rtol=1e-10, atol=1e-13)
+    assert np.all(st[chi:] < 1e-12)
+
+
+def test_truncation_exact_when_chi_covers_the_cut():
+    """eps = 0 (the a-posteriori estimate vanishes) whenever chi >= 2^(n/2): nothing is
+    discarded and the step equals the untruncated one."""
+    psi, pt, eps = _truncating_step(6, 2, 8, seed=44)
+    assert eps < 1e-14
+    assert 1 - abs(np.vdot(pt, psi)) ** 2 < 1e-13
 
 
 def test_trajectory_average_matches_density_matrix():
