@@ -91,8 +91,11 @@ typedef struct {
     const double* fixed_u; /* may be NULL unless unravel_mode == MPSB_FIXED */
 } mpsb_circuit;
 
-/* Sizes of the two caller buffers for n_traj trajectories; trajectory t is a chain of
- * width[t] qubits truncated to bond dimension chi[t] (1..MPSB_MAX_CHI).  Bond k (between
+/* Sizes of the two caller buffers for n_traj trajectories of the truncated trajectory
+ * sampling task (Sec. "Truncated Trajectory Sampling Task", Def. "Truncated Trajectory
+ * Sampling": one pure-state MPS per trajectory, eq. def_MPS, bond dimension at most chi).
+ * Trajectory t is a chain of width[t] qubits truncated to bond dimension chi[t]
+ * (1..MPSB_MAX_CHI).  Bond k (between
  * qubits k and k+1) has the fixed capacity min(chi, 2^(k+1), 2^(n-k-1)).  Maximal runs of
  * consecutive trajectories with equal (width, chi) form the batch's uniform sub-batches
  * (group equal shapes together); a batch of one run is a uniform batch.  precision:
@@ -100,7 +103,9 @@ typedef struct {
 int mps_batch_plan(int n_traj, const int32_t* width, const int32_t* chi, int precision,
                    size_t* state_bytes, size_t* work_bytes);
 
-/* Creates a batch in |0...0> with the orthogonality centre at qubit 0.  state_buf /
+/* Creates a batch in the initial state of the circuit description D (Sec. "Truncated
+ * Trajectory Sampling Task": an initial MPS, here |0...0>, in the chain's qubit order) with
+ * the orthogonality centre at qubit 0.  state_buf /
  * work_buf: device buffers of at least the planned sizes (256-byte aligned); seed keys the
  * counter-based branch sampler (SplitMix64 output number 1 + (traj<<32 | layer<<16 |
  * qubit), traj = index in the batch).  The initial state is written on `stream`, which all
@@ -175,8 +180,10 @@ int mps_truncate(mpsb_handle h, int chi, double* discarded);
  * array): the checks of mps_batch_set_circuit, without a handle or a device. */
 int mps_circuit_validate(int n_traj, const int32_t* width, const mpsb_circuit* c);
 
-/* Observables of every trajectory: <Z_i> (i = 0..n-1) then <Z_i Z_{i+1}> (i = 0..n-2),
- * computed in FP64 with left/right environments (normalised by <psi|psi>).  Device
+/* Observable estimation from sampled trajectories (Sec. "Target classical simulation
+ * tasks", Lemma "Expectation value estimation from trajectory sampling" and its corollary:
+ * the estimator is the mean over trajectories of <psi_i|O|psi_i>).  Observables of every
+ * trajectory: <Z_i> (i = 0..n-1) then <Z_i Z_{i+1}> (i = 0..n-2), computed in FP64 with left/right environments (normalised by <psi|psi>).  Device
  * outputs: mean [2n-1] and m2 [2n-1] (sum of squared deviations) over trajectories,
  * reduced in a fixed order (bitwise reproducible), or both NULL; per_traj [n_traj][2W-1]
  * (or NULL), rows NaN-padded past a trajectory's own 2n-1 entries.  A mixed batch
@@ -210,13 +217,20 @@ const char* mps_last_error(void);
  * NULL; r in 1..4), returns U [batch][4][r] c128 (K'_j = sum_i U[j][i] K_i; rows
  * orthonormal so the K'_j are a complete Kraus set), the branch weights p [batch][4]
  * (FP64) and the entanglement of formation eof [batch] reached by the decomposition.
- * All pointers are device pointers; n_k <= MPSB_MAX_CHANNELS. */
+ * All pointers are device pointers; 1 <= n_k <= MPSB_MAX_CHANNELS (MPSB_EINVAL otherwise).
+ * kraus_id is read on the device only: an item whose id lies outside 0..n_k-1 reads no
+ * channel and gets NaN in its U, p and eof. */
 int unravel_opt(int batch, const double* rho_q, const double* kraus, int n_k,
                 const int32_t* kraus_id, int r, double* U, double* p, double* eof,
                 void* stream);
 
 /* Expected entanglement of an unravelling, as a function of the mixing (differentiable
- * cost): for `batch` two-site tensors theta [batch][chi_l][2][2][chi_r] (c64 when prec ==
+ * cost).  The mixing is the unitary freedom of a Kraus representation (Preliminaries,
+ * eq. unitarity_kraus: K'_j = sum_i U_ji K_i describes the same channel); the cost is the
+ * objective that the locally entanglement-optimal unravelling minimises (Sec. "Locally
+ * entanglement-optimal unraveling", eq. target_optimal_unitary: the branch-weighted
+ * entanglement between the noisy qubit and the rest), with the linear or Renyi-2 entropy in
+ * place of the entanglement entropy so that it is smooth.  For `batch` two-site tensors theta [batch][chi_l][2][2][chi_r] (c64 when prec ==
  * MPSB_FP32_BULK, c128 when MPSB_FP64; noise on the first physical index) the reduced
  * state rho_q = sum_{a,t,b} theta[a,s,t,b] conj(theta[a,s',t,b]) is formed (FP64
  * accumulation) and written to rho_out [batch][2][2] c128, then
@@ -232,7 +246,10 @@ int unravel_cost(int batch, const void* theta, int chi_l, int chi_r, int prec,
                  double* f_out, double* rho_out, void* stream);
 
 /* Adjoint of unravel_cost with respect to the 16 mixing parameters (theta is not
- * re-read): grad_out [batch][16] = grad_f[b] * d f_b / d params_b.  Device pointers. */
+ * re-read): grad_out [batch][16] = grad_f[b] * d f_b / d params_b (grad_f NULL: 1), the
+ * derivative of the same objective (Sec. "Locally entanglement-optimal unraveling") through
+ * U = exp(i H) U_ref (eq. unitarity_kraus).  rho_q is the reduced state unravel_cost wrote.
+ * Device pointers. */
 int unravel_cost_grad(int batch, const double* rho_q, const double* kraus,
                       const double* params, const double* u_ref, int kind,
                       const double* grad_f, double* grad_out, void* stream);

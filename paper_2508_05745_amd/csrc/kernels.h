@@ -87,7 +87,7 @@ hipError_t launch_site_event(const EventArgs& ea, const double* rho1, int q, int
                              double* kops, double* p_out, int* status, hipStream_t st);
 hipError_t launch_site_event_check(const EventArgs& ea, const double* rho1, int slot, const int* forced, int* status,
                                    hipStream_t st);
-hipError_t launch_unravel_opt(int batch, const double* rho_q, const double* kraus, const int* kraus_id, int r,
+hipError_t launch_unravel_opt(int batch, const double* rho_q, const double* kraus, int n_k, const int* kraus_id, int r,
                               double* U, double* p, double* eof, hipStream_t st);
 
 // single-site reduced state of a site tensor [a][s][b]: rho1[traj][s][s'] (unnormalised)

@@ -1341,7 +1341,7 @@ int unravel_opt(int batch, const double* rho_q, const double* kraus, int n_k, co
   if (n_k < 1 || n_k > MPSB_MAX_CHANNELS) return fail(MPSB_EINVAL, "n_k out of range");
   if (batch == 0) return MPSB_OK;
   if (!rho_q || !kraus || !U || !p || !eof) return fail(MPSB_EINVAL, "null pointer");
-  HIPCHK(launch_unravel_opt(batch, rho_q, kraus, kraus_id, r, U, p, eof, (hipStream_t)stream));
+  HIPCHK(launch_unravel_opt(batch, rho_q, kraus, n_k, kraus_id, r, U, p, eof, (hipStream_t)stream));
   return MPSB_OK;
 }
 

@@ -658,14 +658,24 @@ __global__ __launch_bounds__(64) void k_site_event_check(EventArgs ea, const dou
 }
 
 // ------------------------------------------------------------------ unravel_opt
+// An item whose channel id lies outside 0..n_k-1 reads no channel: its U, p and eof are NaN.
 __global__ __launch_bounds__(64) void k_unravel_opt(int batch, const double* __restrict__ rho_q, const double* __restrict__ kraus,
-                              const int* __restrict__ kraus_id, int r, double* __restrict__ U, double* __restrict__ p_out,
-                              double* __restrict__ eof) {
+                              int n_k, const int* __restrict__ kraus_id, int r, double* __restrict__ U,
+                              double* __restrict__ p_out, double* __restrict__ eof) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
+  const int kid = kraus_id ? kraus_id[b] : 0;
+  if (kid < 0 || kid >= n_k) {
+    const double nan = __builtin_nan("");
+    for (int j = 0; j < 4; ++j) {
+      p_out[b * 4 + j] = nan;
+      for (int i = 0; i < 2 * r; ++i) U[((long long)b * 4 + j) * r * 2 + i] = nan;
+    }
+    eof[b] = nan;
+    return;
+  }
   cd rho[2][2];
   for (int x = 0; x < 4; ++x) rho[x >> 1][x & 1] = cd{rho_q[b * 8 + 2 * x], rho_q[b * 8 + 2 * x + 1]};
-  int kid = kraus_id ? kraus_id[b] : 0;
   cd K[4][2][2];
   for (int i = 0; i < 4; ++i)
     for (int a = 0; a < 2; ++a)
@@ -694,9 +704,10 @@ __global__ __launch_bounds__(64) void k_unravel_opt(int batch, const double* __r
   eof[b] = h;
 }
 
-hipError_t launch_unravel_opt(int batch, const double* rho_q, const double* kraus, const int* kraus_id, int r,
+hipError_t launch_unravel_opt(int batch, const double* rho_q, const double* kraus, int n_k, const int* kraus_id, int r,
                               double* U, double* p, double* eof, hipStream_t st) {
-  hipLaunchKernelGGL(k_unravel_opt, dim3((batch + 63) / 64), dim3(64), 0, st, batch, rho_q, kraus, kraus_id, r, U, p, eof);
+  hipLaunchKernelGGL(k_unravel_opt, dim3((batch + 63) / 64), dim3(64), 0, st, batch, rho_q, kraus, n_k, kraus_id, r, U, p,
+                     eof);
   return hipGetLastError();
 }
 

@@ -118,3 +118,20 @@ def test_mixed_trajectory_circuit_matches_the_tables():
         # past the trajectory's width / depth: identity and no events
         assert (mc.gate_id[t, c.depth:] == -1).all() and (mc.events[t, c.depth:] == -1).all()
         assert (mc.events[t, :, c.n:] == -1).all()
+
+
+def test_unravel_entry_points_validate_on_the_host():
+    """Sizes and the channel count are checked before any device work (no GPU needed: the
+    calls fail on the host with null device pointers never dereferenced)."""
+    import ctypes
+    lib = M.lib()
+    one = ctypes.c_void_p(8)   # never dereferenced: validation fails first
+    assert lib.unravel_opt(-1, one, one, 1, None, 2, one, one, one, None) == M.EINVAL
+    assert lib.unravel_opt(4, one, one, 0, None, 2, one, one, one, None) == M.EINVAL
+    assert lib.unravel_opt(4, one, one, 1, None, 5, one, one, one, None) == M.EINVAL
+    assert lib.unravel_opt(4, None, one, 1, None, 2, one, one, one, None) == M.EINVAL
+    assert lib.unravel_opt(0, None, None, 1, None, 2, None, None, None, None) == M.OK
+    assert lib.unravel_cost(4, one, 8, 8, 3, one, one, one, 0, one, one, None) == M.EINVAL
+    assert lib.unravel_cost(4, one, 8, 8, 0, one, one, one, 2, one, one, None) == M.EINVAL
+    assert lib.unravel_cost_grad(4, one, one, one, one, 5, None, one, None) == M.EINVAL
+    assert lib.unravel_cost_grad(4, None, one, one, one, 0, None, one, None) == M.EINVAL

@@ -39,3 +39,19 @@ def test_unravel_opt_matches_oracle(name):
         assert abs(eav - ref["eof"]) < 1e-11, (b, eav, ref["eof"])
         assert np.abs(pj - p[b]).max() < 1e-13
         assert abs(p[b].sum() - 1) < 1e-13
+
+
+def test_unravel_opt_channel_ids_out_of_range_give_nan():
+    """Channel ids are read on the device: an id outside 0..n_k-1 reads no channel and
+    leaves NaN in that item's outputs; the other items are unaffected."""
+    from paper_2508_05745_amd import mpsb as M
+    ks = np.stack([I.depolarizing(0.02), I.depolarizing(0.3)])
+    rho = I.random_density_matrices(5, 77)
+    kid = np.array([0, 1, 2, -1, 1], dtype=np.int32)
+    U, p, eof = M.unravel_opt(rho, ks, kid)
+    U, p, eof = U.cpu().numpy(), p.cpu().numpy(), eof.cpu().numpy()
+    for b in (2, 3):
+        assert np.isnan(eof[b]) and np.isnan(p[b]).all() and np.isnan(U[b].real).all()
+    for b in (0, 1, 4):
+        ref = OU.optimal_mixing(rho[b], ks[kid[b]])
+        assert abs(eof[b] - ref["eof"]) < 1e-12
