@@ -10,6 +10,9 @@
 //       per eigenvalue); eigenvalues <= zero_tol * lambda_max are dropped (value 0, vector
 //       0: such directions carry no weight of the state);
 //       clusters of relatively close eigenvalues are reorthogonalised inside the iteration;
+//   E2b the kept vectors are orthonormalised in descending eigenvalue order (blocked
+//       Gram-Schmidt with reorthogonalisation), which inverse iteration alone does not
+//       guarantee for small eigenvalues with tiny absolute gaps;
 //   E3  back-transformation evec = Q diag(omega) X with blocked compact-WY reflectors.
 // Outputs: eigenvalues (descending), eigenvectors n x keep (row-major, ld keep) c128,
 // the trace of the input and the sum of the kept eigenvalues.
@@ -687,6 +690,123 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
   if (tid == 0 && kept_sum) kept_sum[blockIdx.x] = s;
 }
 
+// ---------------------------------------------------------------------------- E2b
+// Orthonormalisation of the tridiagonal eigenvectors in descending eigenvalue order.
+// Inverse iteration gives vector k an error of about eps lambda_max / |lambda_k - lambda_j|
+// along eigenvector j, so the vectors of small eigenvalues whose absolute gaps are tiny
+// (although their relative gaps are not) come out far from orthogonal; a truncation with
+// such vectors no longer projects the state.  Every kept vector is therefore projected out
+// of all vectors before it: blocked Gram-Schmidt with reorthogonalisation, blocks of 16
+// columns against the finished columns in chunks of 16 (block modified Gram-Schmidt, two
+// passes), then modified Gram-Schmidt inside the block on one wave (two passes).  Vectors of
+// well-separated eigenvalues change at rounding level; a vector that cancels almost
+// completely (its eigenvalue lies among eigenvalues closer than rounding can resolve) is
+// replaced by a pseudo-random vector orthogonalised the same way, so that the kept vectors
+// stay a complete orthonormal set.  Columns of dropped eigenvalues stay zero.
+template <int NMAX>
+__global__ __launch_bounds__(ET) void k_tri_orth(int n, int keep, double* __restrict__ ws, long long sW,
+                                                 const double* __restrict__ evals, long long sE) {
+  constexpr int BW = 16;
+  __shared__ double Bs[NMAX * BW];   // the block, [i][j]
+  __shared__ double Xs[NMAX * BW];   // a chunk of finished columns, [i][kk]
+  __shared__ double Wp[BW * BW];     // projections of the block on the chunk, [kk][j]
+  __shared__ double rho[BW];         // norms of the block's columns after its passes
+  __shared__ int s_nk, s_redo;
+  double* X = ws + blockIdx.x * sW + 6 * (long long)n;
+  const double* ev = evals + blockIdx.x * sE;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) {
+    int nk = 0;
+    while (nk < keep && ev[nk] > 0.0) ++nk;
+    s_nk = nk;
+  }
+  __syncthreads();
+  const int nk = s_nk;
+  const int tj = tid & 15, ti = tid >> 4;   // (row group, column) of a thread in the block products
+  for (int c0 = 0; c0 < nk; c0 += BW) {
+    const int pc = min(BW, nk - c0);
+    for (int e = tid; e < n * BW; e += ET) {
+      const int i = e >> 4, j = e & 15;
+      Bs[e] = j < pc ? X[(long long)i * keep + c0 + j] : 0.0;
+    }
+    for (int round = 0; round < 3; ++round) {
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int k0 = 0; k0 < c0; k0 += BW) {
+          __syncthreads();
+          for (int e = tid; e < n * BW; e += ET) {
+            const int i = e >> 4, kk = e & 15;
+            Xs[e] = X[(long long)i * keep + k0 + kk];
+          }
+          __syncthreads();
+          {   // Wp[kk][j] = sum_i Xs[i][kk] Bs[i][j]   (kk = ti, j = tj)
+            double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            int i = 0;
+            for (; i + 3 < n; i += 4) {
+              a0 = fma(Xs[i * BW + ti], Bs[i * BW + tj], a0);
+              a1 = fma(Xs[(i + 1) * BW + ti], Bs[(i + 1) * BW + tj], a1);
+              a2 = fma(Xs[(i + 2) * BW + ti], Bs[(i + 2) * BW + tj], a2);
+              a3 = fma(Xs[(i + 3) * BW + ti], Bs[(i + 3) * BW + tj], a3);
+            }
+            for (; i < n; ++i) a0 = fma(Xs[i * BW + ti], Bs[i * BW + tj], a0);
+            Wp[ti * BW + tj] = (a0 + a1) + (a2 + a3);
+          }
+          __syncthreads();
+          // Bs[i][j] -= sum_kk Xs[i][kk] Wp[kk][j]
+          for (int i = ti; i < n; i += ET / BW) {
+            double acc = Bs[i * BW + tj];
+#pragma unroll
+            for (int kk = 0; kk < BW; ++kk) acc = fma(-Xs[i * BW + kk], Wp[kk * BW + tj], acc);
+            Bs[i * BW + tj] = acc;
+          }
+        }
+      }
+      __syncthreads();
+      // inside the block: modified Gram-Schmidt, two passes, on wave 0 (lanes over rows)
+      if (wv == 0) {
+        for (int j = 0; j < pc; ++j) {
+          for (int pass = 0; pass < 2; ++pass)
+            for (int p = 0; p < j; ++p) {
+              double d = 0;
+              for (int i = lane; i < n; i += 64) d = fma(Bs[i * BW + p], Bs[i * BW + j], d);
+              d = wave_sum(d);
+              for (int i = lane; i < n; i += 64) Bs[i * BW + j] = fma(-d, Bs[i * BW + p], Bs[i * BW + j]);
+            }
+          double q = 0;
+          for (int i = lane; i < n; i += 64) q = fma(Bs[i * BW + j], Bs[i * BW + j], q);
+          q = sqrt(wave_sum(q));
+          const double inv = q > 0 ? 1.0 / q : 0.0;
+          for (int i = lane; i < n; i += 64) Bs[i * BW + j] *= inv;
+          if (lane == 0) rho[j] = q;
+        }
+      }
+      __syncthreads();
+      // the columns came in with unit norm: a column that cancelled to below 1e-4 is
+      // orthogonalised once more (one more round), one that cancelled to below 1e-12 carries
+      // no reliable direction and is refilled with a pseudo-random vector first
+      if (tid == 0) {
+        int redo = 0;
+        for (int j = 0; j < pc; ++j) redo |= rho[j] < 1e-4;
+        s_redo = redo;
+      }
+      __syncthreads();
+      if (!s_redo || round == 2) break;
+      for (int e = tid; e < n * BW; e += ET) {
+        const int i = e >> 4, j = e & 15;
+        if (j < pc && rho[j] < 1e-12)
+          Bs[e] = (double)(hash32((uint32_t)(i * 7919 + (c0 + j) * 104729 + round * 15485863 + 3)) >> 8) *
+                      (1.0 / 16777216.0) - 0.5;
+      }
+      __syncthreads();
+    }
+    // the block is finished: write it back
+    for (int e = tid; e < n * BW; e += ET) {
+      const int i = e >> 4, j = e & 15;
+      if (j < pc) X[(long long)i * keep + c0 + j] = Bs[e];
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------- E3
 // evec = Q diag(omega) X, Q = H_0 ... H_{n-3} with u_j in column j below the diagonal;
 // reflectors are applied in blocks of NB from the last block to the first as
@@ -1083,7 +1203,10 @@ hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long
       hipLaunchKernelGGL(k_tri_eig, dim3(batch), dim3(ET), 0, st, n, keep, zero_tol, ws, sW, evals, sE, kept_sum);
       break;
     case 2:
-      break;   // (reserved)
+      if (n <= 128) hipLaunchKernelGGL((k_tri_orth<128>), dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, evals, sE);
+      else if (n <= 256) hipLaunchKernelGGL((k_tri_orth<256>), dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, evals, sE);
+      else hipLaunchKernelGGL((k_tri_orth<512>), dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, evals, sE);
+      break;
     default: {
       if (n <= 128) {   // blocked LDS form
         hipLaunchKernelGGL((k_backtransform<256, 16>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);

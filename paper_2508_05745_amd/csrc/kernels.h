@@ -75,8 +75,8 @@ hipError_t init_state(int prec, void* state, const long long* d_site_off, int n_
 
 size_t heev_ws_doubles(int n, int keep);
 size_t heev_gws_doubles(int keep);
-// phase 0: tridiagonalisation, 1: eigenvalues + inverse iteration, 2: CholeskyQR2,
-// 3: back-transformation
+// phase 0: tridiagonalisation, 1: eigenvalues + inverse iteration, 2: orthonormalisation of
+// the tridiagonal eigenvectors, 3: back-transformation
 hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long long sA, double* ws, long long sW,
                       double* gws, long long sG, double* evals, long long sE, double* kept_sum, void* Z, long long sZ,
                       int batch, hipStream_t st);
@@ -99,6 +99,16 @@ hipError_t site_apply(int prec, int chi_l, int chi_r, void* site, long long s_tr
 // renormalisation factors 1/sqrt(kept) and discarded weight (kept / trace)
 hipError_t trunc_factors(const double* kept, const double* ws, long long sW, int n, double* alpha,
                          double* discarded, int disc_stride, int accumulate, int n_traj, hipStream_t st);
+// untruncated splits: 1 / ||X||_F per trajectory (and a zero discarded weight unless
+// accumulating), and block re-mapping between full-capacity matrices and compact live blocks
+// (dst[i][j] = alpha * src[i][t * sh + b] with (t, b) = (j / dh, j % dh), live iff i < ri,
+// t < 2, b < bh; conj_t reads conj(src[t * sh + b][i]); src NULL: identity on the live block;
+// zero elsewhere)
+hipError_t split_norm(int prec, const void* X, long long sX, long long len, double* alpha, double* discarded,
+                      int disc_stride, int accumulate, int n_traj, hipStream_t st);
+hipError_t remap(int prec, void* dst, long long sD, int ldd, int drows, int dcols, int dh, int ri, int bh,
+                 const void* src, long long sS, int lds, int sh, bool conj_t, const double* alpha, int n_traj,
+                 hipStream_t st);
 // inverse square roots / square roots of hop eigenvalues (0 for dropped)
 hipError_t hop_scales(const double* evals, long long sE, int n, double* inv_sqrt, double* sqrt_, int n_traj,
                       hipStream_t st);

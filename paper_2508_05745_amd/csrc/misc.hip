@@ -268,4 +268,86 @@ hipError_t obs_reduce(const double* per_traj, int n_obs, int n_traj, double* mea
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ untruncated splits
+// 1 / ||X||_F of each trajectory's two-site matrix (FP64 sums), and a zero discarded weight.
+template <typename T>
+__global__ __launch_bounds__(256) void k_split_norm(const cplx<T>* __restrict__ X, long long sX, long long len,
+                                                    double* __restrict__ alpha, double* discarded, int disc_stride,
+                                                    int accumulate) {
+  __shared__ double red[4];
+  const cplx<T>* x = X + blockIdx.x * sX;
+  double a = 0.0;
+  for (long long e = threadIdx.x; e < len; e += 256) {
+    const double r = (double)x[e].re, i = (double)x[e].im;
+    a = fma(r, r, fma(i, i, a));
+  }
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    alpha[blockIdx.x] = t > 0 ? 1.0 / sqrt(t) : 0.0;
+    if (discarded && !accumulate) discarded[(long long)blockIdx.x * disc_stride] = 0.0;
+  }
+}
+
+hipError_t split_norm(int prec, const void* X, long long sX, long long len, double* alpha, double* discarded,
+                      int disc_stride, int accumulate, int n_traj, hipStream_t st) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_split_norm<float>, dim3(n_traj), dim3(256), 0, st, (const c32*)X, sX, len, alpha, discarded,
+                       disc_stride, accumulate);
+  else
+    hipLaunchKernelGGL(k_split_norm<double>, dim3(n_traj), dim3(256), 0, st, (const c64d*)X, sX, len, alpha,
+                       discarded, disc_stride, accumulate);
+  return hipGetLastError();
+}
+
+// Block re-mapping between a trajectory's full-capacity matrices and the compact live blocks
+// of an untruncated split.  dst[i][j] (i < drows, j < dcols) = alpha_t * S(i, j), where
+// column j is read as (t, b) = (j / dh, j % dh) (dh = dcols: unsplit columns, t = 0), the
+// element is live iff i < ri, t < 2 and b < bh, and then
+//   S(i, j) = src[i][t * sh + b]   (conj_t: conj(src[t * sh + b][i]))
+// or, with src == NULL, S(i, j) = 1 if i == t * bh + b (an identity on the live block);
+// every other element is set to zero.
+template <typename T>
+__global__ void k_remap(cplx<T>* dst, long long sD, int ldd, int drows, int dcols, int dh, int ri, int bh,
+                        const cplx<T>* __restrict__ src, long long sS, int lds, int sh, int conj_t,
+                        const double* __restrict__ alpha) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int tr = blockIdx.y;
+  if (e >= (long long)drows * dcols) return;
+  const int i = (int)(e / dcols), j = (int)(e % dcols);
+  const int t = j / dh, b = j % dh;
+  cplx<T> v = {(T)0, (T)0};
+  if (i < ri && t < 2 && b < bh) {
+    if (!src) {
+      v.re = (i == t * bh + b) ? (T)1 : (T)0;
+    } else {
+      const int c = t * sh + b;
+      v = conj_t ? src[tr * sS + (long long)c * lds + i] : src[tr * sS + (long long)i * lds + c];
+      if (conj_t) v.im = -v.im;
+      if (alpha) {
+        const double a = alpha[tr];
+        v = cplx<T>{(T)(a * (double)v.re), (T)(a * (double)v.im)};
+      }
+    }
+  }
+  dst[tr * sD + (long long)i * ldd + j] = v;
+}
+
+hipError_t remap(int prec, void* dst, long long sD, int ldd, int drows, int dcols, int dh, int ri, int bh,
+                 const void* src, long long sS, int lds, int sh, bool conj_t, const double* alpha, int n_traj,
+                 hipStream_t st) {
+  const long long len = (long long)drows * dcols;
+  if (len <= 0) return hipSuccess;
+  dim3 g((unsigned)((len + 255) / 256), (unsigned)n_traj);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_remap<float>, g, dim3(256), 0, st, (c32*)dst, sD, ldd, drows, dcols, dh, ri, bh,
+                       (const c32*)src, sS, lds, sh, (int)conj_t, alpha);
+  else
+    hipLaunchKernelGGL(k_remap<double>, g, dim3(256), 0, st, (c64d*)dst, sD, ldd, drows, dcols, dh, ri, bh,
+                       (const c64d*)src, sS, lds, sh, (int)conj_t, alpha);
+  return hipGetLastError();
+}
+
 }  // namespace mpsb

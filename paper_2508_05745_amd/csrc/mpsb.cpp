@@ -179,6 +179,10 @@ struct mpsb_batch {
   hipStream_t st = nullptr;
   int centre = 0;
   int next_layer = 0;
+  // upper bound of the number of directions with weight on each bond (1 in the initial
+  // product state; min(kept, 2 left, 2 right) after a split): beyond it the site tensors are
+  // exactly zero, the same for every trajectory
+  std::vector<int> live;
   bool has_circuit = false;
   // circuit (host copy of what the launches need)
   int depth = 0;
@@ -261,9 +265,8 @@ hipError_t heev_all(mpsb_batch* h, int n, int keep, double zt, void* A, long lon
   // one class per kernel instance: the tridiagonalisation has instances for n <= 128,
   // n <= 256 and n <= 512, the back-transformation for n <= 256 and n <= 512
   const int tri = n <= 128 ? PC_TRIDIAG_S : n <= 256 ? PC_TRIDIAG : PC_TRIDIAG_L;
-  const int cls[4] = {tri, PC_TRIEIG, PC_HOPEIG, n <= 256 ? PC_BACK : PC_BACK_L};
+  const int cls[4] = {tri, PC_TRIEIG, PC_TRIEIG, n <= 256 ? PC_BACK : PC_BACK_L};
   for (int ph = 0; ph < 4; ++ph) {
-    if (ph == 2) continue;
     ProfSec s(h, hop ? PC_HOPEIG : cls[ph]);
     hipError_t e = heev_phase(ph, n, keep, zt, A, sA, ws, sW, gws, sG, ev, sE, kept, Z, sZ, batch, h->st);
     if (e != hipSuccess) return e;
@@ -513,6 +516,53 @@ int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, b
   double* Z = W<double>(h, L.o_z);
   double* alpha = W<double>(h, L.o_alpha);
   const int n = left_to_right ? 2 * cl : 2 * cr;
+  // live bound of the neighbouring bonds: the rows (a, s) of X with a >= bl and the columns
+  // (t, b) with b >= br are exactly zero
+  const int bl = q > 0 ? h->live[q - 1] : 1;
+  const int br = q + 1 < L.n - 1 ? h->live[q + 1] : 1;
+  const int kk = std::min(keep, D);
+  const int full = std::min(2 * bl, 2 * br);
+  const bool ident = left_to_right ? bl <= br : br <= bl;
+  if (kk >= full && (ident || full <= 128)) {
+    // nothing is discarded: an exact split of the live block without an eigen-solve (an
+    // identity, or a QR factorisation by Cholesky of the small Gram), so that no direction
+    // of the state, however small its weight, depends on how well a Gram matrix resolves it
+    ProfSec srec(h, PC_RECOMPOSE);
+    const int rows = 2 * cl, cols = 2 * cr;
+    HIPCHK(split_norm(p, X, L.s_x, (long long)rows * cols, alpha, discarded, disc_stride, accumulate, T, h->st));
+    char* Rm = W<char>(h, L.o_rm);
+    char* Xc = W<char>(h, L.o_tmp);
+    if (!ident)   // compact live block Xc (2bl x 2br)
+      HIPCHK(remap(p, Xc, L.s_tmp, 2 * br, 2 * bl, 2 * br, br, 2 * bl, br, X, L.s_x, cols, cr, false, nullptr, T, h->st));
+    if (left_to_right) {
+      if (ident) {   // A_q = I on the 2bl live rows, C_(q+1) = alpha X
+        HIPCHK(remap(p, Sq, L.s_traj, D, rows, D, D, 2 * bl, 2 * bl, nullptr, 0, 0, 0, false, nullptr, T, h->st));
+        HIPCHK(remap(p, Sn, L.s_traj, cols, D, cols, cols, 2 * bl, cols, X, L.s_x, cols, 0, false, alpha, T, h->st));
+      } else {       // Xc = Q R: A_q = Q, C_(q+1) = alpha R
+        HIPCHK(gemm(p, 2, true, false, 2 * br, 2 * br, 2 * bl, Xc, 2 * br, L.s_tmp, Xc, 2 * br, L.s_tmp, gram, 2 * br,
+                    L.s_gram, nullptr, T, h->st));
+        HIPCHK(hop_chol(p, 2 * br, 1, 2 * bl, gram, L.s_gram, Xc, L.s_tmp, Rm, L.s_wm, zero_tol(L), T, h->st));
+        HIPCHK(remap(p, Sq, L.s_traj, D, rows, D, D, 2 * bl, 2 * br, Xc, L.s_tmp, 2 * br, 0, false, nullptr, T, h->st));
+        HIPCHK(remap(p, Sn, L.s_traj, cols, D, cols, cr, 2 * br, br, Rm, L.s_wm, 2 * br, br, false, alpha, T, h->st));
+      }
+      h->centre = q + 1;
+    } else {
+      if (ident) {   // B_(q+1) = I on the 2br live columns, C_q = alpha X (live columns)
+        HIPCHK(remap(p, Sn, L.s_traj, cols, D, cols, cr, 2 * br, br, nullptr, 0, 0, 0, false, nullptr, T, h->st));
+        HIPCHK(remap(p, Sq, L.s_traj, D, rows, D, br, 2 * bl, br, X, L.s_x, cols, cr, false, alpha, T, h->st));
+      } else {       // Xc = R^dag Q: B_(q+1) = Q, C_q = alpha R^dag
+        HIPCHK(gemm(p, 2, false, true, 2 * bl, 2 * bl, 2 * br, Xc, 2 * br, L.s_tmp, Xc, 2 * br, L.s_tmp, gram, 2 * bl,
+                    L.s_gram, nullptr, T, h->st));
+        HIPCHK(hop_chol(p, 2 * bl, 0, 2 * br, gram, L.s_gram, Xc, L.s_tmp, Rm, L.s_wm, zero_tol(L), T, h->st));
+        HIPCHK(remap(p, Sn, L.s_traj, cols, D, cols, cr, 2 * bl, br, Xc, L.s_tmp, 2 * br, br, false, nullptr, T, h->st));
+        HIPCHK(remap(p, Sq, L.s_traj, D, rows, D, D, 2 * bl, 2 * bl, Rm, L.s_wm, 2 * bl, 0, true, alpha, T, h->st));
+      }
+      h->centre = q;
+    }
+    h->live[q] = full;
+    return MPSB_OK;
+  }
+  h->live[q] = kk;
   {
     ProfSec s(h, PC_GRAM);
     // the eigensolver reads the lower triangle only
@@ -521,7 +571,6 @@ int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, b
     else
       HIPCHK(gemm(p, 1, true, false, 2 * cr, 2 * cr, 2 * cl, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cr, L.s_gram, nullptr, T, h->st, true));
   }
-  const int kk = std::min(keep, D);
   HIPCHK(heev_all(h, n, kk, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
               W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), Z, L.s_z, T));
   HIPCHK(trunc_factors(W<double>(h, L.o_kept), W<double>(h, L.o_ews), L.s_ews, n, alpha, discarded, disc_stride, accumulate, T, h->st));
@@ -585,7 +634,9 @@ std::vector<LayerOp> layer_ops(const mpsb_batch* h, int layer) {
 }
 
 std::string layer_signature(const mpsb_batch* h, int layer) {
-  std::string sig = std::to_string(layer % 2) + "@" + std::to_string(h->centre) + ":";
+  std::string sig = std::to_string(layer % 2) + "@" + std::to_string(h->centre) + "/";
+  for (int b : h->live) sig += std::to_string(b) + ".";
+  sig += ":";
   for (const LayerOp& o : layer_ops(h, layer))
     sig += std::to_string(o.q) + (o.gate ? "g" : "i") + (o.has_s ? "1" : "0") + (o.has_t ? "1" : "0") + ",";
   return sig;
@@ -675,6 +726,7 @@ int plan_runs(const std::vector<Run>& runs, int prec, std::vector<Layout>& Ls, s
 
 hipError_t init_batch_state(mpsb_batch* h) {
   const Layout& L = h->L;
+  h->live.assign(L.n - 1, 1);
   std::vector<long long> off(L.off.begin(), L.off.end());
   hipError_t e = hipMemcpyAsync(W<long long>(h, L.o_siteoff), off.data(), sizeof(long long) * L.n, hipMemcpyHostToDevice, h->st);
   if (e == hipSuccess) e = hipMemsetAsync(status_ptr(h), 0, 256, h->st);
@@ -1117,8 +1169,14 @@ int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch, do
     for (mpsb_batch* b : bs)
       if (layer < b->depth) {
         for (const LayerOp& op : layer_ops(b, layer)) {
-          if (op.gate) b->centre = (layer % 2 == 0) ? op.q + 1 : op.q;
-          else b->centre = op.q;
+          if (op.gate) {
+            b->centre = (layer % 2 == 0) ? op.q + 1 : op.q;
+            const int q = op.q;
+            const int bl = q > 0 ? b->live[q - 1] : 1, br = q + 1 < b->L.n - 1 ? b->live[q + 1] : 1;
+            b->live[q] = std::min(b->L.cap[q], std::min(2 * bl, 2 * br));
+          } else {
+            b->centre = op.q;
+          }
         }
       }
   }
