@@ -108,13 +108,16 @@ int mps_batch_plan(int n_traj, const int32_t* width, const int32_t* chi, int pre
  * the orthogonality centre at qubit 0.  state_buf /
  * work_buf: device buffers of at least the planned sizes (256-byte aligned); seed keys the
  * counter-based branch sampler (SplitMix64 output number 1 + (traj<<32 | layer<<16 |
- * qubit), traj = index in the batch).  The initial state is written on `stream`, which all
+ * qubit)), traj = traj_offset + index in the batch: a run of T trajectories split into
+ * batches with offsets 0, T1, T1 + T2, ... (memory waves, or shares of several devices)
+ * draws exactly the branches of one batch of T (0 <= traj_offset, traj_offset + n_traj <=
+ * 2^32, else MPSB_EINVAL).  The initial state is written on `stream`, which all
  * later calls use; a mixed batch also creates private streams (default priority) on which
  * its sub-batches run concurrently.  The handle owns host metadata, streams, events and
  * captured graphs only. */
 int mps_batch_create(int n_traj, const int32_t* width, const int32_t* chi, int precision,
-                     uint64_t seed, void* state_buf, size_t state_bytes, void* work_buf,
-                     size_t work_bytes, void* stream, mpsb_handle* out);
+                     uint64_t seed, int64_t traj_offset, void* state_buf, size_t state_bytes,
+                     void* work_buf, size_t work_bytes, void* stream, mpsb_handle* out);
 
 /* Bytes of the device circuit buffer mps_batch_set_circuit needs for circuit c on batch h. */
 int mps_circuit_bytes(mpsb_handle h, const mpsb_circuit* c, size_t* bytes);

@@ -100,7 +100,8 @@ __device__ inline double block_sum(double v, double* red) {
 // waves per SIMD (two 512-thread workgroups per CU for n <= 256).
 template <int NMAX, int NB, int RB, int NT, int WPE = 1>
 __global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
-                                                long long sW) {
+                                                long long sW, const int* __restrict__ active) {
+  if (active && !active[blockIdx.x]) return;
   static_assert(RB == 2 || RB == 4, "row blocks of 2 or 4 rows");
   __shared__ c64d Vt[NB][NMAX], Wt[NB][NMAX];
   __shared__ c64d su[NMAX], sp[NMAX];
@@ -424,7 +425,9 @@ __device__ inline uint32_t hash32(uint32_t x) {
 }
 
 __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol, double* __restrict__ ws, long long sW,
-                                                double* __restrict__ evals, long long sE, double* __restrict__ kept_sum) {
+                                                double* __restrict__ evals, long long sE, double* __restrict__ kept_sum,
+                                                const int* __restrict__ active) {
+  if (active && !active[blockIdx.x]) return;
   __shared__ double sd[EMAX], se[EMAX], se2[EMAX];
   __shared__ c64d sph[EMAX];   // phases of the subdiagonal
   __shared__ double red[ET / 64];
@@ -705,7 +708,9 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
 // stay a complete orthonormal set.  Columns of dropped eigenvalues stay zero.
 template <int NMAX>
 __global__ __launch_bounds__(ET) void k_tri_orth(int n, int keep, double* __restrict__ ws, long long sW,
-                                                 const double* __restrict__ evals, long long sE) {
+                                                 const double* __restrict__ evals, long long sE,
+                                                 const int* __restrict__ active) {
+  if (active && !active[blockIdx.x]) return;
   constexpr int BW = 16;
   __shared__ double Bs[NMAX * BW];   // the block, [i][j]
   __shared__ double Xs[NMAX * BW];   // a chunk of finished columns, [i][kk]
@@ -815,7 +820,8 @@ __global__ __launch_bounds__(ET) void k_tri_orth(int n, int keep, double* __rest
 template <int NMAX, int NB>
 __global__ __launch_bounds__(ET) void k_backtransform(int n, int keep, const c64d* __restrict__ Ag, long long sA,
                                                       double* __restrict__ ws, long long sW,
-                                                      c64d* __restrict__ Zg, long long sZ) {
+                                                      c64d* __restrict__ Zg, long long sZ, const int* __restrict__ mask) {
+  if (mask && !mask[blockIdx.x]) return;
   __shared__ c64d Vb[NMAX][NB];
   __shared__ c64d Tm[NB][NB];
   __shared__ c64d Sv[NB][NB];
@@ -951,7 +957,8 @@ __device__ inline v4d_t mfma64(double a, double b, v4d_t c) { return __builtin_a
 __host__ __device__ inline size_t bt_tfac_offset(int n, int keep) { return (size_t)6 * n + (size_t)6 * n * keep + 64; }
 
 __global__ __launch_bounds__(256) void k_bt_tfac(int n, const c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
-                                                 long long sW, int keep) {
+                                                 long long sW, int keep, const int* __restrict__ active) {
+  if (active && !active[blockIdx.x]) return;
   __shared__ double Sp[4][2][16][16];
   __shared__ c64d Sv[16][16];
   __shared__ c64d Tm[16][16];
@@ -1005,7 +1012,7 @@ __global__ __launch_bounds__(256) void k_bt_tfac(int n, const c64d* __restrict__
 template <int NMAX, int BNT>
 __global__ __launch_bounds__(BNT, BNT / 128) void k_bt_panel(int n, int keep, const c64d* __restrict__ Ag, long long sA,
                                                   const double* __restrict__ ws, long long sW, c64d* __restrict__ Zg,
-                                                  long long sZ, int n_panels) {
+                                                  long long sZ, int n_panels, const int* __restrict__ active) {
   // 80 KB of LDS so that two panels share a CU: the panel (rows of 16 doubles read 4 rows at
   // a time: conflict-free without padding), three slots of partial W (and, while W is folded,
   // the W arrays as a fourth) and the reduced W
@@ -1019,6 +1026,7 @@ __global__ __launch_bounds__(BNT, BNT / 128) void k_bt_panel(int n, int keep, co
   const int q8 = G >> 3, r8 = G & 7, x8 = w & 7;
   const int L = x8 * q8 + min(x8, r8) + (w >> 3);
   const int mat = L / n_panels, panel = L - mat * n_panels;
+  if (active && !active[mat]) return;
   const c64d* A = Ag + mat * sA;
   const double* W = ws + mat * sW;
   const c64d* om = (const c64d*)(W + 4 * n);
@@ -1189,38 +1197,38 @@ size_t heev_gws_doubles(int keep) { return (size_t)keep * keep + 64; }
 
 hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long long sA, double* ws, long long sW,
                       double* gws, long long sG, double* evals, long long sE, double* kept_sum, void* Z, long long sZ,
-                      int batch, hipStream_t st) {
+                      int batch, hipStream_t st, const int* active) {
   if (n > EMAX || keep > n || keep > EMAX / 2 || keep < 1) return hipErrorInvalidValue;
   (void)gws;
   (void)sG;
   switch (phase) {
     case 0:
-      if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 8, 2, 512, 4>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
-      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 6, 2, 512, 4>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
-      else hipLaunchKernelGGL((k_tridiag<512, 4, 2, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW);
+      if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 8, 2, 512, 4>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW, active);
+      else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 6, 2, 512, 4>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW, active);
+      else hipLaunchKernelGGL((k_tridiag<512, 4, 2, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW, active);
       break;
     case 1:
-      hipLaunchKernelGGL(k_tri_eig, dim3(batch), dim3(ET), 0, st, n, keep, zero_tol, ws, sW, evals, sE, kept_sum);
+      hipLaunchKernelGGL(k_tri_eig, dim3(batch), dim3(ET), 0, st, n, keep, zero_tol, ws, sW, evals, sE, kept_sum, active);
       break;
     case 2:
-      if (n <= 128) hipLaunchKernelGGL((k_tri_orth<128>), dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, evals, sE);
-      else if (n <= 256) hipLaunchKernelGGL((k_tri_orth<256>), dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, evals, sE);
-      else hipLaunchKernelGGL((k_tri_orth<512>), dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, evals, sE);
+      if (n <= 128) hipLaunchKernelGGL((k_tri_orth<128>), dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, evals, sE, active);
+      else if (n <= 256) hipLaunchKernelGGL((k_tri_orth<256>), dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, evals, sE, active);
+      else hipLaunchKernelGGL((k_tri_orth<512>), dim3(batch), dim3(ET), 0, st, n, keep, ws, sW, evals, sE, active);
       break;
     default: {
       if (n <= 128) {   // blocked LDS form
-        hipLaunchKernelGGL((k_backtransform<256, 16>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ);
+        hipLaunchKernelGGL((k_backtransform<256, 16>), dim3(batch), dim3(ET), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, active);
         break;
       }
       // 128 < n <= 512: MFMA panel form (T factors, then 16-column panels)
-      hipLaunchKernelGGL(k_bt_tfac, dim3(batch), dim3(256), 0, st, n, (const c64d*)A, sA, ws, sW, keep);
+      hipLaunchKernelGGL(k_bt_tfac, dim3(batch), dim3(256), 0, st, n, (const c64d*)A, sA, ws, sW, keep, active);
       const int np = (keep + 15) / 16;
       const long long blocks = (long long)np * batch;
       if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
       if (n <= 256)
-        hipLaunchKernelGGL((k_bt_panel<256, 512>), dim3((unsigned)blocks), dim3(512), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np);
+        hipLaunchKernelGGL((k_bt_panel<256, 512>), dim3((unsigned)blocks), dim3(512), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np, active);
       else
-        hipLaunchKernelGGL((k_bt_panel<512, 512>), dim3((unsigned)blocks), dim3(512), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np);
+        hipLaunchKernelGGL((k_bt_panel<512, 512>), dim3((unsigned)blocks), dim3(512), 0, st, n, keep, (const c64d*)A, sA, ws, sW, (c64d*)Z, sZ, np, active);
       break;
     }
   }

@@ -12,97 +12,12 @@ namespace mpsb {
 // ============================================================================ generic GEMM
 // C[b] = alpha[b] * op(A[b]) * op(B[b]);  op = N (row-major M x K, ld) or
 // C (conjugate transpose of a row-major K x M matrix).  64x64 tiles, BK = 16, 256 threads,
-// 4x4 complex accumulators per thread, LDS staging as separate re/im planes.
+// LDS staging as separate re/im planes.
 constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
 
 template <typename T> struct Ld;
 template <> struct Ld<float> { using C = c32; };
 template <> struct Ld<double> { using C = c64d; };
-
-template <typename TA, typename TB, typename TACC, typename TC, bool CA, bool CB>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const cplx<TA>* __restrict__ A,
-                                              int lda, long long sA, const cplx<TB>* __restrict__ B,
-                                              int ldb, long long sB, cplx<TC>* __restrict__ C, int ldc,
-                                              long long sC, const double* __restrict__ alpha) {
-  __shared__ TACC As_re[GB_K][GB_M + 4], As_im[GB_K][GB_M + 4];
-  __shared__ TACC Bs_re[GB_K][GB_N + 4], Bs_im[GB_K][GB_N + 4];
-  const int bz = blockIdx.z;
-  A += bz * sA;
-  B += bz * sB;
-  C += bz * sC;
-  const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  TACC acc_re[4][4], acc_im[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc_re[i][j] = acc_im[i][j] = 0;
-
-  for (int k0 = 0; k0 < K; k0 += GB_K) {
-    // ---- stage A tile: op(A)[m][k], m in [m0, m0+64), k in [k0, k0+16)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int e = tid + 256 * r;
-      int mm, kk;
-      if (!CA) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
-      int m = m0 + mm, k = k0 + kk;
-      cplx<TA> v = {0, 0};
-      if (m < M && k < K) {
-        if (!CA) v = A[(long long)m * lda + k];
-        else { v = A[(long long)k * lda + m]; v.im = -v.im; }
-      }
-      As_re[kk][mm] = (TACC)v.re;
-      As_im[kk][mm] = (TACC)v.im;
-    }
-    // ---- stage B tile: op(B)[k][n]
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int e = tid + 256 * r;
-      int nn, kk;
-      if (!CB) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
-      int n = n0 + nn, k = k0 + kk;
-      cplx<TB> v = {0, 0};
-      if (n < N && k < K) {
-        if (!CB) v = B[(long long)k * ldb + n];
-        else { v = B[(long long)n * ldb + k]; v.im = -v.im; }
-      }
-      Bs_re[kk][nn] = (TACC)v.re;
-      Bs_im[kk][nn] = (TACC)v.im;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GB_K; ++kk) {
-      TACC ar[4], ai[4], br[4], bi[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) { ar[i] = As_re[kk][ty + 16 * i]; ai[i] = As_im[kk][ty + 16 * i]; }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) { br[j] = Bs_re[kk][tx + 16 * j]; bi[j] = Bs_im[kk][tx + 16 * j]; }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc_re[i][j] += ar[i] * br[j] - ai[i] * bi[j];
-          acc_im[i][j] += ar[i] * bi[j] + ai[i] * br[j];
-        }
-    }
-    __syncthreads();
-  }
-  const double al = alpha ? alpha[bz] : 1.0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int m = m0 + ty + 16 * i;
-    if (m >= M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int n = n0 + tx + 16 * j;
-      if (n >= N) continue;
-      cplx<TC> o;
-      o.re = (TC)(al * (double)acc_re[i][j]);
-      o.im = (TC)(al * (double)acc_im[i][j]);
-      C[(long long)m * ldc + n] = o;
-    }
-  }
-}
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -140,12 +55,14 @@ template <typename TA, typename TB, typename TACC, typename TC, bool CA, bool CB
 __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cplx<TA>* __restrict__ A,
                                                    int lda, long long sA, const cplx<TB>* __restrict__ B,
                                                    int ldb, long long sB, cplx<TC>* __restrict__ C, int ldc,
-                                                   long long sC, const double* __restrict__ alpha, int lower) {
+                                                   long long sC, const double* __restrict__ alpha, int lower,
+                                                   const int* __restrict__ active) {
   using Mf = MfmaAcc<TACC>;
   using V = typename Mf::V;
   __shared__ TACC As_re[GB_K][GB_M + 4], As_im[GB_K][GB_M + 4];
   __shared__ TACC Bs_re[GB_K][GB_N + 4], Bs_im[GB_K][GB_N + 4];
   const int bz = blockIdx.z;
+  if (active && !active[bz]) return;
   A += bz * sA;
   B += bz * sB;
   C += bz * sC;
@@ -259,30 +176,30 @@ template <typename TA, typename TB, typename TACC, typename TC>
 static hipError_t gemm_dispatch(bool ca, bool cb, int M, int N, int K, const void* A, int lda,
                                 long long sA, const void* B, int ldb, long long sB, void* C,
                                 int ldc, long long sC, const double* alpha, int batch,
-                                hipStream_t st, int lower) {
+                                hipStream_t st, int lower, const int* active) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch);
   auto a = (const cplx<TA>*)A;
   auto b = (const cplx<TB>*)B;
   auto c = (cplx<TC>*)C;
-  if (!ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower);
-  else if (ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower);
-  else if (!ca && cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower);
-  else hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower);
+  if (!ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
+  else if (ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
+  else if (!ca && cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
+  else hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
   return hipGetLastError();
 }
 
 hipError_t gemm(int prec_in, int prec_out, bool ca, bool cb, int M, int N, int K, const void* A,
                 int lda, long long sA, const void* B, int ldb, long long sB, void* C, int ldc,
-                long long sC, const double* alpha, int batch, hipStream_t st, bool lower) {
+                long long sC, const double* alpha, int batch, hipStream_t st, bool lower, const int* active) {
   const int lo = lower ? 1 : 0;
   if (prec_in == 0 && prec_out == 0)
-    return gemm_dispatch<float, float, float, float>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo);
+    return gemm_dispatch<float, float, float, float>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo, active);
   if (prec_in == 0 && prec_out == 1)
-    return gemm_dispatch<float, float, float, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo);
+    return gemm_dispatch<float, float, float, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo, active);
   if (prec_in == 0 && prec_out == 2)   // c64 operands, FP64 accumulation and output
-    return gemm_dispatch<float, float, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo);
-  return gemm_dispatch<double, double, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo);
+    return gemm_dispatch<float, float, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo, active);
+  return gemm_dispatch<double, double, double, double>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lo, active);
 }
 
 // ============================================================================ theta

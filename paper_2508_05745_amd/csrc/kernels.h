@@ -31,7 +31,7 @@ struct EventArgs {
   const int* nk_tab;         // [n_ch]
   const double* fixed_tab;   // [n_ch][4][4] c128 or NULL
   const int* layer_ptr;
-  int traj_base;
+  long long traj_base;   // global trajectory index of trajectory 0 (key of its branch draws)
 };
 
 // Gate of a two-site step: by value, or (pool set) pool[ids[t * traj_stride + layer *
@@ -44,13 +44,14 @@ struct GateRef {
   const int* layer;
 };
 
+// active: per-batch-entry mask (NULL = all); inactive entries are left untouched.
 // prec: 0 = complex64 storage / FP32 arithmetic, 1 = complex128 / FP64; gemm prec_out 2 =
 // c128 output with FP64 accumulation of c64 operands; lower: only the 64 x 64 output tiles that
 // hold elements on or below the diagonal are written (Hermitian products read from their lower
 // triangle)
 hipError_t gemm(int prec_in, int prec_out, bool conj_a, bool conj_b, int M, int N, int K, const void* A, int lda,
                 long long sA, const void* B, int ldb, long long sB, void* C, int ldc, long long sC,
-                const double* alpha, int batch, hipStream_t st, bool lower = false);
+                const double* alpha, int batch, hipStream_t st, bool lower = false, const int* active = nullptr);
 hipError_t theta(int prec, int chi_l, int chi_m, int chi_r, const void* Cs, const void* Bs, long long s_traj,
                  void* out, long long s_out, const Mat4& gate, const GateRef& gref, double* partial, int n_traj,
                  hipStream_t st, int variant = -1);
@@ -79,7 +80,7 @@ size_t heev_gws_doubles(int keep);
 // the tridiagonal eigenvectors, 3: back-transformation
 hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long long sA, double* ws, long long sW,
                       double* gws, long long sG, double* evals, long long sE, double* kept_sum, void* Z, long long sZ,
-                      int batch, hipStream_t st);
+                      int batch, hipStream_t st, const int* active = nullptr);
 
 hipError_t launch_gate_events(const EventArgs& ea, const double* partial, int n_tiles, int q, int has_s, int has_t,
                               double* kops, int* status, hipStream_t st);
@@ -109,6 +110,20 @@ hipError_t split_norm(int prec, const void* X, long long sX, long long len, doub
 hipError_t remap(int prec, void* dst, long long sD, int ldd, int drows, int dcols, int dh, int ri, int bh,
                  const void* src, long long sS, int lds, int sh, bool conj_t, const double* alpha, int n_traj,
                  hipStream_t st);
+// second-level truncation (cuts below the Gram's resolution): per-trajectory decision and
+// masked resolved directions, elementwise difference, placement of the residual directions
+hipError_t l2_prep(const double* evals, long long sE, const double* ws, long long sW, const double* kept_l1, int n,
+                   int kk, double tau, const double* Z, long long sZ, double* Zr, long long sZr, int* act, int* r,
+                   double* info, int n_traj, hipStream_t st);
+hipError_t l2_sub(double* out, long long sO, const double* a, long long sa, const double* b, long long sb, long long len,
+                  const int* act, int n_traj, hipStream_t st);
+hipError_t l2_merge(const int* act, const int* r, int n, int kk, double* Z, long long sZ, const double* Z2, long long sZ2,
+                    const double* ev2, long long sE, const double* info, double* alpha, double* discarded,
+                    int disc_stride, int accumulate, int n_traj, hipStream_t st);
+// block copies (c128) into a sub-block of a larger matrix, and accumulation
+hipError_t put_block(double* dst, long long sD, int ldd, int r0, int c0, int rows, int cols, const double* src,
+                     long long sS, int lds, bool conj_t, int n_traj, hipStream_t st);
+hipError_t add_c128(double* acc, long long sA, const double* b, long long sB, long long len, int n_traj, hipStream_t st);
 // inverse square roots / square roots of hop eigenvalues (0 for dropped)
 hipError_t hop_scales(const double* evals, long long sE, int n, double* inv_sqrt, double* sqrt_, int n_traj,
                       hipStream_t st);

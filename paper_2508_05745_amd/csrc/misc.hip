@@ -350,4 +350,160 @@ hipError_t remap(int prec, void* dst, long long sD, int ldd, int drows, int dcol
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ second-level truncation
+// A Gram matrix G = M M^dag resolves singular values only down to about sqrt(eps) of the
+// largest (its eigenvectors carry an absolute error of eps * lambda_max), so when a truncation
+// cut falls below that level the kept subspace is re-solved from the residual
+// R = M - Z_r Z_r^dag M of the well-resolved directions Z_r (lambda > tau lambda_max), whose own
+// Gram R R^dag resolves the rest.  l2_prep decides per trajectory (active iff the kept
+// eigenvalue at the cut lies below tau lambda_max), counts r and masks Z to its first r
+// columns; l2_merge places the top kept - r residual directions after them and updates the
+// renormalisation and the discarded weight.
+__global__ __launch_bounds__(256) void k_l2_prep(const double* __restrict__ evals, long long sE, const double* __restrict__ ws,
+                                                 long long sW, const double* __restrict__ kept_l1, int n, int kk, double tau,
+                                                 const c64d* __restrict__ Z, long long sZ, c64d* __restrict__ Zr,
+                                                 long long sZr, int* __restrict__ act, int* __restrict__ rr,
+                                                 double* __restrict__ info) {
+  __shared__ int s_r;
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const double* ev = evals + t * sE;
+  const double thr = tau * ev[0];
+  if (tid == 0) {
+    int r = 0;
+    double k1 = 0.0;
+    while (r < kk && ev[r] >= thr && ev[r] > 0.0) k1 += ev[r++];
+    const int a = (r < kk && ev[0] > 0.0) ? 1 : 0;
+    act[t] = a;
+    rr[t] = r;
+    info[3 * t] = k1;                     // kept weight of the resolved directions
+    info[3 * t + 1] = ws[t * sW + 3 * n]; // trace of the Gram
+    info[3 * t + 2] = kept_l1[t];         // kept weight of the first-level truncation
+    s_r = r;
+  }
+  __syncthreads();
+  const int r = s_r;
+  for (long long e = tid; e < (long long)n * kk; e += 256) {
+    const int c = (int)(e % kk);
+    Zr[t * sZr + e] = c < r ? Z[t * sZ + e] : c64d{0.0, 0.0};
+  }
+}
+
+hipError_t l2_prep(const double* evals, long long sE, const double* ws, long long sW, const double* kept_l1, int n,
+                   int kk, double tau, const double* Z, long long sZ, double* Zr, long long sZr, int* act, int* r,
+                   double* info, int n_traj, hipStream_t st) {
+  hipLaunchKernelGGL(k_l2_prep, dim3(n_traj), dim3(256), 0, st, evals, sE, ws, sW, kept_l1, n, kk, tau, (const c64d*)Z,
+                     sZ, (c64d*)Zr, sZr, act, r, info);
+  return hipGetLastError();
+}
+
+// out = a - b elementwise (len c128 per trajectory) for active trajectories (act NULL: all)
+__global__ void k_l2_sub(c64d* out, long long sO, const c64d* __restrict__ a, long long sa, const c64d* __restrict__ b,
+                         long long sb, long long len, const int* __restrict__ act) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (e >= len || (act && !act[t])) return;
+  const c64d x = a[t * sa + e], y = b[t * sb + e];
+  out[t * sO + e] = c64d{x.re - y.re, x.im - y.im};
+}
+
+hipError_t l2_sub(double* out, long long sO, const double* a, long long sa, const double* b, long long sb, long long len,
+                  const int* act, int n_traj, hipStream_t st) {
+  dim3 g((unsigned)((len + 255) / 256), (unsigned)n_traj);
+  hipLaunchKernelGGL(k_l2_sub, g, dim3(256), 0, st, (c64d*)out, sO, (const c64d*)a, sa, (const c64d*)b, sb, len, act);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_l2_merge(const int* __restrict__ act, const int* __restrict__ rr, int n, int kk,
+                                                  c64d* __restrict__ Z, long long sZ, const c64d* __restrict__ Z2,
+                                                  long long sZ2, const double* __restrict__ ev2, long long sE,
+                                                  const double* __restrict__ info, double* __restrict__ alpha,
+                                                  double* discarded, int disc_stride, int accumulate) {
+  __shared__ double red[4];
+  __shared__ double s_inv;
+  const int t = blockIdx.x, tid = threadIdx.x;
+  if (!act[t]) return;
+  const int r = rr[t];
+  for (int j = 0; j + r < kk; ++j) {
+    const c64d* z = Z2 + t * sZ2;
+    double a = 0.0;
+    for (int i = tid; i < n; i += 256) {
+      const c64d v = z[(long long)i * kk + j];
+      a = fma(v.re, v.re, fma(v.im, v.im, a));
+    }
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = a;
+    __syncthreads();
+    if (tid == 0) {
+      const double q = (red[0] + red[1]) + (red[2] + red[3]);
+      // a residual direction of no weight (eigenvalue dropped) stays a zero vector
+      s_inv = (q > 0.0 && ev2[t * sE + j] > 0.0) ? 1.0 / sqrt(q) : 0.0;
+    }
+    __syncthreads();
+    const double inv = s_inv;
+    for (int i = tid; i < n; i += 256) {
+      const c64d v = z[(long long)i * kk + j];
+      Z[t * sZ + (long long)i * kk + r + j] = c64d{v.re * inv, v.im * inv};
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double kept = info[3 * t];
+    for (int j = 0; j + r < kk; ++j) kept += fmax(ev2[t * sE + j], 0.0);
+    const double tr = info[3 * t + 1], k1 = info[3 * t + 2];
+    alpha[t] = kept > 0.0 ? 1.0 / sqrt(kept) : 0.0;
+    if (discarded) {
+      const double e2 = tr > 0.0 ? fmax(tr - kept, 0.0) / tr : 0.0;
+      const double e1 = tr > 0.0 ? fmax(tr - k1, 0.0) / tr : 0.0;
+      double* d = discarded + (long long)t * disc_stride;
+      *d = accumulate ? *d - e1 + e2 : e2;
+    }
+  }
+}
+
+hipError_t l2_merge(const int* act, const int* r, int n, int kk, double* Z, long long sZ, const double* Z2, long long sZ2,
+                    const double* ev2, long long sE, const double* info, double* alpha, double* discarded,
+                    int disc_stride, int accumulate, int n_traj, hipStream_t st) {
+  hipLaunchKernelGGL(k_l2_merge, dim3(n_traj), dim3(256), 0, st, act, r, n, kk, (c64d*)Z, sZ, (const c64d*)Z2, sZ2, ev2,
+                     sE, info, alpha, discarded, disc_stride, accumulate);
+  return hipGetLastError();
+}
+
+// dst[r0 + i][c0 + j] = src[i][j] (c128, rows x cols), conj_t: conj(src[j][i]); the rest of dst
+// is not touched
+__global__ void k_put_block(c64d* dst, long long sD, int ldd, int r0, int c0, int rows, int cols,
+                            const c64d* __restrict__ src, long long sS, int lds, int conj_t) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (e >= (long long)rows * cols) return;
+  const int i = (int)(e / cols), j = (int)(e % cols);
+  c64d v = conj_t ? src[t * sS + (long long)j * lds + i] : src[t * sS + (long long)i * lds + j];
+  if (conj_t) v.im = -v.im;
+  dst[t * sD + (long long)(r0 + i) * ldd + c0 + j] = v;
+}
+
+hipError_t put_block(double* dst, long long sD, int ldd, int r0, int c0, int rows, int cols, const double* src,
+                     long long sS, int lds, bool conj_t, int n_traj, hipStream_t st) {
+  const long long len = (long long)rows * cols;
+  if (len <= 0) return hipSuccess;
+  dim3 g((unsigned)((len + 255) / 256), (unsigned)n_traj);
+  hipLaunchKernelGGL(k_put_block, g, dim3(256), 0, st, (c64d*)dst, sD, ldd, r0, c0, rows, cols, (const c64d*)src, sS, lds,
+                     (int)conj_t);
+  return hipGetLastError();
+}
+
+// acc += b (c128, len per trajectory)
+__global__ void k_add(c64d* acc, long long sA, const c64d* __restrict__ b, long long sB, long long len) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (e >= len) return;
+  const c64d x = acc[t * sA + e], y = b[t * sB + e];
+  acc[t * sA + e] = c64d{x.re + y.re, x.im + y.im};
+}
+
+hipError_t add_c128(double* acc, long long sA, const double* b, long long sB, long long len, int n_traj, hipStream_t st) {
+  dim3 g((unsigned)((len + 255) / 256), (unsigned)n_traj);
+  hipLaunchKernelGGL(k_add, g, dim3(256), 0, st, (c64d*)acc, sA, (const c64d*)b, sB, len);
+  return hipGetLastError();
+}
+
 }  // namespace mpsb

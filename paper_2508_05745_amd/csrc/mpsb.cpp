@@ -38,6 +38,8 @@ namespace {
 // Relative drop thresholds of Gram eigenvalues (truncation) and Cholesky pivots (centre hops):
 // directions below them are represented by zero vectors.
 constexpr double ZERO_TOL_FP64 = 1e-26;
+// FP64 truncation: a kept eigenvalue below L2_TAU * lambda_max is re-solved from the residual
+constexpr double L2_TAU = 1e-8;
 constexpr double ZERO_TOL_FP32 = 1e-13;
 
 struct Layout {
@@ -48,7 +50,8 @@ struct Layout {
   long long s_traj;                 // elements per trajectory
   // work buffer (byte offsets)
   size_t o_status, o_siteoff, o_x, o_partial, o_kops, o_gram, o_ews, o_gws, o_evals, o_z, o_kept, o_alpha,
-      o_invs, o_sqrt, o_wm, o_rm, o_rho1, o_tmp, o_obs, o_norm, o_pbuf, o_exp;
+      o_invs, o_sqrt, o_wm, o_rm, o_rho1, o_tmp, o_obs, o_norm, o_pbuf, o_exp, o_l2zr, o_l2cr, o_l2z2, o_l2act,
+      o_l2r, o_l2info;
   long long s_x, s_partial, s_gram, s_ews, s_gws, s_evals, s_z, s_wm, s_tmp;
   int exp_chunk;
   long long s_env;                  // c128 elements per environment slot
@@ -131,6 +134,14 @@ int make_layout(int n_traj, int n, int chi, int prec, Layout& L) {
   L.o_wm = take(L.esz * L.s_wm * T);
   L.o_rm = take(L.esz * L.s_wm * T);
   L.o_tmp = take(L.esz * L.s_tmp * T);
+  if (prec == MPSB_FP64) {   // second-level truncation (FP64 path)
+    L.o_l2zr = take(16 * L.s_z * T);
+    L.o_l2cr = take(16 * L.s_z * T);
+    L.o_l2z2 = take(16 * L.s_z * T);
+    L.o_l2act = take(sizeof(int) * T);
+    L.o_l2r = take(sizeof(int) * T);
+    L.o_l2info = take(sizeof(double) * 3 * T);
+  }
   size_t gate_end = o;
   o = base;
   L.o_exp = take((size_t)per_exp * L.exp_chunk);
@@ -193,7 +204,8 @@ struct mpsb_batch {
   std::vector<double> fixed_u;
   std::vector<unsigned char> any_ev;   // [depth][n]: some trajectory has an event on (layer, qubit)
   Tables tab;
-  int traj_base = 0;                   // global index of trajectory 0 (sub-batch of a mixed batch)
+  int traj_base = 0;                   // index of trajectory 0 in the batch (sub-batch of a mixed batch)
+  long long traj_offset = 0;           // global index of the batch's trajectory 0 (branch-draw keys)
   int rec_stride = 0;                  // record row length (the widest trajectory of the batch)
   // mixed batch: sub-batches and their streams
   std::vector<mpsb_batch*> sub;
@@ -261,14 +273,14 @@ void prof_collect(mpsb_batch* h) {
 
 hipError_t heev_all(mpsb_batch* h, int n, int keep, double zt, void* A, long long sA, double* ws, long long sW,
                     double* gws, long long sG, double* ev, long long sE, double* kept, void* Z, long long sZ, int batch,
-                    bool hop = false) {
+                    bool hop = false, const int* active = nullptr) {
   // one class per kernel instance: the tridiagonalisation has instances for n <= 128,
   // n <= 256 and n <= 512, the back-transformation for n <= 256 and n <= 512
   const int tri = n <= 128 ? PC_TRIDIAG_S : n <= 256 ? PC_TRIDIAG : PC_TRIDIAG_L;
   const int cls[4] = {tri, PC_TRIEIG, PC_TRIEIG, n <= 256 ? PC_BACK : PC_BACK_L};
   for (int ph = 0; ph < 4; ++ph) {
     ProfSec s(h, hop ? PC_HOPEIG : cls[ph]);
-    hipError_t e = heev_phase(ph, n, keep, zt, A, sA, ws, sW, gws, sG, ev, sE, kept, Z, sZ, batch, h->st);
+    hipError_t e = heev_phase(ph, n, keep, zt, A, sA, ws, sW, gws, sG, ev, sE, kept, Z, sZ, batch, h->st, active);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -298,6 +310,26 @@ hipError_t copy_blocks(void* dst, size_t dpitch, const void* src, size_t spitch,
 
 double zero_tol(const Layout& L) { return L.prec == MPSB_FP64 ? ZERO_TOL_FP64 : ZERO_TOL_FP32; }
 
+// QR factors through the eigen-decomposition of the m x m Gram in the gram buffer, every
+// direction above the zero-weight cut kept: right (C = Q R, Gram C^dag C = W Lambda W^dag):
+// Wm = W Lambda^-1/2 (Q = C Wm), Rm = Lambda^1/2 W^dag; left (C = R Q, Gram C C^dag):
+// Wm = Lambda^-1/2 W^dag (Q = Wm C), Rm = W Lambda^1/2.
+hipError_t gram_qr_factors(mpsb_batch* h, int m, bool right) {
+  Layout& L = h->L;
+  const int p = L.prec == MPSB_FP64 ? 1 : 0, T = L.n_traj;
+  hipError_t e = heev_all(h, m, m, zero_tol(L), W<double>(h, L.o_gram), L.s_gram, W<double>(h, L.o_ews), L.s_ews,
+                          W<double>(h, L.o_gws), L.s_gws, W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept),
+                          W<double>(h, L.o_z), L.s_z, T, true);
+  if (e != hipSuccess) return e;
+  double* invs = W<double>(h, L.o_invs);
+  double* sq = W<double>(h, L.o_sqrt);
+  if ((e = hop_scales(W<double>(h, L.o_evals), L.s_evals, m, invs, sq, T, h->st)) != hipSuccess) return e;
+  if ((e = scale_cast(p, m, m, W<double>(h, L.o_z), m, L.s_z, invs, m, !right, W<char>(h, L.o_wm), m, L.s_wm, T,
+                      h->st)) != hipSuccess)
+    return e;
+  return scale_cast(p, m, m, W<double>(h, L.o_z), m, L.s_z, sq, m, right, W<char>(h, L.o_rm), m, L.s_wm, T, h->st);
+}
+
 // Move the orthogonality centre from site j to j+1: C_j = Q R via the Gram matrix C^dag C.
 int hop_right(mpsb_batch* h, int j) {
   Layout& L = h->L;
@@ -306,6 +338,64 @@ int hop_right(mpsb_batch* h, int j) {
   char* Cj = site_ptr(h, j);
   char* Bn = site_ptr(h, j + 1);
   double* gram = W<double>(h, L.o_gram);
+  char* tmp = W<char>(h, L.o_tmp);
+  const int bj = h->live[j], bl = j > 0 ? h->live[j - 1] : 1;
+  if (cr > 128 && bj <= 128) {
+    // the live block (2 bl x bj) is factored by Cholesky QR in compact form
+    ProfSec sh(h, PC_HOPEIG);
+    HIPCHK(remap(p, tmp, L.s_tmp, bj, 2 * bl, bj, bj, 2 * bl, bj, Cj, L.s_traj, cr, 0, false, nullptr, T, h->st));
+    HIPCHK(gemm(p, 2, true, false, bj, bj, 2 * bl, tmp, bj, L.s_tmp, tmp, bj, L.s_tmp, gram, bj, L.s_gram, nullptr, T, h->st));
+    HIPCHK(hop_chol(p, bj, 1, 2 * bl, gram, L.s_gram, tmp, L.s_tmp, W<char>(h, L.o_rm), L.s_wm, zero_tol(L), T, h->st));
+    HIPCHK(remap(p, Cj, L.s_traj, cr, 2 * cl, cr, cr, 2 * bl, bj, tmp, L.s_tmp, bj, 0, false, nullptr, T, h->st));
+    HIPCHK(remap(p, W<char>(h, L.o_wm), L.s_wm, cr, cr, cr, cr, bj, bj, W<char>(h, L.o_rm), L.s_wm, bj, 0, false, nullptr,
+                 T, h->st));
+    ProfSec shg(h, PC_HOPGEMM);
+    // C_{j+1} = R B_{j+1}
+    HIPCHK(gemm(p, p, false, false, cr, 2 * cr2, cr, W<char>(h, L.o_wm), cr, L.s_wm, Bn, 2 * cr2, L.s_traj, tmp, 2 * cr2,
+                L.s_tmp, nullptr, T, h->st));
+    HIPCHK(copy_blocks(Bn, L.s_traj * L.esz, tmp, L.s_tmp * L.esz, (size_t)cr * 2 * cr2 * L.esz, T, h->st));
+    h->centre = j + 1;
+    return MPSB_OK;
+  }
+  if (p == 1 && cr > 128) {
+    // FP64, more than 128 live columns: Cholesky QR in two column blocks (block Gram-Schmidt
+    // with one reorthogonalisation between them), C = [Q1 Q2] [[R11 R12] [0 R22]]
+    ProfSec sh(h, PC_HOPEIG);
+    const int n2 = bj - 128, rows = 2 * bl;
+    double* C1 = W<double>(h, L.o_tmp);
+    double* C2 = C1 + 2LL * rows * 128;
+    double* Tq = W<double>(h, L.o_x);
+    double* R11 = W<double>(h, L.o_rm);
+    double* R22 = R11 + 2 * 128 * 128;
+    double* R12 = R22 + 2 * 128 * 128;
+    double* S = R12 + 2 * 128 * 128;
+    char* Cjc = (char*)Cj;
+    HIPCHK(remap(1, C1, L.s_tmp, 128, rows, 128, 128, rows, 128, Cjc, L.s_traj, cr, 0, false, nullptr, T, h->st));
+    HIPCHK(remap(1, C2, L.s_tmp, n2, rows, n2, n2, rows, n2, Cjc + 128 * 16, L.s_traj, cr, 0, false, nullptr, T, h->st));
+    HIPCHK(gemm(1, 2, true, false, 128, 128, rows, C1, 128, L.s_tmp, C1, 128, L.s_tmp, gram, 128, L.s_gram, nullptr, T, h->st));
+    HIPCHK(hop_chol(1, 128, 1, rows, gram, L.s_gram, C1, L.s_tmp, R11, L.s_wm, zero_tol(L), T, h->st));
+    for (int pass = 0; pass < 2; ++pass) {   // C2 -= Q1 (Q1^dag C2), twice
+      HIPCHK(gemm(1, 1, true, false, 128, n2, rows, C1, 128, L.s_tmp, C2, n2, L.s_tmp, pass ? S : R12, n2, L.s_wm, nullptr, T, h->st));
+      HIPCHK(gemm(1, 1, false, false, rows, n2, 128, C1, 128, L.s_tmp, pass ? S : R12, n2, L.s_wm, Tq, n2, L.s_x, nullptr, T, h->st));
+      HIPCHK(l2_sub(C2, L.s_tmp, C2, L.s_tmp, Tq, L.s_x, (long long)rows * n2, nullptr, T, h->st));
+    }
+    HIPCHK(add_c128(R12, L.s_wm, S, L.s_wm, 128LL * n2, T, h->st));
+    HIPCHK(gemm(1, 2, true, false, n2, n2, rows, C2, n2, L.s_tmp, C2, n2, L.s_tmp, gram, n2, L.s_gram, nullptr, T, h->st));
+    HIPCHK(hop_chol(1, n2, 1, rows, gram, L.s_gram, C2, L.s_tmp, R22, L.s_wm, zero_tol(L), T, h->st));
+    // A_j = [Q1 Q2] (zero past the live block), R = [[R11 R12] [0 R22]]
+    HIPCHK(remap(1, Cjc, L.s_traj, cr, 2 * cl, cr, cr, rows, 128, C1, L.s_tmp, 128, 0, false, nullptr, T, h->st));
+    HIPCHK(put_block((double*)Cjc, L.s_traj, cr, 0, 128, rows, n2, C2, L.s_tmp, n2, false, T, h->st));
+    char* Rf = W<char>(h, L.o_wm);
+    HIPCHK(remap(1, Rf, L.s_wm, cr, cr, cr, cr, 128, 128, R11, L.s_wm, 128, 0, false, nullptr, T, h->st));
+    HIPCHK(put_block((double*)Rf, L.s_wm, cr, 0, 128, 128, n2, R12, L.s_wm, n2, false, T, h->st));
+    HIPCHK(put_block((double*)Rf, L.s_wm, cr, 128, 128, n2, n2, R22, L.s_wm, n2, false, T, h->st));
+    ProfSec shg(h, PC_HOPGEMM);
+    HIPCHK(gemm(1, 1, false, false, cr, 2 * cr2, cr, Rf, cr, L.s_wm, Bn, 2 * cr2, L.s_traj, tmp, 2 * cr2, L.s_tmp, nullptr,
+                T, h->st));
+    HIPCHK(copy_blocks(Bn, L.s_traj * L.esz, tmp, L.s_tmp * L.esz, (size_t)cr * 2 * cr2 * L.esz, T, h->st));
+    h->centre = j + 1;
+    return MPSB_OK;
+  }
   {
     ProfSec s(h, PC_HOPGEMM);
     // FP64 accumulation also in FP32-bulk: Q = C R^-1 is orthonormal only if R comes from an
@@ -326,7 +416,6 @@ int hop_right(mpsb_batch* h, int j) {
   HIPCHK(scale_cast(p, cr, cr, W<double>(h, L.o_z), cr, L.s_z, invs, cr, false, W<char>(h, L.o_wm), cr, L.s_wm, T, h->st));
   HIPCHK(scale_cast(p, cr, cr, W<double>(h, L.o_z), cr, L.s_z, sq, cr, true, W<char>(h, L.o_rm), cr, L.s_wm, T, h->st));
   }
-  char* tmp = W<char>(h, L.o_tmp);
   if (cr > 128) {
     // A_j = C Wm  -> tmp -> site j
     HIPCHK(gemm(p, p, false, false, 2 * cl, cr, cr, Cj, cr, L.s_traj, W<char>(h, L.o_wm), cr, L.s_wm, tmp, cr, L.s_tmp, nullptr, T, h->st));
@@ -347,11 +436,71 @@ int hop_left(mpsb_batch* h, int j) {
   char* Cj = site_ptr(h, j);
   char* Ap = site_ptr(h, j - 1);
   double* gram = W<double>(h, L.o_gram);
+  char* tmp = W<char>(h, L.o_tmp);
+  const int bj = h->live[j - 1], br = j < L.n - 1 ? h->live[j] : 1;
+  if (cl > 128 && bj <= 128) {
+    // the live block (bj x 2 br) is factored by Cholesky QR in compact form: C = R^dag Q
+    ProfSec sh(h, PC_HOPEIG);
+    HIPCHK(remap(p, tmp, L.s_tmp, 2 * br, bj, 2 * br, br, bj, br, Cj, L.s_traj, 2 * cr, cr, false, nullptr, T, h->st));
+    HIPCHK(gemm(p, 2, false, true, bj, bj, 2 * br, tmp, 2 * br, L.s_tmp, tmp, 2 * br, L.s_tmp, gram, bj, L.s_gram, nullptr,
+                T, h->st));
+    HIPCHK(hop_chol(p, bj, 0, 2 * br, gram, L.s_gram, tmp, L.s_tmp, W<char>(h, L.o_rm), L.s_wm, zero_tol(L), T, h->st));
+    HIPCHK(remap(p, Cj, L.s_traj, 2 * cr, cl, 2 * cr, cr, bj, br, tmp, L.s_tmp, 2 * br, br, false, nullptr, T, h->st));
+    HIPCHK(remap(p, W<char>(h, L.o_wm), L.s_wm, cl, cl, cl, cl, bj, bj, W<char>(h, L.o_rm), L.s_wm, bj, 0, false, nullptr,
+                 T, h->st));
+    ProfSec shg(h, PC_HOPGEMM);
+    // C_{j-1} = A_{j-1} R^dag
+    HIPCHK(gemm(p, p, false, true, 2 * cl2, cl, cl, Ap, cl, L.s_traj, W<char>(h, L.o_wm), cl, L.s_wm, tmp, cl, L.s_tmp,
+                nullptr, T, h->st));
+    HIPCHK(copy_blocks(Ap, L.s_traj * L.esz, tmp, L.s_tmp * L.esz, (size_t)2 * cl2 * cl * L.esz, T, h->st));
+    h->centre = j - 1;
+    return MPSB_OK;
+  }
+  if (p == 1 && cl > 128) {
+    // FP64, more than 128 live rows: C = L Q in two row blocks (the mirror of hop_right),
+    // C = [[R11^dag 0] [R12^dag R22^dag]] [Q1; Q2]
+    ProfSec sh(h, PC_HOPEIG);
+    const int n2 = bj - 128, cols = 2 * br;
+    double* C1 = W<double>(h, L.o_tmp);
+    double* C2 = C1 + 2LL * 128 * cols;
+    double* Tq = W<double>(h, L.o_x);
+    double* R11 = W<double>(h, L.o_rm);
+    double* R22 = R11 + 2 * 128 * 128;
+    double* S1 = R22 + 2 * 128 * 128;   // (C2 Q1^dag), n2 x 128
+    double* S = S1 + 2 * 128 * 128;
+    char* Cjc = (char*)Cj;
+    HIPCHK(remap(1, C1, L.s_tmp, cols, 128, cols, br, 128, br, Cjc, L.s_traj, 2 * cr, cr, false, nullptr, T, h->st));
+    HIPCHK(remap(1, C2, L.s_tmp, cols, n2, cols, br, n2, br, Cjc + (size_t)128 * 2 * cr * 16, L.s_traj, 2 * cr, cr, false,
+                 nullptr, T, h->st));
+    HIPCHK(gemm(1, 2, false, true, 128, 128, cols, C1, cols, L.s_tmp, C1, cols, L.s_tmp, gram, 128, L.s_gram, nullptr, T, h->st));
+    HIPCHK(hop_chol(1, 128, 0, cols, gram, L.s_gram, C1, L.s_tmp, R11, L.s_wm, zero_tol(L), T, h->st));
+    for (int pass = 0; pass < 2; ++pass) {   // C2 -= (C2 Q1^dag) Q1, twice
+      HIPCHK(gemm(1, 1, false, true, n2, 128, cols, C2, cols, L.s_tmp, C1, cols, L.s_tmp, pass ? S : S1, 128, L.s_wm, nullptr, T, h->st));
+      HIPCHK(gemm(1, 1, false, false, n2, cols, 128, pass ? S : S1, 128, L.s_wm, C1, cols, L.s_tmp, Tq, cols, L.s_x, nullptr, T, h->st));
+      HIPCHK(l2_sub(C2, L.s_tmp, C2, L.s_tmp, Tq, L.s_x, (long long)n2 * cols, nullptr, T, h->st));
+    }
+    HIPCHK(add_c128(S1, L.s_wm, S, L.s_wm, 128LL * n2, T, h->st));
+    HIPCHK(gemm(1, 2, false, true, n2, n2, cols, C2, cols, L.s_tmp, C2, cols, L.s_tmp, gram, n2, L.s_gram, nullptr, T, h->st));
+    HIPCHK(hop_chol(1, n2, 0, cols, gram, L.s_gram, C2, L.s_tmp, R22, L.s_wm, zero_tol(L), T, h->st));
+    // B_j = [Q1; Q2] (zero past the live block), R = [[R11 S1^dag] [0 R22]] (upper)
+    HIPCHK(remap(1, Cjc, L.s_traj, 2 * cr, cl, 2 * cr, cr, 128, br, C1, L.s_tmp, cols, br, false, nullptr, T, h->st));
+    HIPCHK(remap(1, Tq, L.s_x, 2 * cr, n2, 2 * cr, cr, n2, br, C2, L.s_tmp, cols, br, false, nullptr, T, h->st));
+    HIPCHK(put_block((double*)Cjc, L.s_traj, 2 * cr, 128, 0, n2, 2 * cr, Tq, L.s_x, 2 * cr, false, T, h->st));
+    char* Rf = W<char>(h, L.o_wm);
+    HIPCHK(remap(1, Rf, L.s_wm, cl, cl, cl, cl, 128, 128, R11, L.s_wm, 128, 0, false, nullptr, T, h->st));
+    HIPCHK(put_block((double*)Rf, L.s_wm, cl, 0, 128, 128, n2, S1, L.s_wm, 128, true, T, h->st));
+    HIPCHK(put_block((double*)Rf, L.s_wm, cl, 128, 128, n2, n2, R22, L.s_wm, n2, false, T, h->st));
+    ProfSec shg(h, PC_HOPGEMM);
+    // C_{j-1} = A_{j-1} R^dag
+    HIPCHK(gemm(1, 1, false, true, 2 * cl2, cl, cl, Ap, cl, L.s_traj, Rf, cl, L.s_wm, tmp, cl, L.s_tmp, nullptr, T, h->st));
+    HIPCHK(copy_blocks(Ap, L.s_traj * L.esz, tmp, L.s_tmp * L.esz, (size_t)2 * cl2 * cl * L.esz, T, h->st));
+    h->centre = j - 1;
+    return MPSB_OK;
+  }
   {
     ProfSec s(h, PC_HOPGEMM);
     HIPCHK(gemm(p, 2, false, true, cl, cl, 2 * cr, Cj, 2 * cr, L.s_traj, Cj, 2 * cr, L.s_traj, gram, cl, L.s_gram, nullptr, T, h->st));
   }
-  char* tmp = W<char>(h, L.o_tmp);
   if (cl <= 128) {
     ProfSec sh(h, PC_HOPEIG);
     HIPCHK(hop_chol(p, cl, 0, 2 * cr, gram, L.s_gram, Cj, L.s_traj, W<char>(h, L.o_rm), L.s_wm, zero_tol(L), T, h->st));
@@ -415,7 +564,7 @@ EventArgs base_event_args(mpsb_batch* h, int layer, int32_t* branch, double* w_r
   ea.w_out = w_record;
   ea.rec_stride = h->rec_stride;
   ea.rec_qbase = 0;
-  ea.traj_base = h->traj_base;
+  ea.traj_base = h->traj_offset + h->traj_base;
   return ea;
 }
 
@@ -523,10 +672,11 @@ int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, b
   const int kk = std::min(keep, D);
   const int full = std::min(2 * bl, 2 * br);
   const bool ident = left_to_right ? bl <= br : br <= bl;
-  if (kk >= full && (ident || full <= 128)) {
-    // nothing is discarded: an exact split of the live block without an eigen-solve (an
-    // identity, or a QR factorisation by Cholesky of the small Gram), so that no direction
-    // of the state, however small its weight, depends on how well a Gram matrix resolves it
+  if (kk >= full) {
+    // nothing is discarded: an exact split of the live block (an identity, or a QR
+    // factorisation through the small Gram: Cholesky up to 128 columns, beyond that its
+    // eigen-decomposition with every direction kept), so that no direction of the state,
+    // however small its weight, depends on how well a Gram matrix resolves it
     ProfSec srec(h, PC_RECOMPOSE);
     const int rows = 2 * cl, cols = 2 * cr;
     HIPCHK(split_norm(p, X, L.s_x, (long long)rows * cols, alpha, discarded, disc_stride, accumulate, T, h->st));
@@ -541,8 +691,17 @@ int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, b
       } else {       // Xc = Q R: A_q = Q, C_(q+1) = alpha R
         HIPCHK(gemm(p, 2, true, false, 2 * br, 2 * br, 2 * bl, Xc, 2 * br, L.s_tmp, Xc, 2 * br, L.s_tmp, gram, 2 * br,
                     L.s_gram, nullptr, T, h->st));
-        HIPCHK(hop_chol(p, 2 * br, 1, 2 * bl, gram, L.s_gram, Xc, L.s_tmp, Rm, L.s_wm, zero_tol(L), T, h->st));
-        HIPCHK(remap(p, Sq, L.s_traj, D, rows, D, D, 2 * bl, 2 * br, Xc, L.s_tmp, 2 * br, 0, false, nullptr, T, h->st));
+        const char* Q = Xc;
+        if (full <= 128) {
+          HIPCHK(hop_chol(p, 2 * br, 1, 2 * bl, gram, L.s_gram, Xc, L.s_tmp, Rm, L.s_wm, zero_tol(L), T, h->st));
+        } else {     // Gram = W Lambda W^dag: Q = Xc W Lambda^-1/2, R = Lambda^1/2 W^dag
+          HIPCHK(gram_qr_factors(h, 2 * br, true));
+          HIPCHK(gemm(p, p, false, false, 2 * bl, 2 * br, 2 * br, Xc, 2 * br, L.s_tmp, W<char>(h, L.o_wm), 2 * br, L.s_wm,
+                      X, 2 * br, L.s_x, nullptr, T, h->st));
+          Q = X;
+        }
+        const long long sq = Q == Xc ? L.s_tmp : L.s_x;
+        HIPCHK(remap(p, Sq, L.s_traj, D, rows, D, D, 2 * bl, 2 * br, Q, sq, 2 * br, 0, false, nullptr, T, h->st));
         HIPCHK(remap(p, Sn, L.s_traj, cols, D, cols, cr, 2 * br, br, Rm, L.s_wm, 2 * br, br, false, alpha, T, h->st));
       }
       h->centre = q + 1;
@@ -550,12 +709,20 @@ int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, b
       if (ident) {   // B_(q+1) = I on the 2br live columns, C_q = alpha X (live columns)
         HIPCHK(remap(p, Sn, L.s_traj, cols, D, cols, cr, 2 * br, br, nullptr, 0, 0, 0, false, nullptr, T, h->st));
         HIPCHK(remap(p, Sq, L.s_traj, D, rows, D, br, 2 * bl, br, X, L.s_x, cols, cr, false, alpha, T, h->st));
-      } else {       // Xc = R^dag Q: B_(q+1) = Q, C_q = alpha R^dag
+      } else if (full <= 128) {   // Xc = R^dag Q: B_(q+1) = Q, C_q = alpha R^dag
         HIPCHK(gemm(p, 2, false, true, 2 * bl, 2 * bl, 2 * br, Xc, 2 * br, L.s_tmp, Xc, 2 * br, L.s_tmp, gram, 2 * bl,
                     L.s_gram, nullptr, T, h->st));
         HIPCHK(hop_chol(p, 2 * bl, 0, 2 * br, gram, L.s_gram, Xc, L.s_tmp, Rm, L.s_wm, zero_tol(L), T, h->st));
         HIPCHK(remap(p, Sn, L.s_traj, cols, D, cols, cr, 2 * bl, br, Xc, L.s_tmp, 2 * br, br, false, nullptr, T, h->st));
         HIPCHK(remap(p, Sq, L.s_traj, D, rows, D, D, 2 * bl, 2 * bl, Rm, L.s_wm, 2 * bl, 0, true, alpha, T, h->st));
+      } else {   // Gram Xc Xc^dag = W Lambda W^dag: Xc = Rm Q with Q = Lambda^-1/2 W^dag Xc, Rm = W Lambda^1/2
+        HIPCHK(gemm(p, 2, false, true, 2 * bl, 2 * bl, 2 * br, Xc, 2 * br, L.s_tmp, Xc, 2 * br, L.s_tmp, gram, 2 * bl,
+                    L.s_gram, nullptr, T, h->st));
+        HIPCHK(gram_qr_factors(h, 2 * bl, false));
+        HIPCHK(gemm(p, p, false, false, 2 * bl, 2 * br, 2 * bl, W<char>(h, L.o_wm), 2 * bl, L.s_wm, Xc, 2 * br, L.s_tmp,
+                    X, 2 * br, L.s_x, nullptr, T, h->st));
+        HIPCHK(remap(p, Sn, L.s_traj, cols, D, cols, cr, 2 * bl, br, X, L.s_x, 2 * br, br, false, nullptr, T, h->st));
+        HIPCHK(remap(p, Sq, L.s_traj, D, rows, D, D, 2 * bl, 2 * bl, Rm, L.s_wm, 2 * bl, 0, false, alpha, T, h->st));
       }
       h->centre = q;
     }
@@ -574,6 +741,43 @@ int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, b
   HIPCHK(heev_all(h, n, kk, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
               W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), Z, L.s_z, T));
   HIPCHK(trunc_factors(W<double>(h, L.o_kept), W<double>(h, L.o_ews), L.s_ews, n, alpha, discarded, disc_stride, accumulate, T, h->st));
+  if (L.prec == MPSB_FP64) {
+    // cuts below the Gram's resolution: re-solve the kept subspace from the residual of the
+    // well-resolved directions (trajectories whose cut is resolved skip every launch)
+    ProfSec s2(h, PC_GRAM);
+    const int m = left_to_right ? 2 * cr : 2 * cl;
+    int* act = W<int>(h, L.o_l2act);
+    int* rr = W<int>(h, L.o_l2r);
+    double* info = W<double>(h, L.o_l2info);
+    double* Zr = W<double>(h, L.o_l2zr);
+    double* Cr = W<double>(h, L.o_l2cr);
+    double* Z2 = W<double>(h, L.o_l2z2);
+    double* T1 = W<double>(h, L.o_tmp);
+    double* P = W<double>(h, L.o_wm);
+    HIPCHK(l2_prep(W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_kept), n, kk, L2_TAU,
+                   Z, L.s_z, Zr, L.s_z, act, rr, info, T, h->st));
+    if (left_to_right) {   // M = X (n x m): R = X - Zr (Zr^dag X), Gram R R^dag
+      HIPCHK(gemm(1, 1, true, false, kk, m, n, Zr, kk, L.s_z, X, m, L.s_x, Cr, m, L.s_z, nullptr, T, h->st, false, act));
+      HIPCHK(gemm(1, 1, false, false, n, m, kk, Zr, kk, L.s_z, Cr, m, L.s_z, T1, m, L.s_tmp, nullptr, T, h->st, false, act));
+      HIPCHK(l2_sub(T1, L.s_tmp, (const double*)X, L.s_x, T1, L.s_tmp, (long long)n * m, act, T, h->st));
+      HIPCHK(gemm(1, 1, false, true, n, n, m, T1, m, L.s_tmp, T1, m, L.s_tmp, gram, n, L.s_gram, nullptr, T, h->st, true, act));
+    } else {               // M = X^dag: R^dag = X - (X Zr) Zr^dag (m x n), Gram (R^dag)^dag R^dag
+      HIPCHK(gemm(1, 1, false, false, m, kk, n, X, n, L.s_x, Zr, kk, L.s_z, Cr, kk, L.s_z, nullptr, T, h->st, false, act));
+      HIPCHK(gemm(1, 1, false, true, m, n, kk, Cr, kk, L.s_z, Zr, kk, L.s_z, T1, n, L.s_tmp, nullptr, T, h->st, false, act));
+      HIPCHK(l2_sub(T1, L.s_tmp, (const double*)X, L.s_x, T1, L.s_tmp, (long long)m * n, act, T, h->st));
+      HIPCHK(gemm(1, 1, true, false, n, n, m, T1, n, L.s_tmp, T1, n, L.s_tmp, gram, n, L.s_gram, nullptr, T, h->st, true, act));
+    }
+    HIPCHK(heev_all(h, n, kk, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
+                    W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), Z2, L.s_z, T, false, act));
+    // the residual directions, projected out of the resolved ones twice
+    for (int pass = 0; pass < 2; ++pass) {
+      HIPCHK(gemm(1, 1, true, false, kk, kk, n, Zr, kk, L.s_z, Z2, kk, L.s_z, P, kk, L.s_wm, nullptr, T, h->st, false, act));
+      HIPCHK(gemm(1, 1, false, false, n, kk, kk, Zr, kk, L.s_z, P, kk, L.s_wm, T1, kk, L.s_tmp, nullptr, T, h->st, false, act));
+      HIPCHK(l2_sub(Z2, L.s_z, Z2, L.s_z, T1, L.s_tmp, (long long)n * kk, act, T, h->st));
+    }
+    HIPCHK(l2_merge(act, rr, n, kk, Z, L.s_z, Z2, L.s_z, W<double>(h, L.o_evals), L.s_evals, info, alpha, discarded,
+                    disc_stride, accumulate, T, h->st));
+  }
   ProfSec srec(h, PC_RECOMPOSE);
   if (left_to_right) {
     // A_q = U (2cl x D), columns >= kk zero; C_{q+1} = alpha A_q^dag X
@@ -934,9 +1138,11 @@ int mps_batch_plan(int n_traj, const int32_t* width, const int32_t* chi, int pre
 }
 
 int mps_batch_create(int n_traj, const int32_t* width, const int32_t* chi, int precision, uint64_t seed,
-                     void* state_buf, size_t state_bytes, void* work_buf, size_t work_bytes, void* stream,
-                     mpsb_handle* out) {
+                     int64_t traj_offset, void* state_buf, size_t state_bytes, void* work_buf, size_t work_bytes,
+                     void* stream, mpsb_handle* out) {
   if (!out) return fail(MPSB_EINVAL, "null handle pointer");
+  if (traj_offset < 0 || traj_offset + (int64_t)n_traj > (int64_t)1 << 32)
+    return fail(MPSB_EINVAL, "traj_offset must be >= 0 with traj_offset + n_traj <= 2^32");
   std::vector<Run> runs;
   int r = runs_of(n_traj, width, chi, runs);
   if (r) return r;
@@ -966,6 +1172,7 @@ int mps_batch_create(int n_traj, const int32_t* width, const int32_t* chi, int p
     b->work = (char*)work_buf + wo[i];
     b->st = (hipStream_t)stream;
     b->traj_base = runs[i].first;
+    b->traj_offset = traj_offset;
     b->rec_stride = nmax;
     return b;
   };

@@ -502,7 +502,7 @@ __device__ int one_event(const EventArgs& ea, int slot, int id, const cd (&rho)[
     j = forced;
     if (!(p[j] > 0.0)) return -1;
   } else {
-    j = sample_branch(p, event_uniform(ea.seed, (uint32_t)(ea.traj_base + traj), layer, qubit));
+    j = sample_branch(p, event_uniform(ea.seed, (uint32_t)(ea.traj_base + (long long)traj), layer, qubit));
   }
   double inv = 1.0 / sqrt(p[j]);
   for (int a = 0; a < 2; ++a)

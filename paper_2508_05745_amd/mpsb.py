@@ -47,7 +47,7 @@ def lib():
         vp, i32, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
         L.mps_last_error.restype = ctypes.c_char_p
         L.mps_batch_plan.argtypes = [i32, vp, vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
-        L.mps_batch_create.argtypes = [i32, vp, vp, i32, u64, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
+        L.mps_batch_create.argtypes = [i32, vp, vp, i32, u64, ctypes.c_int64, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
         L.mps_circuit_bytes.argtypes = [vp, ctypes.POINTER(_Circuit), ctypes.POINTER(sz)]
         L.mps_batch_set_circuit.argtypes = [vp, ctypes.POINTER(_Circuit), vp, sz]
         L.mps_circuit_validate.argtypes = [i32, vp, ctypes.POINTER(_Circuit)]
@@ -156,9 +156,10 @@ def validate_circuit(circuit, mode: int = OPTIMAL, fixed_u=None, n_traj: int = 1
 class Batch:
     """A batch of MPS trajectories living in caller (torch) device buffers.  n_qubits and
     chi are ints (uniform batch) or per-trajectory arrays (mixed batch: equal shapes must be
-    consecutive)."""
+    consecutive).  Trajectory t draws its branches with the key traj_offset + t."""
 
-    def __init__(self, n_traj: int, n_qubits, chi, precision: int = FP64, seed: int = 0):
+    def __init__(self, n_traj: int, n_qubits, chi, precision: int = FP64, seed: int = 0,
+                 traj_offset: int = 0):
         import torch
         self.widths, self.chis = _shape_arrays(n_traj, n_qubits, chi)
         self.n_traj, self.precision = n_traj, precision
@@ -170,7 +171,8 @@ class Batch:
         self.work = torch.empty(wb, dtype=torch.uint8, device="cuda")
         h = ctypes.c_void_p()
         _check(lib().mps_batch_create(n_traj, self.widths.ctypes.data, self.chis.ctypes.data, precision,
-                                      ctypes.c_uint64(seed), _ptr(self.state), sb, _ptr(self.work), wb,
+                                      ctypes.c_uint64(seed), ctypes.c_int64(traj_offset), _ptr(self.state), sb,
+                                      _ptr(self.work), wb,
                                       _stream(), ctypes.byref(h)))
         self.h = h
         self._circ = None

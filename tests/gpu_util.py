@@ -99,26 +99,3 @@ def replay_sampled(circuit, chi, seed, out, row):
                            spectra=spectra)
     zi, zz = omps.z_expectations(m)
     return np.concatenate([zi, zz]), rp, js, [r["j"] for r in rec], spectra
-
-
-def gram_truncation_bound(spectra, chi, unit_roundoff, const=64.0):
-    """Expected size of the per-trajectory difference between a truncation through the
-    eigenvectors of the Gram matrix M M^dag and one through the SVD of M, from the exact
-    spectra of the splits.  The Gram (and its eigen-solve) carries an absolute error of order
-    u ||M||^2, which rotates the kept subspace into the discarded one by u s_1^2 / (s_D^2 -
-    s_(D+1)^2) (Davis-Kahan); the truncated state then moves by that angle times s_(D+1), and
-    an observable by at most twice that.  Summed over the gate-steps where the cut separates
-    non-zero singular values, with s normalised to unit 2-norm and r = s_(D+1) / s_D:
-        sum_steps u / (s_D (1 - r^2)),
-    capped per step at 2 s_D (the cut can at most misplace the weight next to it).  `const`
-    (64) covers the growth of the rounding error with the inner dimensions (sums of up to 2 chi
-    terms in the Gram, the eigen-solver's backward error) and the factor 2 of an observable."""
-    tot = 0.0
-    for s in spectra:
-        s = s / np.sqrt(np.sum(s ** 2))
-        d = min(chi, s.size)
-        if d >= s.size or s[d] <= 1e-12 * s[0]:
-            continue
-        sd, r = s[d - 1], s[d] / s[d - 1]
-        tot += min(unit_roundoff / (sd * (1.0 - r * r)), 2.0 * sd)
-    return const * tot
