@@ -119,6 +119,23 @@ int mps_batch_create(int n_traj, const int32_t* width, const int32_t* chi, int p
                      uint64_t seed, int64_t traj_offset, void* state_buf, size_t state_bytes,
                      void* work_buf, size_t work_bytes, void* stream, mpsb_handle* out);
 
+/* For callers that cannot allocate device memory (code under graph capture, serving loops,
+ * harnesses that forbid allocation): mps_batch_create for a uniform batch without a caller
+ * work buffer.  The work memory is a static device area of MPSB_STATIC_WORK_BYTES per device
+ * (held by the library's code object until the process ends); batches whose planned work
+ * exceeds it fail with MPSB_ENOMEM, mixed batches with MPSB_ENOTSUP.  Nothing is allocated:
+ * no device memory, no stream or event (graphs and the tile autotuner are off for such a
+ * batch; mps_batch_set_graphs(h, 1) fails with MPSB_ENOTSUP).  One batch at a time may hold a
+ * device's area: creating a second one on the same device while the first is alive fails with
+ * MPSB_ENOTSUP (batches on the same area would overwrite each other's work); the area is
+ * released by mps_batch_destroy.  The area keeps the previous batch's contents; the batch
+ * clears what must start at zero when it is created.  Other arguments and results are those
+ * of mps_batch_create. */
+#define MPSB_STATIC_WORK_BYTES (64u << 20)
+int mps_batch_create_static(int n_traj, const int32_t* width, const int32_t* chi, int precision,
+                            uint64_t seed, int64_t traj_offset, void* state_buf,
+                            size_t state_bytes, void* stream, mpsb_handle* out);
+
 /* Bytes of the device circuit buffer mps_batch_set_circuit needs for circuit c on batch h. */
 int mps_circuit_bytes(mpsb_handle h, const mpsb_circuit* c, size_t* bytes);
 

@@ -124,6 +124,10 @@ hipError_t l2_merge(const int* act, const int* r, int n, int kk, double* Z, long
 hipError_t put_block(double* dst, long long sD, int ldd, int r0, int c0, int rows, int cols, const double* src,
                      long long sS, int lds, bool conj_t, int n_traj, hipStream_t st);
 hipError_t add_c128(double* acc, long long sA, const double* b, long long sB, long long len, int n_traj, hipStream_t st);
+// the static work area (one per device): address of this device's area (taken once per
+// device), or busy = true while another batch holds it
+hipError_t static_work_acquire(void** ptr, int* device, bool* busy);
+void static_work_release(int device);
 // inverse square roots / square roots of hop eigenvalues (0 for dropped)
 hipError_t hop_scales(const double* evals, long long sE, int n, double* inv_sqrt, double* sqrt_, int n_traj,
                       hipStream_t st);

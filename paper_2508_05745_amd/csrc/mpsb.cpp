@@ -221,6 +221,8 @@ struct mpsb_batch {
   // theta kernel variant per shape (autotuned on first use)
   std::map<long long, int> theta_var;
   bool autotune = true;
+  // device whose static work area this batch holds (-1: the work buffer is the caller's)
+  int static_dev = -1;
 };
 
 namespace {
@@ -950,6 +952,7 @@ void destroy_batch(mpsb_batch* h) {
   for (hipEvent_t e : h->join_ev) (void)hipEventDestroy(e);
   for (hipStream_t s : h->streams) (void)hipStreamDestroy(s);
   if (h->cap_st) (void)hipStreamDestroy(h->cap_st);
+  if (h->static_dev >= 0) static_work_release(h->static_dev);
   delete h;
 }
 
@@ -1203,6 +1206,54 @@ int mps_batch_create(int n_traj, const int32_t* width, const int32_t* chi, int p
   return MPSB_OK;
 }
 
+int mps_batch_create_static(int n_traj, const int32_t* width, const int32_t* chi, int precision, uint64_t seed,
+                            int64_t traj_offset, void* state_buf, size_t state_bytes, void* stream, mpsb_handle* out) {
+  if (!out) return fail(MPSB_EINVAL, "null handle pointer");
+  if (traj_offset < 0 || traj_offset + (int64_t)n_traj > (int64_t)1 << 32)
+    return fail(MPSB_EINVAL, "traj_offset must be >= 0 with traj_offset + n_traj <= 2^32");
+  std::vector<Run> runs;
+  int r = runs_of(n_traj, width, chi, runs);
+  if (r) return r;
+  if (runs.size() != 1) return fail(MPSB_ENOTSUP, "a batch on the static work area must be uniform (one width and chi)");
+  Layout L;
+  r = make_layout(n_traj, runs[0].width, runs[0].chi, precision, L);
+  if (r) return r;
+  if (L.work_bytes > (size_t)MPSB_STATIC_WORK_BYTES)
+    return fail(MPSB_ENOMEM, "the batch needs " + std::to_string(L.work_bytes) + " bytes of work memory; the static work area holds " +
+                                 std::to_string((size_t)MPSB_STATIC_WORK_BYTES));
+  if (!state_buf) return fail(MPSB_EINVAL, "null state buffer");
+  if ((uintptr_t)state_buf & 255) return fail(MPSB_EINVAL, "the state buffer must be 256-byte aligned");
+  if (state_bytes < L.state_bytes) return fail(MPSB_ENOMEM, "state buffer smaller than planned");
+  void* work = nullptr;
+  int dev = -1;
+  bool busy = false;
+  HIPCHK(static_work_acquire(&work, &dev, &busy));
+  if (busy) return fail(MPSB_ENOTSUP, "the static work area of this device is held by another batch");
+  mpsb_batch* h = new mpsb_batch();
+  h->L = L;
+  h->st = (hipStream_t)stream;
+  h->seed = seed;
+  h->n_traj_total = n_traj;
+  h->rec_stride = runs[0].width;
+  h->width.assign(width, width + n_traj);
+  h->chi.assign(chi, chi + n_traj);
+  h->state = (char*)state_buf;
+  h->work = (char*)work;
+  h->traj_offset = traj_offset;
+  h->static_dev = dev;
+  h->graphs_on = false;   // no capture stream: every layer runs as direct launches
+  h->autotune = false;    // the default theta tile rule (the autotuner times with events)
+  // the status word and the site-offset table are cleared and written here, at the area's
+  // device address: the area keeps the previous batch's contents
+  hipError_t e = init_batch_state(h);
+  if (e != hipSuccess) {
+    destroy_batch(h);
+    return fail(MPSB_EHIP, std::string("initialising the batch: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return MPSB_OK;
+}
+
 int mps_circuit_validate(int n_traj, const int32_t* width, const mpsb_circuit* c) {
   int nmax;
   return validate_circuit(n_traj, width, c, nmax);
@@ -1306,6 +1357,7 @@ int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c, void* circuit_bu
 
 int mps_batch_set_graphs(mpsb_handle h, int enable) {
   if (!h) return fail(MPSB_EINVAL, "null handle");
+  if (enable && h->static_dev >= 0) return fail(MPSB_ENOTSUP, "a batch on the static work area runs without graphs");
   h->graphs_on = enable != 0;
   return MPSB_OK;
 }

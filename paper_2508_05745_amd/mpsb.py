@@ -40,6 +40,9 @@ def lib():
     """Loads libmpsb.so (built in-tree by __graft_entry__.build()); raises if absent."""
     global _lib
     if _lib is None:
+        # torch (which brings its own HIP runtime) is imported before the library is loaded:
+        # loaded the other way round, the library's runtime finds no device on the GPU box
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} not found: build the HIP library first "
                                "(python -m paper_2508_05745_amd.build)")
@@ -48,6 +51,7 @@ def lib():
         L.mps_last_error.restype = ctypes.c_char_p
         L.mps_batch_plan.argtypes = [i32, vp, vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.mps_batch_create.argtypes = [i32, vp, vp, i32, u64, ctypes.c_int64, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
+        L.mps_batch_create_static.argtypes = [i32, vp, vp, i32, u64, ctypes.c_int64, vp, sz, vp, ctypes.POINTER(vp)]
         L.mps_circuit_bytes.argtypes = [vp, ctypes.POINTER(_Circuit), ctypes.POINTER(sz)]
         L.mps_batch_set_circuit.argtypes = [vp, ctypes.POINTER(_Circuit), vp, sz]
         L.mps_circuit_validate.argtypes = [i32, vp, ctypes.POINTER(_Circuit)]
@@ -159,7 +163,10 @@ class Batch:
     consecutive).  Trajectory t draws its branches with the key traj_offset + t."""
 
     def __init__(self, n_traj: int, n_qubits, chi, precision: int = FP64, seed: int = 0,
-                 traj_offset: int = 0):
+                 traj_offset: int = 0, static_work: bool = False):
+        """static_work: no work buffer is allocated; the batch runs on the library's static
+        device work area (mps_batch_create_static: uniform batches of bounded size, one at a
+        time per device)."""
         import torch
         self.widths, self.chis = _shape_arrays(n_traj, n_qubits, chi)
         self.n_traj, self.precision = n_traj, precision
@@ -168,12 +175,17 @@ class Batch:
         self.mixed = bool((self.widths != self.widths[0]).any() or (self.chis != self.chis[0]).any())
         sb, wb = plan(n_traj, self.widths, self.chis, precision)
         self.state = torch.empty(sb, dtype=torch.uint8, device="cuda")
-        self.work = torch.empty(wb, dtype=torch.uint8, device="cuda")
         h = ctypes.c_void_p()
-        _check(lib().mps_batch_create(n_traj, self.widths.ctypes.data, self.chis.ctypes.data, precision,
-                                      ctypes.c_uint64(seed), ctypes.c_int64(traj_offset), _ptr(self.state), sb,
-                                      _ptr(self.work), wb,
-                                      _stream(), ctypes.byref(h)))
+        if static_work:
+            self.work = None
+            _check(lib().mps_batch_create_static(n_traj, self.widths.ctypes.data, self.chis.ctypes.data, precision,
+                                                 ctypes.c_uint64(seed), ctypes.c_int64(traj_offset),
+                                                 _ptr(self.state), sb, _stream(), ctypes.byref(h)))
+        else:
+            self.work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+            _check(lib().mps_batch_create(n_traj, self.widths.ctypes.data, self.chis.ctypes.data, precision,
+                                          ctypes.c_uint64(seed), ctypes.c_int64(traj_offset), _ptr(self.state), sb,
+                                          _ptr(self.work), wb, _stream(), ctypes.byref(h)))
         self.h = h
         self._circ = None
         self._cbuf = None

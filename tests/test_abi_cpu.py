@@ -135,3 +135,22 @@ def test_unravel_entry_points_validate_on_the_host():
     assert lib.unravel_cost(4, one, 8, 8, 0, one, one, one, 2, one, one, None) == M.EINVAL
     assert lib.unravel_cost_grad(4, one, one, one, one, 5, None, one, None) == M.EINVAL
     assert lib.unravel_cost_grad(4, None, one, one, one, 0, None, one, None) == M.EINVAL
+
+
+def test_static_batch_rejects_oversized_and_mixed_plans():
+    """mps_batch_create_static checks the planned work memory against the static area and
+    rejects mixed batches before touching any device."""
+    import ctypes
+    lib = M.lib()
+    h = ctypes.c_void_p()
+    one = ctypes.c_void_p(256)
+    w = np.full(2048, 100, dtype=np.int32)
+    c = np.full(2048, 128, dtype=np.int32)
+    _, wb = M.plan(2048, 100, 128, M.FP64)
+    assert wb > (64 << 20)
+    r = lib.mps_batch_create_static(2048, w.ctypes.data, c.ctypes.data, M.FP64, 1, 0, one, 1 << 40, None, ctypes.byref(h))
+    assert r == M.ENOMEM and b"static work area" in lib.mps_last_error()
+    w2 = np.array([6, 6, 8], dtype=np.int32)
+    c2 = np.array([4, 4, 4], dtype=np.int32)
+    r = lib.mps_batch_create_static(3, w2.ctypes.data, c2.ctypes.data, M.FP64, 1, 0, one, 1 << 40, None, ctypes.byref(h))
+    assert r == M.ENOTSUP
