@@ -176,6 +176,17 @@ int mps_batch_set_autotune(mpsb_handle h, int enable);
 int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch,
                 double* w_record);
 
+/* apply_layer following recorded decisions (Alg. 1 with its choices given): w_in [n_traj][W]
+ * [4][4] c128 (the w_record layout) replaces the mixing the unravel mode would choose for each
+ * event, branch_in [n_traj][W] int32 (the branch layout) replaces the draw; either may be NULL
+ * (then chosen / drawn as in apply_layer); entries of qubits without an event are not read.
+ * The branch weights are still computed from this batch's own state, so that a run in another
+ * precision can follow a recorded run event by event (paired comparison); a replayed branch of
+ * zero weight is reported as MPSB_ENUM by mps_batch_sync.  Device pointers; the outputs are
+ * those of apply_layer.  Layers with replay inputs run without graphs. */
+int apply_layer_replay(mpsb_handle h, int layer, const double* w_in, const int32_t* branch_in,
+                       double* discarded, int32_t* branch, double* w_record);
+
 /* Channel-unravelling subprocedure (Alg. 1) for one noise event per trajectory on qubit
  * qubit[t] (host array [n_traj], the centre is moved there first) with channel
  * `channel`, mode `unravel_mode` (MPSB_FIXED uses the circuit's fixed_u).  forced: host
@@ -203,7 +214,10 @@ int mps_circuit_validate(int n_traj, const int32_t* width, const mpsb_circuit* c
 /* Observable estimation from sampled trajectories (Sec. "Target classical simulation
  * tasks", Lemma "Expectation value estimation from trajectory sampling" and its corollary:
  * the estimator is the mean over trajectories of <psi_i|O|psi_i>).  Observables of every
- * trajectory: <Z_i> (i = 0..n-1) then <Z_i Z_{i+1}> (i = 0..n-2), computed in FP64 with left/right environments (normalised by <psi|psi>).  Device
+ * trajectory: <Z_i> (i = 0..n-1) then <Z_i Z_{i+1}> (i = 0..n-2), in FP64, normalised by
+ * <psi|psi>, from a measurement sweep: the orthogonality centre walks from site 0 to n-2 and
+ * each pair's two-site reduced state is accumulated by the two-site contraction (so the call
+ * leaves the centre at site n-2; the state itself is unchanged).  Device
  * outputs: mean [2n-1] and m2 [2n-1] (sum of squared deviations) over trajectories,
  * reduced in a fixed order (bitwise reproducible), or both NULL; per_traj [n_traj][2W-1]
  * (or NULL), rows NaN-padded past a trajectory's own 2n-1 entries.  A mixed batch
@@ -229,6 +243,30 @@ int mps_profile_read(mpsb_handle h, double* ms, long long* count, int n);
 int mps_batch_sync(mpsb_handle h);
 int mps_batch_destroy(mpsb_handle h);
 const char* mps_last_error(void);
+
+/* Certified error of the sampled trajectories (Sec. "Upper bounds on the simulation errors",
+ * Thm. "Truncated Trajectory Sampling error"; Props. "Path error bound" and "systematic error
+ * bound"; Sec. "Errors based on MPS truncations"; Sec. "Improvements of the error bounds due to
+ * concentration").
+ *
+ * mps_error_accumulate: eps_tot[t] += weight * sum over the layer's truncation steps of the
+ * step's trace-norm change, from discarded [n_traj][slots] FP64 (apply_layer's output, slots =
+ * W/2; zero for steps that discard nothing): MPSB_STEP_EXACT = 2 sqrt(eps) (exact for one
+ * truncated bond with renormalisation), MPSB_STEP_PAPER = 4 sqrt(2 eps) (the paper's bound).
+ * weight = 1 gives Thm. 1's cumulated error; alpha^(L-l) or min(sqrt(8n)(1-p)^(L-l), 1) the
+ * concentration variants (layers l = 1..L).  eps_tot [n_traj] is device memory that the
+ * caller zeroes before the first layer.
+ * mps_error_estimate: out[0] = eps_hat = mean over trajectories of eps_bound (eps_tot if
+ * eps_tot <= eps_max - 2, else eps_max; 2 <= eps_max), out[1] = the Hoeffding buffer
+ * sqrt(eps_max^2 log(1/delta) / (2 n_traj)), out[2] = out[0] + out[1]: with probability at
+ * least 1 - delta the trace distance between the exact state and the sampled mixture is at
+ * most out[2].  The sum runs in a fixed order.  Device pointers; asynchronous on `stream`. */
+#define MPSB_STEP_EXACT 0
+#define MPSB_STEP_PAPER 1
+int mps_error_accumulate(int n_traj, int slots, const double* discarded, int step_kind,
+                         double weight, double* eps_tot, void* stream);
+int mps_error_estimate(int n_traj, const double* eps_tot, double eps_max, double delta,
+                       double* out, void* stream);
 
 /* Batched locally entanglement-optimal unravelling (Sec. "Locally entanglement-optimal
  * unraveling"; appendix "Practical/closed-form version" of Wootters' decomposition): for

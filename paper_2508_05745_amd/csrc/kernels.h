@@ -21,6 +21,10 @@ struct EventArgs {
   uint64_t seed;
   int32_t* branch_out;   // [n_traj][rec_stride] or NULL
   double* w_out;         // [n_traj][rec_stride][4][4] c128 or NULL
+  // replay inputs in the record layouts (NULL: choose / draw): the mixing U and the branch
+  // of each event are taken from here instead
+  const double* w_in;
+  const int32_t* branch_in;
   int n_kraus[2];
   double kraus[2][32];
   double fixed_u[2][32];
@@ -136,14 +140,16 @@ hipError_t hop_scales(const double* evals, long long sE, int n, double* inv_sqrt
 hipError_t hop_chol(int prec, int n, int left_to_right, int other, const void* E, long long sE, void* C, long long sC,
                     void* Rout, long long sR, double tol, int n_traj, hipStream_t st);
 
-// observables
-hipError_t env_init(double* env, long long s_env, int n_traj, hipStream_t st);
-hipError_t widen(const void* in, long long s_in, void* out, long long s_out, long long len, int n_traj, hipStream_t st);
-hipError_t neg_cols(void* X, long long sX, int rows, int ld, int c0, int w, int n_traj, hipStream_t st);
 hipError_t zero_cols(int prec, void* X, long long sX, int rows, int ld, int c0, int w, int n_traj, hipStream_t st);
-hipError_t obs_trace(int chi, const double* X, long long s_env, const double* R, long long s_R, double* out,
-                     int out_stride, int n_traj, hipStream_t st);
-hipError_t obs_normalise(double* per_traj, int n_obs, int stride, const double* norms, int n_traj, hipStream_t st);
+// observables: <Z_i>, <Z_i Z_(i+1)> from the two-site reduced state of a theta step (identity
+// gate), and the deterministic mean / M2 over trajectories
+hipError_t obs_pair(const double* partial, int n_tiles, int i, int n, double* per_traj, int stride, int n_traj,
+                    hipStream_t st);
+hipError_t fill_nan(double* per_traj, int stride, int c0, int n_traj, hipStream_t st);
+// certified error: per-trajectory accumulation of a layer's step errors, and the estimate
+hipError_t err_accumulate(int n_traj, int slots, const double* disc, int kind, double weight, double* eps_tot,
+                          hipStream_t st);
+hipError_t err_estimate(int n_traj, const double* eps_tot, double eps_max, double delta, double* out, hipStream_t st);
 hipError_t obs_reduce(const double* per_traj, int n_obs, int n_traj, double* mean, double* m2, hipStream_t st);
 
 // unravelling cost

@@ -142,95 +142,34 @@ hipError_t hop_scales(const double* evals, long long sE, int n, double* inv_sqrt
   return hipGetLastError();
 }
 
-// c64 -> c128 copy of a batch of contiguous blocks
-__global__ void k_widen(const c32* __restrict__ in, long long s_in, c64d* __restrict__ out, long long s_out, long long len,
-                        int n_traj) {
-  long long total = len * n_traj;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
-    int t = (int)(e / len);
-    long long i = e % len;
-    c32 v = in[t * s_in + i];
-    out[t * s_out + i] = c64d{(double)v.re, (double)v.im};
-  }
+
+// Observables of a two-site step with the identity gate: the 4 x 4 two-site reduced state of
+// sites (i, i+1) summed over the theta tiles' partials in a fixed order (FP64), then
+// <Z_i>, <Z_i Z_(i+1)> (and <Z_(i+1)> for the last pair) normalised by its trace, into row
+// traj of per_traj (stride doubles): <Z_k> at k, <Z_k Z_(k+1)> at n + k.
+__global__ void k_obs_pair(const double* __restrict__ partial, int n_tiles, int i, int n, double* __restrict__ per_traj,
+                           int stride, int n_traj) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_traj) return;
+  const double* pp = partial + (long long)t * n_tiles * 32;
+  double d[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < n_tiles; ++k)
+    for (int x = 0; x < 4; ++x) d[x] += pp[k * 32 + 2 * (5 * x)];   // diagonal element (x, x)
+  const double tr = (d[0] + d[1]) + (d[2] + d[3]);
+  const double inv = tr > 0.0 ? 1.0 / tr : __builtin_nan("");
+  double* o = per_traj + (long long)t * stride;
+  o[i] = ((d[0] + d[1]) - (d[2] + d[3])) * inv;          // x = 2 s + t: s = 0 for x < 2
+  o[n + i] = ((d[0] - d[1]) - (d[2] - d[3])) * inv;      // z_s z_t
+  if (i == n - 2) o[n - 1] = ((d[0] - d[1]) + (d[2] - d[3])) * inv;
 }
 
-hipError_t widen(const void* in, long long s_in, void* out, long long s_out, long long len, int n_traj, hipStream_t st) {
-  hipLaunchKernelGGL(k_widen, dim3(nblocks(len * n_traj)), dim3(256), 0, st, (const c32*)in, s_in, (c64d*)out, s_out, len, n_traj);
+hipError_t obs_pair(const double* partial, int n_tiles, int i, int n, double* per_traj, int stride, int n_traj,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_obs_pair, dim3((n_traj + 127) / 128), dim3(128), 0, st, partial, n_tiles, i, n, per_traj, stride,
+                     n_traj);
   return hipGetLastError();
 }
 
-// negate columns [c0, c0+w) of rows x ld matrices (c128)
-__global__ void k_neg_cols(c64d* X, long long sX, int rows, int ld, int c0, int w, int n_traj) {
-  long long per = (long long)rows * w, total = per * n_traj;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
-    int t = (int)(e / per);
-    long long r = e % per;
-    int i = (int)(r / w), j = (int)(r % w);
-    c64d& v = X[t * sX + (long long)i * ld + c0 + j];
-    v.re = -v.re;
-    v.im = -v.im;
-  }
-}
-
-hipError_t neg_cols(void* X, long long sX, int rows, int ld, int c0, int w, int n_traj, hipStream_t st) {
-  hipLaunchKernelGGL(k_neg_cols, dim3(nblocks((long long)rows * w * n_traj)), dim3(256), 0, st, (c64d*)X, sX, rows, ld, c0, w, n_traj);
-  return hipGetLastError();
-}
-
-__global__ void k_env_one(c64d* env, long long s_env, int n_traj) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n_traj) env[t * s_env] = c64d{1.0, 0.0};
-}
-
-hipError_t env_init(double* env, long long s_env_c, int n_traj, hipStream_t st) {
-  hipLaunchKernelGGL(k_env_one, dim3((n_traj + 255) / 256), dim3(256), 0, st, (c64d*)env, s_env_c, n_traj);
-  return hipGetLastError();
-}
-
-// out[t * stride] = Re Tr(X R) for chi x chi c128 matrices (one workgroup per trajectory)
-__global__ void k_trace_prod(int chi, const c64d* __restrict__ X, long long sX, const c64d* __restrict__ R, long long sR,
-                             double* out, int stride) {
-  __shared__ double red[4];
-  const c64d* x = X + blockIdx.x * sX;
-  const c64d* r = R + blockIdx.x * sR;
-  double acc = 0;
-  const long long tot = (long long)chi * chi;
-  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
-    int i = (int)(e / chi), j = (int)(e % chi);
-    c64d a = x[(long long)i * chi + j], b = r[(long long)j * chi + i];
-    acc += a.re * b.re - a.im * b.im;
-  }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) out[(long long)blockIdx.x * stride] = red[0] + red[1] + red[2] + red[3];
-}
-
-hipError_t obs_trace(int chi, const double* X, long long s_env, const double* R, long long s_R, double* out,
-                     int out_stride, int n_traj, hipStream_t st) {
-  hipLaunchKernelGGL(k_trace_prod, dim3(n_traj), dim3(256), 0, st, chi, (const c64d*)X, s_env, (const c64d*)R, s_R, out, out_stride);
-  return hipGetLastError();
-}
-
-// per_traj[t][0..n_obs) /= norms[t]; then columns [n_obs, stride) (padding of a mixed batch)
-// are set to NaN
-__global__ void k_obs_normalise(double* per_traj, int n_obs, int stride, const double* norms, int n_traj) {
-  long long total = (long long)stride * n_traj;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
-    int t = (int)(e / stride), o = (int)(e % stride);
-    if (o < n_obs) per_traj[e] /= norms[t];
-    else per_traj[e] = __builtin_nan("");
-  }
-}
-
-hipError_t obs_normalise(double* per_traj, int n_obs, int stride, const double* norms, int n_traj, hipStream_t st) {
-  hipLaunchKernelGGL(k_obs_normalise, dim3(nblocks((long long)stride * n_traj)), dim3(256), 0, st, per_traj, n_obs, stride,
-                     norms, n_traj);
-  return hipGetLastError();
-}
-
-// mean and M2 over trajectories, one workgroup per observable, fixed-order pairwise merge
-// (Chan et al.) of per-thread Welford accumulators
 __global__ void k_obs_reduce(const double* __restrict__ per_traj, int n_obs, int n_traj, double* mean, double* m2) {
   __shared__ double sn[256], sm[256], sq[256];
   const int o = blockIdx.x, tid = threadIdx.x;
@@ -503,6 +442,73 @@ __global__ void k_add(c64d* acc, long long sA, const c64d* __restrict__ b, long 
 hipError_t add_c128(double* acc, long long sA, const double* b, long long sB, long long len, int n_traj, hipStream_t st) {
   dim3 g((unsigned)((len + 255) / 256), (unsigned)n_traj);
   hipLaunchKernelGGL(k_add, g, dim3(256), 0, st, (c64d*)acc, sA, (const c64d*)b, sB, len);
+  return hipGetLastError();
+}
+
+// per_traj[t][c] = NaN for c0 <= c < stride (rows of a mixed batch past a trajectory's width)
+__global__ void k_fill_nan(double* per_traj, int stride, int c0, int n_traj) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = stride - c0;
+  if (e >= (long long)w * n_traj) return;
+  per_traj[(e / w) * stride + c0 + e % w] = __builtin_nan("");
+}
+
+hipError_t fill_nan(double* per_traj, int stride, int c0, int n_traj, hipStream_t st) {
+  if (c0 >= stride) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_nan, dim3(nblocks((long long)(stride - c0) * n_traj)), dim3(256), 0, st, per_traj, stride, c0,
+                     n_traj);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ certified error
+// eps_tot[t] += weight * sum over the layer's truncation steps of their trace-norm change:
+// 2 sqrt(eps) (kind 0, the exact value for one bond) or 4 sqrt(2 eps) (kind 1, the
+// computable bound of the MPS-truncation section).
+__global__ void k_err_acc(int n_traj, int slots, const double* __restrict__ disc, int kind, double weight,
+                          double* __restrict__ eps_tot) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_traj) return;
+  double s = 0.0;
+  for (int k = 0; k < slots; ++k) {
+    const double e = fmax(disc[(long long)t * slots + k], 0.0);
+    s += kind == 0 ? 2.0 * sqrt(e) : 4.0 * sqrt(2.0 * e);
+  }
+  eps_tot[t] += weight * s;
+}
+
+hipError_t err_accumulate(int n_traj, int slots, const double* disc, int kind, double weight, double* eps_tot,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_err_acc, dim3((n_traj + 255) / 256), dim3(256), 0, st, n_traj, slots, disc, kind, weight, eps_tot);
+  return hipGetLastError();
+}
+
+// out = (mean of the capped errors, Hoeffding buffer, their sum): eps_bound = eps_tot when
+// eps_tot <= eps_max - 2, else eps_max; one workgroup, fixed summation order.
+__global__ __launch_bounds__(256) void k_err_est(int n_traj, const double* __restrict__ eps_tot, double eps_max,
+                                                 double delta, double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < n_traj; t += 256) {
+    const double e = eps_tot[t];
+    s += e <= eps_max - 2.0 ? e : eps_max;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double hat = red[0] / n_traj;
+    const double buf = sqrt(eps_max * eps_max * log(1.0 / delta) / (2.0 * n_traj));
+    out[0] = hat;
+    out[1] = buf;
+    out[2] = hat + buf;
+  }
+}
+
+hipError_t err_estimate(int n_traj, const double* eps_tot, double eps_max, double delta, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_err_est, dim3(1), dim3(256), 0, st, n_traj, eps_tot, eps_max, delta, out);
   return hipGetLastError();
 }
 

@@ -50,11 +50,9 @@ struct Layout {
   long long s_traj;                 // elements per trajectory
   // work buffer (byte offsets)
   size_t o_status, o_siteoff, o_x, o_partial, o_kops, o_gram, o_ews, o_gws, o_evals, o_z, o_kept, o_alpha,
-      o_invs, o_sqrt, o_wm, o_rm, o_rho1, o_tmp, o_obs, o_norm, o_pbuf, o_exp, o_l2zr, o_l2cr, o_l2z2, o_l2act,
+      o_invs, o_sqrt, o_wm, o_rm, o_rho1, o_tmp, o_obs, o_norm, o_pbuf, o_l2zr, o_l2cr, o_l2z2, o_l2act,
       o_l2r, o_l2info;
   long long s_x, s_partial, s_gram, s_ews, s_gws, s_evals, s_z, s_wm, s_tmp;
-  int exp_chunk;
-  long long s_env;                  // c128 elements per environment slot
   size_t state_bytes, work_bytes;
   int max_tiles;
 };
@@ -104,11 +102,6 @@ int make_layout(int n_traj, int n, int chi, int prec, Layout& L) {
   L.s_z = 2 * c * c;                                  // c128
   L.s_wm = c * c;                                     // prec elements
   L.s_tmp = 4 * c * c;                                // prec elements (hop results)
-  // expect chunk: (n + 1) environments + 8 scratch matrices of 2c^2 c128 per trajectory
-  L.s_env = 2 * c * c;
-  long long per_exp = (long long)(n + 1 + 8) * L.s_env * 16;
-  long long budget = 1LL << 31;
-  L.exp_chunk = (int)std::max<long long>(1, std::min<long long>(T, budget / std::max<long long>(per_exp, 1)));
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
   L.o_status = take(256);
@@ -120,8 +113,6 @@ int make_layout(int n_traj, int n, int chi, int prec, Layout& L) {
   L.o_norm = take(sizeof(double) * T);
   L.o_pbuf = take(sizeof(double) * 4 * T);
   L.o_obs = take(sizeof(double) * (2 * n - 1) * T);
-  // gate-step region and expect region overlap
-  size_t base = o;
   L.o_x = take(L.esz * L.s_x * T);
   L.o_partial = take(sizeof(double) * L.s_partial * T);
   L.o_gram = take(16 * L.s_gram * T);
@@ -142,10 +133,7 @@ int make_layout(int n_traj, int n, int chi, int prec, Layout& L) {
     L.o_l2r = take(sizeof(int) * T);
     L.o_l2info = take(sizeof(double) * 3 * T);
   }
-  size_t gate_end = o;
-  o = base;
-  L.o_exp = take((size_t)per_exp * L.exp_chunk);
-  L.work_bytes = std::max(gate_end, o);
+  L.work_bytes = o;
   return MPSB_OK;
 }
 
@@ -205,6 +193,8 @@ struct mpsb_batch {
   std::vector<unsigned char> any_ev;   // [depth][n]: some trajectory has an event on (layer, qubit)
   Tables tab;
   int traj_base = 0;                   // index of trajectory 0 in the batch (sub-batch of a mixed batch)
+  const double* rep_w = nullptr;       // replay inputs of the layer being enqueued (rows of this batch)
+  const int32_t* rep_b = nullptr;
   long long traj_offset = 0;           // global index of the batch's trajectory 0 (branch-draw keys)
   int rec_stride = 0;                  // record row length (the widest trajectory of the batch)
   // mixed batch: sub-batches and their streams
@@ -564,6 +554,8 @@ EventArgs base_event_args(mpsb_batch* h, int layer, int32_t* branch, double* w_r
   ea.seed = h->seed;
   ea.branch_out = branch;
   ea.w_out = w_record;
+  ea.w_in = h->rep_w;
+  ea.branch_in = h->rep_b;
   ea.rec_stride = h->rec_stride;
   ea.rec_qbase = 0;
   ea.traj_base = h->traj_offset + h->traj_base;
@@ -1074,12 +1066,14 @@ std::vector<mpsb_batch*> members(mpsb_batch* h) {
 // Enqueues one layer of every member batch on stream S (members of a mixed batch on the
 // private streams, forked from and joined back into S), then advances the layer counter.
 int enqueue_layer(mpsb_batch* h, int layer, hipStream_t S, double* discarded, int32_t* branch, double* w_record,
-                  bool capturing) {
+                  bool capturing, const double* w_in = nullptr, const int32_t* branch_in = nullptr) {
   const int rs = h->rec_stride, dstr = rs / 2;
   auto recs = [&](mpsb_batch* b, double*& d, int32_t*& br, double*& w) {
     d = discarded ? discarded + (size_t)b->traj_base * dstr : nullptr;
     br = branch ? branch + (size_t)b->traj_base * rs : nullptr;
     w = w_record ? w_record + (size_t)b->traj_base * rs * 32 : nullptr;
+    b->rep_w = w_in ? w_in + (size_t)b->traj_base * rs * 32 : nullptr;
+    b->rep_b = branch_in ? branch_in + (size_t)b->traj_base * rs : nullptr;
   };
   if (h->sub.empty()) {
     hipStream_t keep = h->st;
@@ -1088,6 +1082,8 @@ int enqueue_layer(mpsb_batch* h, int layer, hipStream_t S, double* discarded, in
     recs(h, d, br, w);
     int r = run_layer(h, layer, d, dstr, br, w, capturing);
     h->st = keep;
+    h->rep_w = nullptr;
+    h->rep_b = nullptr;
     if (r) return r;
     HIPCHK(inc_int(h->tab.layer, S));
     return MPSB_OK;
@@ -1103,6 +1099,8 @@ int enqueue_layer(mpsb_batch* h, int layer, hipStream_t S, double* discarded, in
     double* d; int32_t* br; double* w;
     recs(b, d, br, w);
     r = run_layer(b, layer, d, dstr, br, w, capturing);
+    b->rep_w = nullptr;
+    b->rep_b = nullptr;
   }
   for (int j = 0; j < NS; ++j) {
     HIPCHK(hipEventRecord(h->join_ev[j], h->streams[j]));
@@ -1371,7 +1369,8 @@ int mps_batch_set_autotune(mpsb_handle h, int enable) {
   return MPSB_OK;
 }
 
-int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch, double* w_record) {
+int apply_layer_replay(mpsb_handle h, int layer, const double* w_in, const int32_t* branch_in, double* discarded,
+                       int32_t* branch, double* w_record) {
   if (!h) return fail(MPSB_EINVAL, "null handle");
   if (!h->has_circuit) return fail(MPSB_EINVAL, "no circuit set");
   if (layer < 0 || layer >= h->depth) return fail(MPSB_EINVAL, "layer out of range");
@@ -1380,10 +1379,10 @@ int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch, do
   if (branch) HIPCHK(hipMemsetAsync(branch, 0xFF, sizeof(int32_t) * T * rs, h->st));
   if (w_record) HIPCHK(hipMemsetAsync(w_record, 0, sizeof(double) * 32 * T * rs, h->st));
   if (discarded) HIPCHK(hipMemsetAsync(discarded, 0, sizeof(double) * T * (rs / 2), h->st));
-  const bool rec = discarded || branch || w_record;
+  const bool rec = discarded || branch || w_record || w_in || branch_in;
   std::vector<mpsb_batch*> bs = members(h);
   if (!h->graphs_on || rec || profiling(h)) {
-    int r = enqueue_layer(h, layer, h->st, discarded, branch, w_record, false);
+    int r = enqueue_layer(h, layer, h->st, discarded, branch, w_record, false, w_in, branch_in);
     if (r) return r;
     for (mpsb_batch* b : bs) b->next_layer = layer + 1;
     h->next_layer = layer + 1;
@@ -1445,6 +1444,10 @@ int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch, do
   return MPSB_OK;
 }
 
+int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch, double* w_record) {
+  return apply_layer_replay(h, layer, nullptr, nullptr, discarded, branch, w_record);
+}
+
 int sample_kraus(mpsb_handle h, const int32_t* qubit, int channel, int unravel_mode, int rng_layer,
                  const int32_t* forced, int32_t* branch, double* p) {
   if (!h || !qubit) return fail(MPSB_EINVAL, "null argument");
@@ -1503,91 +1506,41 @@ int mps_truncate(mpsb_handle h, int chi, double* discarded) {
 }  // extern "C"
 
 namespace {
-// Observables of a uniform batch into per_traj rows of `stride` doubles (NaN past 2n-1), and
-// (mean, m2) over its trajectories when requested.
+// Observables of a uniform batch into per_traj rows of `stride` doubles, and (mean, m2) over
+// its trajectories when requested.  A measurement sweep: the orthogonality centre walks from
+// site 0 to site n-2; at each site i the two-site contraction of (i, i+1) with the identity
+// gate accumulates the two-site reduced state (the environments are orthonormal, so this is
+// the state's own reduced state), from which <Z_i>, <Z_i Z_(i+1)> (and <Z_(n-1)>) follow.
+// 2(n-1) batched launches plus the centre hops, all trajectories in each.
 int expect_uniform(mpsb_batch* h, double* mean, double* m2, double* per_traj, int stride) {
   const Layout& L = h->L;
   const int n = L.n, nobs = 2 * n - 1, T = L.n_traj;
   const int p = L.prec == MPSB_FP64 ? 1 : 0;
   if (!per_traj) stride = nobs;
   double* obs = per_traj ? per_traj : W<double>(h, L.o_obs);
-  double* norms = W<double>(h, L.o_norm);
-  const long long se = L.s_env;   // c128 elements per slot
-  char* ex = W<char>(h, L.o_exp);
-  const int chunk = L.exp_chunk;
+  // one profiler class for the whole sweep (the hops inside are not split out)
   ProfSec sexp(h, PC_EXPECT);
-  for (int t0 = 0; t0 < T; t0 += chunk) {
-    const int ct = std::min(chunk, T - t0);
-    // per trajectory of the chunk: [R_0 .. R_n][L][Lz][Lzp][Y][Tm][site]
-    const long long per = (long long)(n + 1 + 8) * se;   // c128 elements
-    auto slot = [&](int s) { return (double*)(ex + (size_t)s * se * 16); };
-    double* Rs = slot(0);
-    double* Lc = slot(n + 1);
-    double* Lz = slot(n + 2);
-    double* Lzp = slot(n + 3);
-    double* Y = slot(n + 4);
-    double* Tm = slot(n + 5);
-    double* Sw = slot(n + 6);   // 2 slots
-    const long long sp = per;   // trajectory stride (c128 elements)
-    auto site_c128 = [&](int k) -> const void* {
-      const char* s = site_ptr(h, k) + (size_t)t0 * L.s_traj * L.esz;
-      if (p == 1) return s;
-      return s;  // widened below
-    };
-    (void)site_c128;
-    auto get_site = [&](int k, long long& stride) -> const void* {
-      const char* s = site_ptr(h, k) + (size_t)t0 * L.s_traj * L.esz;
-      if (p == 1) { stride = L.s_traj; return s; }
-      long long len = 2LL * dl(L, k) * dr(L, k);
-      (void)widen(s, L.s_traj, Sw, sp, len, ct, h->st);
-      stride = sp;
-      return Sw;
-    };
-    // R_n = 1
-    HIPCHK(env_init(Rs + (size_t)n * se * 2, sp, ct, h->st));
-    for (int k = n - 1; k >= 0; --k) {
-      long long ss;
-      const void* A = get_site(k, ss);
-      const int cl = dl(L, k), cr = dr(L, k);
-      double* Rin = Rs + (size_t)(k + 1) * se * 2;
-      double* Rout = Rs + (size_t)k * se * 2;
-      // Tm = A2 Rin  (A2: (2cl) x cr)
-      HIPCHK(gemm(1, 1, false, false, 2 * cl, cr, cr, A, cr, ss, Rin, cr, sp, Tm, cr, sp, nullptr, ct, h->st));
-      // Rout = Tm' A'^dag  (Tm', A' : cl x 2cr)
-      HIPCHK(gemm(1, 1, false, true, cl, cl, 2 * cr, Tm, 2 * cr, sp, A, 2 * cr, ss, Rout, cl, sp, nullptr, ct, h->st));
-    }
-    HIPCHK(env_init(Lc, sp, ct, h->st));
-    double* ob = obs + (size_t)t0 * stride;
-    for (int k = 0; k < n; ++k) {
-      long long ss;
-      const void* A = get_site(k, ss);
-      const int cl = dl(L, k), cr = dr(L, k);
-      double* Rn = Rs + (size_t)(k + 1) * se * 2;
-      // Tm = Lc A' (cl x 2cr)
-      HIPCHK(gemm(1, 1, false, false, cl, 2 * cr, cl, Lc, cl, sp, A, 2 * cr, ss, Tm, 2 * cr, sp, nullptr, ct, h->st));
-      // Lz = A2^dag Tm2 with the s=1 half negated; Lc' = A2^dag Tm2
-      double* Lnew = Y;   // temporarily
-      HIPCHK(gemm(1, 1, true, false, cr, cr, 2 * cl, A, cr, ss, Tm, cr, sp, Lnew, cr, sp, nullptr, ct, h->st));
-      HIPCHK(neg_cols(Tm, sp, cl, 2 * cr, cr, cr, ct, h->st));
-      HIPCHK(gemm(1, 1, true, false, cr, cr, 2 * cl, A, cr, ss, Tm, cr, sp, Lz, cr, sp, nullptr, ct, h->st));
-      HIPCHK(obs_trace(cr, Lz, sp, Rn, sp, ob + k, stride, ct, h->st));
-      if (k >= 1) {
-        const int clp = cl;
-        // Y = Z-weighted transfer of Lzp through site k
-        HIPCHK(gemm(1, 1, false, false, clp, 2 * cr, clp, Lzp, clp, sp, A, 2 * cr, ss, Tm, 2 * cr, sp, nullptr, ct, h->st));
-        HIPCHK(neg_cols(Tm, sp, clp, 2 * cr, cr, cr, ct, h->st));
-        HIPCHK(gemm(1, 1, true, false, cr, cr, 2 * clp, A, cr, ss, Tm, cr, sp, Lzp, cr, sp, nullptr, ct, h->st));
-        HIPCHK(obs_trace(cr, Lzp, sp, Rn, sp, ob + n + k - 1, stride, ct, h->st));
-      }
-      // rotate: Lc <- Lnew, Lzp <- Lz
-      HIPCHK(copy_blocks(Lc, sp * 16, Lnew, sp * 16, (size_t)cr * cr * 16, ct, h->st));
-      HIPCHK(copy_blocks(Lzp, sp * 16, Lz, sp * 16, (size_t)cr * cr * 16, ct, h->st));
-    }
-    // norm = L_n (1x1)
-    HIPCHK(copy_blocks(norms + t0, sizeof(double), Lc, sp * 16, sizeof(double), ct, h->st));
-    HIPCHK(obs_normalise(ob, nobs, stride, norms + t0, ct, h->st));
-    (void)Rs;
+  const bool prof_on = h->prof.on;
+  h->prof.on = false;
+  Mat4 id;
+  memset(&id, 0, sizeof(id));
+  for (int i = 0; i < 4; ++i) id.v[2 * (4 * i + i)] = 1.0;
+  GateRef none;
+  memset(&none, 0, sizeof(none));
+  int r = MPSB_OK;
+  for (int i = 0; i + 1 < n && r == MPSB_OK; ++i) {
+    r = move_centre(h, i, i);
+    if (r) break;
+    const int cl = dl(L, i), cm = dr(L, i), cr = dr(L, i + 1);
+    const int var = theta_default_variant(p, cl, cr);
+    hipError_t e = theta(p, cl, cm, cr, site_ptr(h, i), site_ptr(h, i + 1), L.s_traj, W<char>(h, L.o_x), L.s_x, id, none,
+                         W<double>(h, L.o_partial), T, h->st, var);
+    if (e == hipSuccess) e = obs_pair(W<double>(h, L.o_partial), theta_tiles(var, cl, cr), i, n, obs, stride, T, h->st);
+    if (e != hipSuccess) r = fail(MPSB_EHIP, std::string("measurement sweep: ") + hipGetErrorString(e));
   }
+  h->prof.on = prof_on;
+  if (r) return r;
+  if (stride > nobs) HIPCHK(fill_nan(obs, stride, nobs, T, h->st));
   if (mean) HIPCHK(obs_reduce(obs, nobs, T, mean, m2, h->st));
   return MPSB_OK;
 }
@@ -1648,6 +1601,26 @@ int mps_batch_sync(mpsb_handle h) {
 int mps_batch_destroy(mpsb_handle h) {
   if (!h) return fail(MPSB_EINVAL, "null handle");
   destroy_batch(h);
+  return MPSB_OK;
+}
+
+int mps_error_accumulate(int n_traj, int slots, const double* discarded, int step_kind, double weight, double* eps_tot,
+                         void* stream) {
+  if (n_traj < 0 || slots < 0) return fail(MPSB_EINVAL, "bad sizes");
+  if (step_kind != MPSB_STEP_EXACT && step_kind != MPSB_STEP_PAPER) return fail(MPSB_EINVAL, "unknown step kind");
+  if (!(weight >= 0.0) || !std::isfinite(weight)) return fail(MPSB_EINVAL, "weight must be finite and >= 0");
+  if (n_traj == 0) return MPSB_OK;
+  if (!eps_tot || (slots > 0 && !discarded)) return fail(MPSB_EINVAL, "null pointer");
+  HIPCHK(err_accumulate(n_traj, slots, discarded, step_kind, weight, eps_tot, (hipStream_t)stream));
+  return MPSB_OK;
+}
+
+int mps_error_estimate(int n_traj, const double* eps_tot, double eps_max, double delta, double* out, void* stream) {
+  if (n_traj < 1) return fail(MPSB_EINVAL, "n_traj must be >= 1");
+  if (!(eps_max >= 2.0) || !std::isfinite(eps_max)) return fail(MPSB_EINVAL, "eps_max must be >= 2");
+  if (!(delta > 0.0 && delta < 1.0)) return fail(MPSB_EINVAL, "delta must be in (0, 1)");
+  if (!eps_tot || !out) return fail(MPSB_EINVAL, "null pointer");
+  HIPCHK(err_estimate(n_traj, eps_tot, eps_max, delta, out, (hipStream_t)stream));
   return MPSB_OK;
 }
 

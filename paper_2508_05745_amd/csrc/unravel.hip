@@ -494,9 +494,17 @@ __device__ int one_event(const EventArgs& ea, int slot, int id, const cd (&rho)[
   cd K[4][2][2], Uf[4][4], Kp[4][2][2];
   int r;
   load_channel(ea, slot, id, K, r, Uf);
-  double conc;
-  choose_mixing(ea.mode, rho, K, r, Uf, W, conc);
+  const long long ridx = (long long)traj * ea.rec_stride + ((int)qubit - ea.rec_qbase);
+  if (ea.w_in) {   // replayed mixing: W[i][j] = U[j][i]
+    const double* w = ea.w_in + ridx * 32;
+    for (int jj = 0; jj < 4; ++jj)
+      for (int i = 0; i < 4; ++i) W[i][jj] = cd{w[2 * (4 * jj + i)], w[2 * (4 * jj + i) + 1]};
+  } else {
+    double conc;
+    choose_mixing(ea.mode, rho, K, r, Uf, W, conc);
+  }
   mixed_ops(K, r, W, rho, Kp, p);
+  if (ea.branch_in && forced < 0) forced = ea.branch_in[ridx];
   int j;
   if (forced >= 0) {
     j = forced;

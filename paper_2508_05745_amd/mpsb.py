@@ -58,12 +58,15 @@ def lib():
         L.mps_batch_set_graphs.argtypes = [vp, i32]
         L.mps_batch_set_autotune.argtypes = [vp, i32]
         L.apply_layer.argtypes = [vp, i32, vp, vp, vp]
+        L.apply_layer_replay.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.sample_kraus.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
         L.mps_truncate.argtypes = [vp, i32, vp]
         L.expect.argtypes = [vp, vp, vp, vp]
         L.mps_batch_sync.argtypes = [vp]
         L.mps_batch_destroy.argtypes = [vp]
         L.unravel_opt.argtypes = [i32, vp, vp, i32, vp, i32, vp, vp, vp, vp]
+        L.mps_error_accumulate.argtypes = [i32, i32, vp, i32, ctypes.c_double, vp, vp]
+        L.mps_error_estimate.argtypes = [i32, vp, ctypes.c_double, ctypes.c_double, vp, vp]
         L.unravel_cost.argtypes = [i32, vp, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp]
         L.unravel_cost_grad.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, vp]
         _lib = L
@@ -206,8 +209,13 @@ class Batch:
     def set_autotune(self, enable: bool):
         _check(lib().mps_batch_set_autotune(self.h, int(bool(enable))))
 
-    def apply_layer(self, layer: int, discarded=None, branch=None, w_record=None):
-        _check(lib().apply_layer(self.h, layer, _ptr(discarded), _ptr(branch), _ptr(w_record)))
+    def apply_layer(self, layer: int, discarded=None, branch=None, w_record=None, w_in=None, branch_in=None):
+        """w_in / branch_in (record layouts, device tensors): follow recorded mixings / branches."""
+        if w_in is None and branch_in is None:
+            _check(lib().apply_layer(self.h, layer, _ptr(discarded), _ptr(branch), _ptr(w_record)))
+        else:
+            _check(lib().apply_layer_replay(self.h, layer, _ptr(w_in), _ptr(branch_in), _ptr(discarded),
+                                            _ptr(branch), _ptr(w_record)))
 
     def sample_kraus(self, qubit: int, channel: int, mode: int, rng_layer: int, forced=None,
                      branch=None, p=None):
@@ -246,6 +254,34 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------------- certified error
+
+STEP_EXACT, STEP_PAPER = 0, 1
+
+
+class ErrorBound:
+    """Per-trajectory cumulated truncation error of a run (device FP64 accumulator) and the
+    certified estimate of Thm. "Truncated Trajectory Sampling error"."""
+
+    def __init__(self, n_traj: int, step_kind: int = STEP_EXACT):
+        import torch
+        self.n_traj, self.kind = n_traj, step_kind
+        self.eps_tot = torch.zeros(n_traj, dtype=torch.float64, device="cuda")
+
+    def add_layer(self, discarded, weight: float = 1.0):
+        slots = discarded.shape[1]
+        _check(lib().mps_error_accumulate(self.n_traj, slots, _ptr(discarded.contiguous()), self.kind,
+                                          ctypes.c_double(weight), _ptr(self.eps_tot), _stream()))
+
+    def estimate(self, eps_max: float = 4.0, delta: float = 0.05):
+        """(eps_hat, Hoeffding buffer, bound) as host floats."""
+        import torch
+        out = torch.empty(3, dtype=torch.float64, device="cuda")
+        _check(lib().mps_error_estimate(self.n_traj, _ptr(self.eps_tot), ctypes.c_double(eps_max),
+                                        ctypes.c_double(delta), _ptr(out), _stream()))
+        return tuple(float(x) for x in out.cpu())
 
 
 # ------------------------------------------------------------------------- unravelling

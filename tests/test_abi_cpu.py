@@ -154,3 +154,16 @@ def test_static_batch_rejects_oversized_and_mixed_plans():
     c2 = np.array([4, 4, 4], dtype=np.int32)
     r = lib.mps_batch_create_static(3, w2.ctypes.data, c2.ctypes.data, M.FP64, 1, 0, one, 1 << 40, None, ctypes.byref(h))
     assert r == M.ENOTSUP
+
+
+def test_error_entry_points_validate_on_the_host():
+    import ctypes
+    lib = M.lib()
+    one = ctypes.c_void_p(256)
+    assert lib.mps_error_accumulate(4, 2, one, 2, ctypes.c_double(1.0), one, None) == M.EINVAL
+    assert lib.mps_error_accumulate(4, 2, one, 0, ctypes.c_double(-1.0), one, None) == M.EINVAL
+    assert lib.mps_error_accumulate(4, 2, None, 0, ctypes.c_double(1.0), one, None) == M.EINVAL
+    assert lib.mps_error_accumulate(0, 2, None, 0, ctypes.c_double(1.0), None, None) == M.OK
+    assert lib.mps_error_estimate(4, one, ctypes.c_double(1.5), ctypes.c_double(0.05), one, None) == M.EINVAL
+    assert lib.mps_error_estimate(4, one, ctypes.c_double(4.0), ctypes.c_double(1.0), one, None) == M.EINVAL
+    assert lib.mps_error_estimate(0, one, ctypes.c_double(4.0), ctypes.c_double(0.05), one, None) == M.EINVAL

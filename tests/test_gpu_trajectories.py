@@ -84,3 +84,44 @@ def test_truncated_trajectories_match_oracle_mps(prec, tol):
             for q in order:
                 gd.append(out["disc"][l][t, (q - l % 2) // 2])
         assert np.abs(np.array(gd) - np.array(eps)).max() < (1e-10 if prec == 1 else 1e-5)
+
+
+def test_replay_inputs_follow_a_recorded_run():
+    """apply_layer with replay inputs: an FP64 run fed its own recorded mixings and branches
+    (or only the branches) reproduces itself bit for bit; an FP32-bulk run fed the FP64 run's
+    decisions takes the same branches and stays within 1e-4 of it per trajectory (the paired
+    comparison of the two precisions)."""
+    import torch
+
+    from paper_2508_05745_amd import mpsb as M
+    c = I.brickwork(10, 8, seed=45, channel=I.depolarizing(0.05))
+    T, chi = 64, 16
+
+    def run(prec, w_in=None, b_in=None):
+        b = M.Batch(T, c.n, chi, prec, 13)
+        b.set_circuit(c, M.OPTIMAL)
+        w = torch.zeros((T, c.n, 4, 4), dtype=torch.complex128, device="cuda")
+        br = torch.zeros((T, c.n), dtype=torch.int32, device="cuda")
+        ws, brs = [], []
+        for l in range(c.depth):
+            b.apply_layer(l, branch=br, w_record=w,
+                          w_in=None if w_in is None else w_in[l], branch_in=None if b_in is None else b_in[l])
+            ws.append(w.clone())
+            brs.append(br.clone())
+        _, _, pt = b.expect()
+        b.sync()
+        out = (pt.cpu().numpy(), ws, brs)
+        b.close()
+        return out
+
+    ref, ws, brs = run(1)
+    same, ws2, brs2 = run(1, ws, brs)
+    assert np.array_equal(same, ref)
+    assert all(torch.equal(a, b) for a, b in zip(brs, brs2))
+    only_b, _, _ = run(1, None, brs)
+    assert np.array_equal(only_b, ref)
+    f32, _, brs32 = run(0, ws, brs)
+    assert all(torch.equal(a, b) for a, b in zip(brs, brs32))
+    err = np.abs(f32 - ref).max()
+    print(f"FP32-bulk replay of the FP64 run: max |d<O>| = {err:.2e}", flush=True)
+    assert err < 1e-4
