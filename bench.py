@@ -1,5 +1,5 @@
 """Throughput benchmark: trajectory gate-steps/s of the MPS trajectory simulator with
-locally entanglement-optimal unravelling.
+locally entanglement-optimal unravelling, with the observable error of both precisions.
 
 Workload: 100-qubit open chain, brickwork depth 40 of Haar-random two-qubit gates,
 depolarizing p = 0.02 on both qubits after every gate, optimal unravelling of every noise
@@ -8,11 +8,21 @@ brickwork layer applied to all trajectories (gate, two noise events, truncation 
 move for every pair).  Bond capacities are fixed from the first layer on, so the dense kernels
 do the work of the saturated bond dimension in every layer.
 
-The FP32-bulk path (c64 contractions, FP64 eigen-solves / unravelling / probabilities /
-observables) gives `value`; the full-FP64 path is timed on the same steps and the paired
-difference of the per-trajectory observables is reported.  The default warm-up of 8 layers
-brings the bulk bonds to chi = 128 (a bond can grow by a factor 2 per layer), so the timed
-layers 8 and 9 run on saturated spectra as most layers of the 40-layer circuit do.
+Passes (each over layers 0 .. K-1, K = 40 by default: the whole circuit, timed from the first
+layer through the measurement sweep that gives every trajectory's <Z_i>, <Z_i Z_i+1>; the
+discarded weights of every layer feed the certified error estimate inside the timed region;
+graphs on, no profiling; W warm-up layers run first on a 64-trajectory batch):
+  1. FP32-bulk (c64 contractions; FP64 eigen-solves, unravelling, probabilities,
+     observables), its own decisions: `value`;
+  2. FP64, recording every event's mixing and branch: `fp64.value`;
+  3. FP32-bulk following the FP64 decisions (untimed; layers 8 and 9, saturated, profiled
+     per kernel class): the paired per-trajectory observable differences against pass 2
+     (the 1e-4 target), `kernels_ms` and the roofline of the dominant kernel;
+  4. the oracle replaying trajectory 0 (and 1, if time allows) of pass 2 on the host through
+     all K layers: `cpu_baseline` (its rate over layers 8 and 9) and `oracle_error`
+     (per-trajectory observable error of passes 2 and 3).
+A batch that does not fit in device memory (FP64 at chi = 256) runs in memory waves of
+consecutive trajectories with the trajectory offset.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--chi 128] [--traj 2048]
        python bench.py --mixed [--traj 16384] [--steps K] [--warmup W]   (mixed-batch workload)
@@ -42,6 +52,7 @@ TRIDIAG = {"tridiag_s": (0, 128), "tridiag": (129, 256), "tridiag_l": (257, 512)
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
 EIG_SRC = os.path.join(ROOT, "paper_2508_05745_amd", "csrc", "eig.hip")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.txt")
+EPS_MAX, DELTA = 4.0, 0.05     # cap of the per-trajectory error bound, failure probability
 
 
 def caps(n, chi):
@@ -100,75 +111,200 @@ def measured_traffic(kernel, n_traj, chi):
     return None
 
 
-def run_gpu(workload, layers_warm, layers_timed, precision, profile=True):
+def n_waves(n_traj, n, chi, prec):
+    """Memory waves: the batch runs as 2^k consecutive trajectory ranges (each its own batch,
+    draws keyed by the global trajectory index through the trajectory offset) when its state
+    and work buffers do not fit in the free device memory."""
     import torch
 
     from paper_2508_05745_amd import mpsb as M
-    c = workload.circuit
-    b = M.Batch(workload.n_traj, c.n, workload.chi, precision, workload.seed)
-    b.set_circuit(c, M.OPTIMAL)
-    for l in layers_warm:
+    free, _ = torch.cuda.mem_get_info()
+    waves = 1
+    while waves < n_traj:
+        sb, wb = M.plan(n_traj // waves, n, chi, prec)
+        if sb + wb < 0.9 * free - (2 << 30):
+            break
+        waves *= 2
+    return waves
+
+
+def warm_up(wl, precision, layers):
+    """Untimed: `layers` layers on a small batch of the same shapes (loads the code objects
+    and runs each kernel once)."""
+    import torch
+
+    from paper_2508_05745_amd import mpsb as M
+    if layers <= 0:
+        return
+    b = M.Batch(64, wl.circuit.n, wl.chi, precision, wl.seed)
+    b.set_circuit(wl.circuit, M.OPTIMAL)
+    for l in range(min(layers, wl.circuit.depth)):
         b.apply_layer(l)
+    b.expect()
     b.sync()
-    lib = M.lib()
-    if profile:
-        lib.mps_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
-        lib.mps_profile(b.h, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for l in layers_timed:
-        b.apply_layer(l)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    b.sync()
-    prof = None
-    if profile:
-        ms = (ctypes.c_double * 32)()
-        cnt = (ctypes.c_longlong * 32)()
-        lib.mps_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
-        nc = lib.mps_profile_read(b.h, ms, cnt, 32)
-        prof = {PROF_NAMES[i]: (ms[i], cnt[i]) for i in range(min(nc, len(PROF_NAMES)))}
-        lib.mps_profile(b.h, 0)
-    _, _, pt = b.expect()
-    b.sync()
-    obs = pt.cpu().numpy()
     b.close()
-    del b
-    torch.cuda.empty_cache()
-    return t1 - t0, prof, obs
+    torch.cuda.synchronize()
 
 
-def cpu_baseline(workload, budget_s=25.0):
-    """The oracle MPS (NumPy, FP64) on one trajectory of the same circuit and chi: untimed
-    layers until the bond dimension saturates (or half the budget), then timed layers."""
+def run_pass(wl, precision, L, record=None, replay=None, prof_layers=()):
+    """Layers 0 .. L-1 of the workload on all trajectories (in memory waves if needed) and
+    the measurement sweep, timed per wave from the first layer through `expect` (per-trajectory
+    observables) between device synchronisations, with the discarded weights of every layer
+    accumulated into the certified error estimate inside the timed region.  record = (w[l],
+    branch[l]) per-layer device tensors over the whole batch that receive the mixings and
+    branches; replay = the same structure to follow (paired run).  prof_layers: layers timed
+    per kernel class with HIP events (this disables graph replay for them, so a profiled pass
+    is not a timed one)."""
+    import torch
+
+    from paper_2508_05745_amd import mpsb as M
+    c = wl.circuit
+    T = wl.n_traj
+    waves = n_waves(T, c.n, wl.chi, precision)
+    Tw = T // waves
+    lib = M.lib()
+    lib.mps_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.mps_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    obs = torch.empty((T, 2 * c.n - 1), dtype=torch.float64, device="cuda")
+    eb = {k: M.ErrorBound(T, k) for k in (M.STEP_EXACT, M.STEP_PAPER)}
+    prof = {k: [0.0, 0] for k in PROF_NAMES}
+    dt = 0.0
+    for w in range(waves):
+        a, z = w * Tw, (w + 1) * Tw
+        b = M.Batch(Tw, c.n, wl.chi, precision, wl.seed, traj_offset=a)
+        b.set_circuit(c, M.OPTIMAL)
+        ebw = {}
+        for k, e in eb.items():
+            ebw[k] = M.ErrorBound(Tw, k)
+            ebw[k].eps_tot = e.eps_tot[a:z]
+        d = torch.zeros((Tw, c.n // 2), dtype=torch.float64, device="cuda")
+        b.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for l in range(L):
+            if prof_layers and l == prof_layers[0]:
+                lib.mps_profile(b.h, 1)
+            kw = dict(discarded=d)
+            if record is not None:
+                kw.update(w_record=record[0][l][a:z], branch=record[1][l][a:z])
+            if replay is not None:
+                kw.update(w_in=replay[0][l][a:z], branch_in=replay[1][l][a:z])
+            b.apply_layer(l, **kw)
+            for e in ebw.values():
+                e.add_layer(d)
+            if prof_layers and l == prof_layers[-1]:
+                ms = (ctypes.c_double * 32)()
+                cnt = (ctypes.c_longlong * 32)()
+                nc = lib.mps_profile_read(b.h, ms, cnt, 32)
+                for i in range(min(nc, len(PROF_NAMES))):
+                    prof[PROF_NAMES[i]][0] += ms[i]
+                    prof[PROF_NAMES[i]][1] += cnt[i]
+                lib.mps_profile(b.h, 0)
+            if l % 8 == 7:
+                print(f"#   wave {w + 1}/{waves}: layer {l} queued", file=sys.stderr, flush=True)
+        _, _, pt = b.expect()
+        torch.cuda.synchronize()
+        dt += time.perf_counter() - t0
+        b.sync()
+        obs[a:z] = pt
+        b.close()
+        del b, d, pt
+        torch.cuda.empty_cache()
+    est = {}
+    for k, e in eb.items():
+        name = "exact_step" if k == M.STEP_EXACT else "paper_step"
+        est[name] = e.estimate(eps_max=EPS_MAX, delta=DELTA)
+        # without the cap: the mean cumulated error itself (no certificate attached)
+        est[name + "_uncapped_mean"] = e.estimate(eps_max=1e300, delta=DELTA)[0]
+    return dict(seconds=dt, obs=obs.cpu().numpy(), waves=waves, error=est,
+                prof={k: tuple(v) for k, v in prof.items()} if prof_layers else None)
+
+
+def paired_stats(x, y):
+    """Per-trajectory differences d = x - y of two runs over the same trajectories: the
+    distribution of max_i |d_t,i|, the per-observable mean difference with its standard error
+    (the paired comparison of the two runs' estimators), and Hotelling's T^2 test of a zero
+    mean difference over all observables jointly (F distribution; correlated observables)."""
+    from scipy import stats
+    d = x - y
+    T, p = d.shape
+    per = np.abs(d).max(axis=1)
+    md = d.mean(0)
+    se = d.std(0, ddof=1) / np.sqrt(T) + 1e-300
+    i = int(np.argmax(np.abs(md)))
+    out = dict(per_traj_max_abs=dict(max=float(per.max()), median=float(np.median(per)),
+                                     p99=float(np.quantile(per, 0.99))),
+               mean_diff_max_abs=float(np.abs(md).max()), mean_diff_se_at_max=float(se[i]),
+               z_max=float(np.abs(md / se).max()))
+    if per.max() > 0 and T > p + 1:
+        S = np.cov(d, rowvar=False)
+        sol, *_ = np.linalg.lstsq(S, md, rcond=1e-12)
+        t2 = float(T * md @ sol)
+        rank = int(np.linalg.matrix_rank(S, tol=1e-12 * np.abs(S).max()))
+        f = (T - rank) / (rank * (T - 1)) * t2
+        out.update(hotelling_t2=t2, hotelling_rank=rank, hotelling_p=float(stats.f.sf(f, rank, T - rank)))
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, L, rec, obs64, obs32p, rate_layers, budget_s=90.0):
+    """The oracle MPS (NumPy/LAPACK, FP64) replaying sampled trajectories of the FP64 run
+    (its recorded mixings, each checked for completeness and optimality, and its own draws,
+    which must reproduce the recorded branches) through all L layers: its rate is taken over
+    `rate_layers` (saturated bonds), and its final observables give the per-trajectory error
+    of the FP64 run and of the FP32-bulk run that followed the same decisions.  A second
+    trajectory is replayed if the first took under a third of the budget."""
     from oracle import mps as omps
     from oracle import sv as osv
-    c = workload.circuit
-    m = omps.MPS(c.n)
+    c = wl.circuit
     t_start = time.perf_counter()
-    l = 0
-    while l < c.depth and time.perf_counter() - t_start < 0.5 * budget_s:
-        omps.trajectory(c, workload.chi, 0, workload.seed, layer_range=[l], m=m)
-        l += 1
-        if max(m.bond_dims()) >= workload.chi and l >= 14:
+    steps, secs, errs = 0, 0.0, []
+    for t in (0, 1):
+        if t > 0 and time.perf_counter() - t_start > budget_s / 3:
             break
-    warm = l
-    t0 = time.perf_counter()
-    steps = 0
-    while l < c.depth and (time.perf_counter() - t0 < 0.4 * budget_s or steps == 0):
-        omps.trajectory(c, workload.chi, 0, workload.seed, layer_range=[l], m=m)
-        steps += len(c.pairs(l))
-        l += 1
-    dt = time.perf_counter() - t0
+        ws, js = [], []
+        for l in range(L):
+            wl_ = rec[0][l][t].cpu().numpy()
+            bl_ = rec[1][l][t].cpu().numpy()
+            for kind, q in osv.sweep_ops(c, l):
+                for x in osv.event_qubits(c, l, kind, q):
+                    ws.append(wl_[x].T.copy())
+                    js.append(int(bl_[x]))
+        rp = osv.Replay(ws)
+        got = []
+        m = omps.MPS(c.n)
+        for l in range(L):
+            t0 = time.perf_counter()
+            omps.trajectory(c, wl.chi, t, wl.seed, mode=3, layer_range=[l], m=m, replay=rp, record=got)
+            if l in rate_layers:
+                secs += time.perf_counter() - t0
+                steps += len(c.pairs(l))
+        zi, zz = omps.z_expectations(m)
+        ref = np.concatenate([zi, zz])
+        errs.append(dict(traj=t, fp64_max_abs=float(np.abs(obs64[t] - ref).max()),
+                         fp32_bulk_paired_max_abs=float(np.abs(obs32p[t] - ref).max()),
+                         branches_match=js == [r["j"] for r in got],
+                         replay_max_eof_gap=float(rp.max_gap)))
+        print(f"#   oracle trajectory {t}: {time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
     try:
         from threadpoolctl import threadpool_info
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
-    return dict(value=steps / dt, unit="trajectory gate-steps/s", cores=int(cores), kind="oracle",
-                sample=f"1 trajectory, layers {warm}..{l - 1} (after {warm} untimed layers, max bond "
-                       f"{max(m.bond_dims())}) of the same chi={workload.chi} circuit, "
-                       f"NumPy/LAPACK complex128")
+    base = dict(value=steps / secs, unit="trajectory gate-steps/s", cores=int(cores), kind="oracle",
+                cpu=cpu_model(),
+                sample=f"{len(errs)} trajectories of the FP64 run replayed by the oracle (NumPy/LAPACK "
+                       f"complex128) through layers 0..{L - 1}; rate over layers {rate_layers[0]}..{rate_layers[-1]}")
+    return base, errs
 
 
 def calibrate_copy(nbytes=1 << 30, reps=4):
@@ -226,11 +362,37 @@ def bench_mixed(args):
     print(json.dumps(line))
 
 
+def roofline(work, nbytes, prof, wl):
+    """Roofline of the dominant kernel class (largest HIP-event time in the profiled pass;
+    each class times one kernel instance).  The eigensolver's tridiagonalisation is bounded
+    by the FP64 units (16/3 m^3 flops per m x m matrix, on the VALU); its one-stage HBM byte
+    model and the counted traffic are reported beside it."""
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, cnt = prof[dom]
+    sec = ms * 1e-3
+    rate = work.get(dom, 0.0) / sec if sec > 0 else 0.0
+    if dom in TRIDIAG:
+        roof = dict(bound="alu", achieved=rate / 1e12, peak=PEAK["fp64"] / 1e12, unit="TFLOP/s",
+                    frac=rate / PEAK["fp64"], traffic=measured_traffic(KERNEL[dom], wl.n_traj, wl.chi),
+                    hbm_model=dict(bytes_per_launch=nbytes[dom] / max(cnt, 1),
+                                   achieved_gbs=nbytes[dom] / sec / 1e9 if sec > 0 else 0.0,
+                                   frac_of_8tbs=nbytes[dom] / sec / PEAK["hbm"] if sec > 0 else 0.0))
+    elif dom in ("theta", "gram", "recompose"):
+        roof = dict(bound="mfma", achieved=rate / 1e12, peak=PEAK["fp32"] / 1e12, unit="TFLOP/s",
+                    frac=rate / PEAK["fp32"], traffic=None)
+    else:
+        roof = dict(bound="alu", achieved=rate / 1e12, peak=PEAK["fp64"] / 1e12, unit="TFLOP/s",
+                    frac=rate / PEAK["fp64"], traffic=None)
+    roof.update(kernel=KERNEL.get(dom, dom), launches=int(cnt), avg_launch_ms=ms / max(cnt, 1),
+                flops_per_launch=work.get(dom, 0.0) / max(cnt, 1))
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=40, help="layers timed from layer 0 (40 = the whole circuit)")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed layers on a 64-trajectory batch first")
     ap.add_argument("--chi", type=int, default=128)
     ap.add_argument("--traj", type=int, default=2048)
     ap.add_argument("--no-fp64", action="store_true")
@@ -242,82 +404,83 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this library runs on one GPU; a run on several GPUs would give each GPU a "
+                                   "disjoint trajectory range (designed, not built)", "n_gpus": args.gpus}))
+        sys.exit(2)
     if args.mixed:
-        if args.gpus != 1:
-            print(json.dumps({"error": "this library runs on one GPU", "n_gpus": args.gpus}))
-            sys.exit(2)
         bench_mixed(args)
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this library runs on one GPU; multi-GPU sharding (disjoint "
-                                   "trajectory ranges) is designed but not implemented",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
+    import torch
+
     from paper_2508_05745_amd import inputs as I
     from paper_2508_05745_amd import mpsb as M
     wl = I.config_wide(chi=args.chi, n_traj=args.traj)
     c = wl.circuit
     W, K = args.warmup, args.steps
-    if W + K > c.depth:
-        raise SystemExit("warmup + steps exceeds the circuit depth (40)")
-    warm, timed = list(range(W)), list(range(W, W + K))
-    gate_steps = wl.n_traj * sum(len(c.pairs(l)) for l in timed)
-    print(f"# fp32-bulk: {W} warmup + {K} timed layers, {gate_steps} gate-steps", file=sys.stderr, flush=True)
-    dt32, prof, obs32 = run_gpu(wl, warm, timed, M.FP32_BULK)
-    value = gate_steps / dt32
-    print(f"# fp32-bulk: {dt32:.3f} s -> {value:.1f} gate-steps/s", file=sys.stderr, flush=True)
-    fp64 = None
+    T = wl.n_traj
+    if not 2 <= K <= c.depth:
+        raise SystemExit(f"--steps must lie in 2..{c.depth}")
+    # kernel classes and the oracle's rate are taken on two saturated layers
+    prof_layers = [8, 9] if K >= 10 else [K - 2, K - 1]
+    gate_steps = T * sum(len(c.pairs(l)) for l in range(K))
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)
+    log(f"warm-up: {W} layers on 64 trajectories")
+    warm_up(wl, M.FP32_BULK, W)
+    log(f"fp32-bulk: layers 0..{K - 1} and the measurement sweep, {gate_steps} gate-steps")
+    p32 = run_pass(wl, M.FP32_BULK, K)
+    value = gate_steps / p32["seconds"]
+    log(f"fp32-bulk: {p32['seconds']:.3f} s -> {value:.1f} gate-steps/s")
+    fp64, paired, rec = None, None, None
     if not args.no_fp64:
-        dt64, prof64, obs64 = run_gpu(wl, warm, timed, M.FP64, profile=False)
-        # the optimal decomposition is not unique, so paired FP32 / FP64 trajectories can
-        # take different (equally optimal) branches: compare the trajectory averages
-        nt = obs32.shape[0]
-        se = np.sqrt(obs32.var(0, ddof=1) / nt + obs64.var(0, ddof=1) / nt) + 1e-300
-        dmean = np.abs(obs32.mean(0) - obs64.mean(0))
-        fp64 = dict(value=gate_steps / dt64, ms_per_step=1e3 * dt64 / K,
-                    mean_obs_abs_diff_max=float(dmean.max()), mean_obs_z_max=float((dmean / se).max()),
-                    observables=f"<Z_i>, <Z_i Z_i+1> after layer {W + K - 1}, {nt} trajectories each")
-        print(f"# fp64: {dt64:.3f} s, max |d mean<O>| {dmean.max():.2e} (z {float((dmean / se).max()):.2f})",
-              file=sys.stderr, flush=True)
-    # roofline of the dominant kernel class (each timed class is one kernel instance)
-    work, nbytes = algorithmic_work(c.n, wl.chi, timed, wl.n_traj)
-    dom = max(prof, key=lambda k: prof[k][0])
-    ms, cnt = prof[dom]
-    sec = ms * 1e-3
-    if dom in TRIDIAG:
-        # one pass over the trailing lower triangle per column: about 2 flop per byte, far
-        # below the FP64 ridge point (78.6 TFLOP/s / 8 TB/s), so HBM bounds it
-        achieved = nbytes[dom] / sec if sec > 0 else 0.0
-        roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK["hbm"] / 1e9, unit="GB/s",
-                    frac=achieved / PEAK["hbm"],
-                    traffic=measured_traffic(KERNEL[dom], wl.n_traj, wl.chi),
-                    algorithmic_bytes_per_launch=nbytes[dom] / max(cnt, 1),
-                    fp64_tflops=work[dom] / sec / 1e12 if sec > 0 else 0.0)
-    elif dom in ("theta", "gram", "recompose"):
-        achieved = work[dom] / sec if sec > 0 else 0.0
-        roof = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAK["fp32"] / 1e12, unit="TFLOP/s",
-                    frac=achieved / PEAK["fp32"], traffic=None)
+        warm_up(wl, M.FP64, W)
+        rec = ([torch.zeros((T, c.n, 4, 4), dtype=torch.complex128, device="cuda") for _ in range(K)],
+               [torch.zeros((T, c.n), dtype=torch.int32, device="cuda") for _ in range(K)])
+        log("fp64 (recording every decision)")
+        p64 = run_pass(wl, M.FP64, K, record=rec)
+        log(f"fp64: {p64['seconds']:.3f} s -> {gate_steps / p64['seconds']:.1f} gate-steps/s")
+        log(f"fp32-bulk following the fp64 decisions (paired; layers {prof_layers} profiled)")
+        pp = run_pass(wl, M.FP32_BULK, K, replay=rec, prof_layers=prof_layers)
+        fp64 = dict(value=gate_steps / p64["seconds"], ms_per_step=1e3 * p64["seconds"] / K, waves=p64["waves"],
+                    certified_error=p64["error"],
+                    vs_fp32_bulk_own_decisions=paired_stats(p32["obs"], p64["obs"]))
+        paired = paired_stats(pp["obs"], p64["obs"])
+        paired["target"] = 1e-4
+        log(f"paired fp32-bulk vs fp64: max |d<O>| {paired['per_traj_max_abs']['max']:.2e}, "
+            f"max |mean d| {paired['mean_diff_max_abs']:.2e}")
     else:
-        achieved = work.get(dom, 0.0) / sec if sec > 0 else 0.0
-        roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK["fp64"] / 1e12, unit="TFLOP/s",
-                    frac=achieved / PEAK["fp64"], traffic=None)
-    roof.update(kernel=KERNEL.get(dom, dom), launches=int(cnt), avg_launch_ms=ms / max(cnt, 1))
+        log(f"fp32-bulk pass, layers {prof_layers} profiled")
+        pp = run_pass(wl, M.FP32_BULK, K, prof_layers=prof_layers)
+    prof = pp["prof"]
+    work, nbytes = algorithmic_work(c.n, wl.chi, prof_layers, T)
+    roof = roofline(work, nbytes, prof, wl)
     kern = {k: dict(ms=v[0], launches=int(v[1])) for k, v in prof.items() if v[1] > 0}
     th = prof.get("theta", (0, 1))
     theta_rate = work["theta"] / (th[0] * 1e-3) if th[0] > 0 else 0.0
-    cpu = None if args.no_cpu else cpu_baseline(wl)
+    cpu, oracle_err = None, None
+    if not args.no_cpu and rec is not None:
+        log("oracle replay of sampled fp64 trajectories (cpu baseline)")
+        cpu, oracle_err = cpu_baseline(wl, K, rec, p64["obs"], pp["obs"], prof_layers)
     line = {
         "metric": "trajectory gate-steps/s at chi=128 (FP32-bulk vs FP64) + <O> error vs oracle",
         "value": value, "unit": "trajectory gate-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": 1e3 * dt32 / K, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": 1e3 * p32["seconds"] / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64 contractions (fp32) + fp64 eig/unravel",
         "data": "synthetic (seeded Haar brickwork, depolarizing p=0.02)",
         "config": {"workload": wl.name, "n_qubits": c.n, "depth": c.depth, "chi": wl.chi,
-                   "n_traj": wl.n_traj, "unravel": "optimal", "parallelism": "trajectories (1 GPU)"},
+                   "n_traj": T, "unravel": "optimal",
+                   "timed": f"layers 0..{K - 1} + measurement sweep (<Z_i>, <Z_i Z_i+1> per trajectory)",
+                   "waves": p32["waves"], "parallelism": "trajectories (1 GPU)"},
         "roofline": roof, "theta_roofline": dict(kernel=KERNEL["theta"], bound="mfma", achieved=theta_rate / 1e12,
                                                  peak=PEAK["fp32"] / 1e12, unit="TFLOP/s",
                                                  frac=theta_rate / PEAK["fp32"]),
-        "kernels_ms": kern, "fp64": fp64, "cpu_baseline": cpu,
+        "kernels_ms": kern,
+        "kernels_ms_pass": f"fp32-bulk, layers {prof_layers[0]}..{prof_layers[-1]}"
+                           + (" following the fp64 decisions" if rec is not None else ""),
+        "certified_error": dict(p32["error"], eps_max=EPS_MAX, delta=DELTA,
+                                meaning="(eps_hat, Hoeffding buffer, bound): with probability >= 1-delta the "
+                                        "trace distance of the sampled mixture to the exact state is <= bound"),
+        "fp64": fp64, "paired_fp32_bulk_vs_fp64": paired, "oracle_error": oracle_err, "cpu_baseline": cpu,
     }
     print(json.dumps(line))
 

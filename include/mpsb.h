@@ -151,8 +151,11 @@ int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c, void* circuit_bu
 
 /* Whole-layer graphs (default on): the first layer with a given launch signature (sweep
  * parity, operations, centre position) runs directly, the second is captured into a HIP
- * graph and every later one replays it with a single graph launch.  Layers that write
- * records, or run while profiling, always run directly. */
+ * graph and every later one replays it with a single graph launch.  The addresses of the
+ * record outputs of apply_layer are part of the signature (a caller that records into the
+ * same buffers every layer gets graph replays that write them; the outputs are cleared by
+ * direct calls before the graph launch).  Layers with replay inputs, or that run while
+ * profiling, always run directly. */
 int mps_batch_set_graphs(mpsb_handle h, int enable);
 
 /* Autotuning of the theta kernel's tile shape (default on): the first time a shape occurs

@@ -1379,9 +1379,11 @@ int apply_layer_replay(mpsb_handle h, int layer, const double* w_in, const int32
   if (branch) HIPCHK(hipMemsetAsync(branch, 0xFF, sizeof(int32_t) * T * rs, h->st));
   if (w_record) HIPCHK(hipMemsetAsync(w_record, 0, sizeof(double) * 32 * T * rs, h->st));
   if (discarded) HIPCHK(hipMemsetAsync(discarded, 0, sizeof(double) * T * (rs / 2), h->st));
-  const bool rec = discarded || branch || w_record || w_in || branch_in;
+  // replay inputs differ per layer, so such layers run as direct launches; recorded outputs
+  // are part of the launch sequence, so their addresses are part of the graph signature
+  const bool replay = w_in || branch_in;
   std::vector<mpsb_batch*> bs = members(h);
-  if (!h->graphs_on || rec || profiling(h)) {
+  if (!h->graphs_on || replay || profiling(h)) {
     int r = enqueue_layer(h, layer, h->st, discarded, branch, w_record, false, w_in, branch_in);
     if (r) return r;
     for (mpsb_batch* b : bs) b->next_layer = layer + 1;
@@ -1390,12 +1392,17 @@ int apply_layer_replay(mpsb_handle h, int layer, const double* w_in, const int32
   }
   std::string sig;
   for (mpsb_batch* b : bs) sig += (layer < b->depth ? layer_signature(b, layer) : std::string("-")) + "|";
+  {
+    char out[80];
+    snprintf(out, sizeof(out), "%p,%p,%p", (void*)discarded, (void*)branch, (void*)w_record);
+    sig += out;
+  }
   auto it = h->graphs.find(sig);
   if (it == h->graphs.end()) {
     static const std::string seen_tag = "#seen";
     if (h->graphs.find(sig + seen_tag) == h->graphs.end()) {
       // first occurrence: run directly (kernel variants are tuned on live operands here)
-      int r = enqueue_layer(h, layer, h->st, nullptr, nullptr, nullptr, false);
+      int r = enqueue_layer(h, layer, h->st, discarded, branch, w_record, false);
       if (r) return r;
       h->graphs[sig + seen_tag] = mpsb_batch::Graph{nullptr, 0};
       for (mpsb_batch* b : bs) b->next_layer = layer + 1;
@@ -1406,7 +1413,7 @@ int apply_layer_replay(mpsb_handle h, int layer, const double* w_in, const int32
     std::vector<int> centres;
     for (mpsb_batch* b : bs) centres.push_back(b->centre);
     HIPCHK(hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeRelaxed));
-    int r = enqueue_layer(h, layer, h->cap_st, nullptr, nullptr, nullptr, true);
+    int r = enqueue_layer(h, layer, h->cap_st, discarded, branch, w_record, true);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->cap_st, &g);
     if (r) {

@@ -46,3 +46,38 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_paired_stats_detects_a_shift_and_accepts_none():
+    import numpy as np
+    rng = np.random.default_rng(3)
+    T, p = 2048, 40
+    mix = rng.standard_normal((p, p)) / np.sqrt(p)          # correlated observables
+    y = rng.standard_normal((T, p)) @ mix
+    x0 = y + 1e-3 * (rng.standard_normal((T, p)) @ mix)       # same mean
+    s0 = bench.paired_stats(x0, y)
+    assert s0["hotelling_rank"] == p and s0["hotelling_p"] > 1e-3
+    assert abs(s0["per_traj_max_abs"]["max"] - np.abs(x0 - y).max()) == 0.0
+    x1 = x0.copy()
+    x1[:, 7] += 2e-4                                         # a shift of 6 standard errors in one
+    s1 = bench.paired_stats(x1, y)
+    assert s1["hotelling_p"] < 1e-4 and s1["z_max"] > 4.0
+    same = bench.paired_stats(y, y)
+    assert same["per_traj_max_abs"]["max"] == 0.0 and "hotelling_t2" not in same
+
+
+def test_tridiag_roofline_is_fp64_flops():
+    class WL:
+        n_traj, chi = 2048, 128
+    work, nbytes = bench.algorithmic_work(100, 128, [8, 9], 2048)
+    prof = {k: (0.0, 0) for k in bench.PROF_NAMES}
+    cp = bench.caps(100, 128)
+    launches = sum(1 for l in (8, 9) for q in range(l % 2, 99, 2)
+                   if 129 <= (2 * cp[q - 1] if l % 2 == 0 else 2 * cp[q + 1]) <= 256)
+    prof["tridiag"] = (2000.0, launches)
+    prof["theta"] = (100.0, 99)
+    r = bench.roofline(work, nbytes, prof, WL)
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
+    flops = 16.0 / 3.0 * 256 ** 3 * 2048                     # one m = 256 Gram per trajectory per launch
+    assert abs(r["flops_per_launch"] - flops) / flops < 0.02
+    assert abs(r["frac"] - r["achieved"] / 78.6) < 1e-12

@@ -20,25 +20,42 @@ from paper_2508_05745_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("record", [False, True])
 @pytest.mark.parametrize("prec", [1, 0])
-def test_graph_replays_match_direct_runs(prec):
+def test_graph_replays_match_direct_runs(prec, record):
+    """record: both runs write the discarded weights, branches and mixings of every layer
+    into the same output buffers each layer (the addresses are part of the graph's
+    signature, so the graph run captures and replays its records too)."""
     import torch
 
     from paper_2508_05745_amd import mpsb as M
     c = I.brickwork(10, 8, seed=41, channel=I.depolarizing(0.05), idle_noise=True)
-    a = M.Batch(64, c.n, 16, prec, 5)
-    b = M.Batch(64, c.n, 16, prec, 5)
+    T = 64
+    a = M.Batch(T, c.n, 16, prec, 5)
+    b = M.Batch(T, c.n, 16, prec, 5)
     a.set_circuit(c, M.OPTIMAL)
     b.set_circuit(c, M.OPTIMAL)
     b.set_graphs(False)
+
+    def bufs():
+        if not record:
+            return dict()
+        return dict(discarded=torch.zeros((T, c.n // 2), dtype=torch.float64, device="cuda"),
+                    branch=torch.zeros((T, c.n), dtype=torch.int32, device="cuda"),
+                    w_record=torch.zeros((T, c.n, 4, 4), dtype=torch.complex128, device="cuda"))
+    ra, rb = bufs(), bufs()
     for l in range(c.depth):
-        a.apply_layer(l)
-        b.apply_layer(l)
+        a.apply_layer(l, **ra)
+        b.apply_layer(l, **rb)
         # eager work between replays
         x = torch.randn(1 << 20, device="cuda")
         _ = (x * x).sum().item()
         torch.cuda.synchronize()
         assert torch.equal(a.state, b.state), l
+        for k in ra:
+            assert torch.equal(ra[k], rb[k]), (l, k)
+        if record and l > 0:
+            assert bool((ra["branch"] >= 0).any()), l
     ma, _, pa = a.expect()
     mb, _, pb = b.expect()
     assert torch.equal(pa, pb)
