@@ -699,27 +699,40 @@ __global__ __launch_bounds__(ET) void k_tri_eig(int n, int keep, double zero_tol
 // along eigenvector j, so the vectors of small eigenvalues whose absolute gaps are tiny
 // (although their relative gaps are not) come out far from orthogonal; a truncation with
 // such vectors no longer projects the state.  Every kept vector is therefore projected out
-// of all vectors before it: blocked Gram-Schmidt with reorthogonalisation, blocks of 16
-// columns against the finished columns in chunks of 16 (block modified Gram-Schmidt, two
-// passes), then modified Gram-Schmidt inside the block on one wave (two passes).  Vectors of
-// well-separated eigenvalues change at rounding level; a vector that cancels almost
-// completely (its eigenvalue lies among eigenvalues closer than rounding can resolve) is
-// replaced by a pseudo-random vector orthogonalised the same way, so that the kept vectors
-// stay a complete orthonormal set.  Columns of dropped eigenvalues stay zero.
+// of all vectors before it (the Q factor of the QR factorisation of the vectors in
+// descending order): blocks of 16 columns are projected against the finished columns in
+// chunks of 16 (block modified Gram-Schmidt, two passes; the chunk products W = X_c^T B and
+// B -= X_c W run on FP64 16x16x4 MFMAs, the first split over the four waves by rows and
+// summed in LDS, with the next chunk's loads in flight), then orthonormalised inside by
+// Cholesky QR, twice (Gram matrix on MFMAs, 16 x 16 Cholesky factor and its inverse on one
+// wave in LDS, B <- B R^-1 on MFMAs).  Vectors of well-separated eigenvalues change at rounding
+// level.  A column whose relative norm after its projections falls below 1e-4 is projected
+// once more (one more round); below 1e-7 (the resolution of a Gram-based factor) it carries
+// no reliable direction: it is left out of the factor and refilled with a pseudo-random
+// vector orthogonalised the same way in the next round, so that the kept vectors stay a
+// complete orthonormal set.  Columns of dropped eigenvalues stay zero.
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+__device__ inline v4d_t mfma64(double a, double b, v4d_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
 template <int NMAX>
 __global__ __launch_bounds__(ET) void k_tri_orth(int n, int keep, double* __restrict__ ws, long long sW,
                                                  const double* __restrict__ evals, long long sE,
                                                  const int* __restrict__ active) {
   if (active && !active[blockIdx.x]) return;
-  constexpr int BW = 16;
-  __shared__ double Bs[NMAX * BW];   // the block, [i][j]
-  __shared__ double Xs[NMAX * BW];   // a chunk of finished columns, [i][kk]
-  __shared__ double Wp[BW * BW];     // projections of the block on the chunk, [kk][j]
-  __shared__ double rho[BW];         // norms of the block's columns after its passes
+  constexpr int BW = 16, S = BW + 1;   // row stride of the LDS panels (odd: rows fall in different banks)
+  constexpr int PF = NMAX * BW / ET;   // chunk elements loaded ahead per thread
+  __shared__ double Bs[NMAX * S];      // the block, [i][j]; rows n .. NP-1 are zero
+  __shared__ double Xs[NMAX * S];      // a chunk of finished columns, [i][kk]; rows n .. NP-1 zero
+  __shared__ double Wpart[4 * BW * BW];   // the waves' partial products
+  __shared__ double Wp[BW * BW];       // projections on the chunk [kk][j], or Gram / Cholesky factor [k][j]
+  __shared__ double rho[BW];           // relative norms of the block's columns after their projections
+  __shared__ double gdiag[BW];         // diagonal of the block's Gram matrix
   __shared__ int s_nk, s_redo;
+  static_assert(ET == 256, "one element of W per thread");
   double* X = ws + blockIdx.x * sW + 6 * (long long)n;
   const double* ev = evals + blockIdx.x * sE;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;   // MFMA operand coordinates of a lane
   if (tid == 0) {
     int nk = 0;
     while (nk < keep && ev[nk] > 0.0) ++nk;
@@ -727,67 +740,120 @@ __global__ __launch_bounds__(ET) void k_tri_orth(int n, int keep, double* __rest
   }
   __syncthreads();
   const int nk = s_nk;
-  const int tj = tid & 15, ti = tid >> 4;   // (row group, column) of a thread in the block products
+  const int NP = (n + 15) & ~15;       // rows rounded up to whole 16-row tiles
+
+  // W = (sum over 4-row steps of A^T B) for two row-major NP x 16 panels in LDS, summed over
+  // the waves into Wp
+  auto panel_product = [&](const double* A, const double* B) {
+    v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int st = wv; st < (NP >> 2); st += 4) {
+      const int r = 4 * st + lk;
+      acc = mfma64(A[r * S + li], B[r * S + li], acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Wpart[wv * BW * BW + (lk + 4 * q) * BW + li] = acc[q];
+    __syncthreads();
+    Wp[tid] = (Wpart[tid] + Wpart[BW * BW + tid]) + (Wpart[2 * BW * BW + tid] + Wpart[3 * BW * BW + tid]);
+    __syncthreads();
+  };
+
   for (int c0 = 0; c0 < nk; c0 += BW) {
     const int pc = min(BW, nk - c0);
-    for (int e = tid; e < n * BW; e += ET) {
+    for (int e = tid; e < NP * BW; e += ET) {
       const int i = e >> 4, j = e & 15;
-      Bs[e] = j < pc ? X[(long long)i * keep + c0 + j] : 0.0;
+      Bs[i * S + j] = (i < n && j < pc) ? X[(long long)i * keep + c0 + j] : 0.0;
     }
     for (int round = 0; round < 3; ++round) {
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int k0 = 0; k0 < c0; k0 += BW) {
-          __syncthreads();
-          for (int e = tid; e < n * BW; e += ET) {
-            const int i = e >> 4, kk = e & 15;
-            Xs[e] = X[(long long)i * keep + k0 + kk];
-          }
-          __syncthreads();
-          {   // Wp[kk][j] = sum_i Xs[i][kk] Bs[i][j]   (kk = ti, j = tj)
-            double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-            int i = 0;
-            for (; i + 3 < n; i += 4) {
-              a0 = fma(Xs[i * BW + ti], Bs[i * BW + tj], a0);
-              a1 = fma(Xs[(i + 1) * BW + ti], Bs[(i + 1) * BW + tj], a1);
-              a2 = fma(Xs[(i + 2) * BW + ti], Bs[(i + 2) * BW + tj], a2);
-              a3 = fma(Xs[(i + 3) * BW + ti], Bs[(i + 3) * BW + tj], a3);
-            }
-            for (; i < n; ++i) a0 = fma(Xs[i * BW + ti], Bs[i * BW + tj], a0);
-            Wp[ti * BW + tj] = (a0 + a1) + (a2 + a3);
-          }
-          __syncthreads();
-          // Bs[i][j] -= sum_kk Xs[i][kk] Wp[kk][j]
-          for (int i = ti; i < n; i += ET / BW) {
-            double acc = Bs[i * BW + tj];
+      // two passes over the finished columns, chunk by chunk; chunk t of the sequence is
+      // columns 16 (t mod (c0 / 16)) .. + 15, loaded one step ahead into registers
+      const int nch = c0 / BW, nseq = 2 * nch;
+      double pf[PF];
+      auto fetch = [&](int t) {
+        const int k0 = (t % nch) * BW;
 #pragma unroll
-            for (int kk = 0; kk < BW; ++kk) acc = fma(-Xs[i * BW + kk], Wp[kk * BW + tj], acc);
-            Bs[i * BW + tj] = acc;
+        for (int m = 0; m < PF; ++m) {
+          const int e = tid + m * ET, i = e >> 4, kk = e & 15;
+          pf[m] = (e < NP * BW && i < n) ? X[(long long)i * keep + k0 + kk] : 0.0;
+        }
+      };
+      if (nseq > 0) fetch(0);
+      for (int t = 0; t < nseq; ++t) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PF; ++m) {
+          const int e = tid + m * ET;
+          if (e < NP * BW) Xs[(e >> 4) * S + (e & 15)] = pf[m];
+        }
+        __syncthreads();
+        if (t + 1 < nseq) fetch(t + 1);
+        panel_product(Xs, Bs);   // W[kk][j] = sum_i Xs[i][kk] Bs[i][j]
+        // Bs[i][j] -= sum_kk Xs[i][kk] W[kk][j], one 16-row tile per wave at a time
+        for (int rt = wv; rt < (NP >> 4); rt += 4) {
+          v4d_t c;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) c[q] = Bs[(16 * rt + lk + 4 * q) * S + li];
+#pragma unroll
+          for (int st = 0; st < 4; ++st) c = mfma64(-Xs[(16 * rt + li) * S + 4 * st + lk], Wp[(4 * st + lk) * BW + li], c);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Bs[(16 * rt + lk + 4 * q) * S + li] = c[q];
+        }
+      }
+      __syncthreads();
+      // inside the block: Cholesky QR, twice
+      for (int cp = 0; cp < 2; ++cp) {
+        panel_product(Bs, Bs);   // Gram matrix G[k][j] in Wp
+        if (wv == 0) {
+          // G = R^T R on one wave, in place in LDS (upper triangle); pivots below 1e-14 of the
+          // column's squared norm leave the column out (R_kk = 1, rest of row k zero)
+          if (lane < BW) gdiag[lane] = Wp[lane * BW + lane];
+          __builtin_amdgcn_wave_barrier();
+          for (int k = 0; k < BW; ++k) {
+            const double gkk = Wp[k * BW + k], g0 = gdiag[k];
+            const bool ok = k < pc && g0 > 0.0 && gkk > 1e-14 * g0;
+            if (cp == 0 && lane == 0) rho[k] = (k < pc && g0 > 0.0) ? sqrt(fmax(gkk, 0.0) / g0) : 1.0;
+            const double rkk = ok ? sqrt(gkk) : 1.0;
+            __builtin_amdgcn_wave_barrier();
+            if (lane < BW) {
+              const double v = Wp[k * BW + lane];
+              Wp[k * BW + lane] = lane > k ? (ok ? v / rkk : 0.0) : (lane == k ? rkk : 0.0);
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int m = 0; m < BW * BW / 64; ++m) {
+              const int e = lane + 64 * m, i = e >> 4, j = e & 15;
+              if (i > k && j >= i) Wp[e] = fma(-Wp[k * BW + i], Wp[k * BW + j], Wp[e]);
+            }
+            __builtin_amdgcn_wave_barrier();
+          }
+          // R^-1 into Wpart, lane j < 16 computing column j by back-substitution
+          if (lane < BW) {
+            const int j = lane;
+            for (int i = 0; i < BW; ++i) Wpart[i * BW + j] = 0.0;
+            Wpart[j * BW + j] = 1.0 / Wp[j * BW + j];
+            for (int i = j - 1; i >= 0; --i) {
+              double acc = 0.0;
+              for (int k = i + 1; k <= j; ++k) acc = fma(Wp[i * BW + k], Wpart[k * BW + j], acc);
+              Wpart[i * BW + j] = -acc / Wp[i * BW + i];
+            }
           }
         }
-      }
-      __syncthreads();
-      // inside the block: modified Gram-Schmidt, two passes, on wave 0 (lanes over rows)
-      if (wv == 0) {
-        for (int j = 0; j < pc; ++j) {
-          for (int pass = 0; pass < 2; ++pass)
-            for (int p = 0; p < j; ++p) {
-              double d = 0;
-              for (int i = lane; i < n; i += 64) d = fma(Bs[i * BW + p], Bs[i * BW + j], d);
-              d = wave_sum(d);
-              for (int i = lane; i < n; i += 64) Bs[i * BW + j] = fma(-d, Bs[i * BW + p], Bs[i * BW + j]);
-            }
-          double q = 0;
-          for (int i = lane; i < n; i += 64) q = fma(Bs[i * BW + j], Bs[i * BW + j], q);
-          q = sqrt(wave_sum(q));
-          const double inv = q > 0 ? 1.0 / q : 0.0;
-          for (int i = lane; i < n; i += 64) Bs[i * BW + j] *= inv;
-          if (lane == 0) rho[j] = q;
+        __syncthreads();
+        // B <- B R^-1 on MFMAs, one 16-row tile per wave at a time (a tile is read before it
+        // is overwritten)
+        for (int rt = wv; rt < (NP >> 4); rt += 4) {
+          double a[4];
+#pragma unroll
+          for (int st = 0; st < 4; ++st) a[st] = Bs[(16 * rt + li) * S + 4 * st + lk];
+          v4d_t c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int st = 0; st < 4; ++st) c = mfma64(a[st], Wpart[(4 * st + lk) * BW + li], c);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Bs[(16 * rt + lk + 4 * q) * S + li] = c[q];
         }
+        __syncthreads();
       }
-      __syncthreads();
-      // the columns came in with unit norm: a column that cancelled to below 1e-4 is
-      // orthogonalised once more (one more round), one that cancelled to below 1e-12 carries
-      // no reliable direction and is refilled with a pseudo-random vector first
+      // a column that cancelled to below 1e-4 of its norm is projected once more (one more
+      // round); one below 1e-7 is refilled with a pseudo-random vector first
       if (tid == 0) {
         int redo = 0;
         for (int j = 0; j < pc; ++j) redo |= rho[j] < 1e-4;
@@ -797,16 +863,16 @@ __global__ __launch_bounds__(ET) void k_tri_orth(int n, int keep, double* __rest
       if (!s_redo || round == 2) break;
       for (int e = tid; e < n * BW; e += ET) {
         const int i = e >> 4, j = e & 15;
-        if (j < pc && rho[j] < 1e-12)
-          Bs[e] = (double)(hash32((uint32_t)(i * 7919 + (c0 + j) * 104729 + round * 15485863 + 3)) >> 8) *
-                      (1.0 / 16777216.0) - 0.5;
+        if (j < pc && rho[j] < 1e-7)
+          Bs[i * S + j] = (double)(hash32((uint32_t)(i * 7919 + (c0 + j) * 104729 + round * 15485863 + 3)) >> 8) *
+                              (1.0 / 16777216.0) - 0.5;
       }
       __syncthreads();
     }
     // the block is finished: write it back
     for (int e = tid; e < n * BW; e += ET) {
       const int i = e >> 4, j = e & 15;
-      if (j < pc) X[(long long)i * keep + c0 + j] = Bs[e];
+      if (j < pc) X[(long long)i * keep + c0 + j] = Bs[i * S + j];
     }
     __syncthreads();
   }
@@ -949,9 +1015,6 @@ __global__ __launch_bounds__(ET) void k_backtransform(int n, int keep, const c64
 // numbered so that they run on one XCD); the panel is written out once.
 // MFMA lane layout (f64 16x16x4): A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
 // D[i][j] in lane j + 16 (i % 4), register i / 4.
-typedef double v4d_t __attribute__((ext_vector_type(4)));
-__device__ inline v4d_t mfma64(double a, double b, v4d_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-
 // workspace per matrix: d, e, trace, omega, X and the inverse-iteration arrays (6 n + 6 n keep
 // doubles), then the T factors (2 * 16 * 16 doubles per block of 16 reflectors)
 __host__ __device__ inline size_t bt_tfac_offset(int n, int keep) { return (size_t)6 * n + (size_t)6 * n * keep + 64; }
