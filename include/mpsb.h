@@ -47,8 +47,16 @@ extern "C" {
  * are K'_j = sum_i U[j][i] K_i, j = 0..3 (always four outputs, some possibly zero). */
 #define MPSB_ORTHOGONAL 0 /* the channel's own operators (U = identity, zero-padded)     */
 #define MPSB_FIXED 1      /* a caller-given, state-independent 4 x r mixing U           */
+#define MPSB_HAAR_OPT 2   /* the Haar Optimal unraveling (table of unravelings, Sec.
+                             "Noisy random circuits"; appendix "Some common unravelings"):
+                             the channel's operators rotated by H (two operators) or by
+                             the printed 4 x 4 Hadamard matrix (four); 1, 2 or 4 operators */
 #define MPSB_OPTIMAL 3    /* locally entanglement-optimal mixing (Thm. 2: Wootters'
                              decomposition of the effective two-qubit state)            */
+#define MPSB_LEAST_UNITARY 4 /* the least unitary unraveling (appendix "Vectorized Kraus
+                             operators and the least unitary unraveling"): the optimal
+                             mixing for the maximally mixed reduced state, i.e. of the
+                             channel's Choi state; state independent                    */
 
 #define MPSB_MAX_CHI 256      /* largest supported bond dimension                       */
 #define MPSB_MAX_QUBITS 4096
@@ -76,6 +84,9 @@ typedef struct mpsb_batch* mpsb_handle;
  *          qubits follows that gate (lower qubit first); noise on an idle qubit is applied
  *          when the layer's sweep reaches it;
  *   fixed_u [n_channels][4][4] c128 (row j = output operator), used with MPSB_FIXED.
+ * With MPSB_HAAR_OPT or MPSB_LEAST_UNITARY the library computes a fixed mixing per channel
+ * when the circuit is set (the least unitary one by the unravelling kernel on the device)
+ * and the batch runs as MPSB_FIXED with it (sample_kraus with MPSB_FIXED uses it too).
  */
 typedef struct {
     int depth;
@@ -88,7 +99,8 @@ typedef struct {
     const int32_t* events;
     int events_per_traj;
     int unravel_mode;
-    const double* fixed_u; /* may be NULL unless unravel_mode == MPSB_FIXED */
+    const double* fixed_u; /* may be NULL unless unravel_mode == MPSB_FIXED (ignored with
+                              MPSB_HAAR_OPT and MPSB_LEAST_UNITARY)                      */
 } mpsb_circuit;
 
 /* Sizes of the two caller buffers for n_traj trajectories of the truncated trajectory
@@ -189,6 +201,18 @@ int apply_layer(mpsb_handle h, int layer, double* discarded, int32_t* branch,
  * those of apply_layer.  Layers with replay inputs run without graphs. */
 int apply_layer_replay(mpsb_handle h, int layer, const double* w_in, const int32_t* branch_in,
                        double* discarded, int32_t* branch, double* w_record);
+
+/* Optional bond-entropy output of apply_layer / apply_layer_replay (Preliminaries,
+ * "Entanglement measures": the von Neumann entanglement entropy of a bipartition, here the
+ * cut at the pair's bond): entropy [n_traj][W/2] FP64 device array, or NULL to stop.  Every
+ * gate-step of a layer writes, in slot i (pair p + 2i: the layout of `discarded`), the
+ * entropy (base 2) of the pair's bond after the step, -sum_k s_k log2 s_k over the kept,
+ * renormalised squared Schmidt coefficients s_k, i.e. the FP64 eigenvalues of the step's
+ * Gram matrix (a step that discards nothing solves that Gram matrix for this output only);
+ * slots without a gate in the layer are set to 0.  The array must stay allocated while it
+ * is set; its address is part of the layer-graph signature.  mps_truncate, expect and
+ * sample_kraus do not write it. */
+int mps_batch_set_entropy(mpsb_handle h, double* entropy);
 
 /* Channel-unravelling subprocedure (Alg. 1) for one noise event per trajectory on qubit
  * qubit[t] (host array [n_traj], the centre is moved there first) with channel

@@ -47,7 +47,9 @@ import numpy as np
 
 MODE_ORTHOGONAL = 0
 MODE_FIXED = 1
+MODE_HAAR_OPT = 2
 MODE_OPTIMAL = 3
+MODE_LEAST_UNITARY = 4
 
 YY = np.kron(np.array([[0, -1j], [1j, 0]]), np.array([[0, -1j], [1j, 0]])).real.astype(np.complex128)
 H4 = 0.5 * np.array([[1, 1, 1, 1], [1, 1, -1, -1], [1, -1, 1, -1], [1, -1, -1, 1]],
@@ -225,12 +227,39 @@ def optimal_mixing(rho_q: np.ndarray, kraus: np.ndarray):
                 separable=separable, z=z, phi=phi, v=v, tau=tau, x=x, rank=rank)
 
 
+def haar_optimal_u(r: int) -> np.ndarray:
+    """The mixing of the Haar Optimal unravelings (table of unravelings, Sec. "Noisy random
+    circuits"; appendix "Some common unravelings"): the Orthogonal Kraus set rotated by the
+    Hadamard matrix H (two operators: dephasing, amplitude damping) or, for four operators
+    (depolarizing), by the 4 x 4 matrix the appendix prints (H (x) H with its two middle rows
+    exchanged: the same operators in the printed branch order); one operator is left alone.
+    Returned as 4 x r, zero rows past r."""
+    h = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
+    h4 = 0.5 * np.array([[1, 1, 1, 1], [1, 1, -1, -1], [1, -1, 1, -1], [1, -1, -1, 1]], dtype=np.complex128)
+    mats = {1: np.ones((1, 1), dtype=np.complex128), 2: h, 4: h4}
+    if r not in mats:
+        raise ValueError(f"the Haar Optimal mixing is defined for 1, 2 or 4 Kraus operators, not {r}")
+    u = np.zeros((4, r), dtype=np.complex128)
+    u[:r] = mats[r]
+    return u
+
+
+def least_unitary_w(kraus: np.ndarray) -> np.ndarray:
+    """The least unitary unraveling (appendix "Vectorized Kraus operators and the least
+    unitary unraveling"): the locally entanglement-optimal mixing for the maximally mixed
+    reduced state I/2, i.e. Wootters' optimal decomposition of the channel's normalised Choi
+    state; it does not depend on the state it is applied to."""
+    return optimal_mixing(np.eye(2, dtype=np.complex128) / 2.0, kraus)["W"]
+
+
 def mixing(rho_q: np.ndarray, kraus: np.ndarray, mode: int, fixed_u=None) -> np.ndarray:
     """W (r x 4) for the requested unravelling mode.
 
-    ORTHOGONAL: the channel's own Kraus operators (padded with zero operators to 4);
-    FIXED:      K'_j = sum_i U_ji K_i for a caller-given 4 x r matrix U;
-    OPTIMAL:    the locally entanglement-optimal mixing above.
+    ORTHOGONAL:    the channel's own Kraus operators (padded with zero operators to 4);
+    FIXED:         K'_j = sum_i U_ji K_i for a caller-given 4 x r matrix U;
+    HAAR_OPT:      FIXED with the Haar Optimal mixing of the channel's rank;
+    OPTIMAL:       the locally entanglement-optimal mixing above;
+    LEAST_UNITARY: the optimal mixing of the channel's Choi state (state independent).
     """
     r = kraus.shape[0]
     if mode == MODE_ORTHOGONAL:
@@ -239,8 +268,12 @@ def mixing(rho_q: np.ndarray, kraus: np.ndarray, mode: int, fixed_u=None) -> np.
         return w
     if mode == MODE_FIXED:
         return np.asarray(fixed_u, dtype=np.complex128).T.copy()
+    if mode == MODE_HAAR_OPT:
+        return haar_optimal_u(r).T.copy()
     if mode == MODE_OPTIMAL:
         return optimal_mixing(rho_q, kraus)["W"]
+    if mode == MODE_LEAST_UNITARY:
+        return least_unitary_w(kraus)
     raise ValueError(f"unknown mode {mode}")
 
 

@@ -102,6 +102,7 @@ hipError_t site_rdm(int prec, int chi_l, int chi_r, const void* site, long long 
 hipError_t site_apply(int prec, int chi_l, int chi_r, void* site, long long s_traj, const double* kops, int n_traj,
                       hipStream_t st);
 // renormalisation factors 1/sqrt(kept) and discarded weight (kept / trace)
+hipError_t bond_entropy(const double* ev, long long sE, int keep, double* out, int stride, int n_traj, hipStream_t st);
 hipError_t trunc_factors(const double* kept, const double* ws, long long sW, int n, double* alpha,
                          double* discarded, int disc_stride, int accumulate, int n_traj, hipStream_t st);
 // untruncated splits: 1 / ||X||_F per trajectory (and a zero discarded weight unless

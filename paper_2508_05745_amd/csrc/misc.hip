@@ -107,6 +107,31 @@ hipError_t trunc_factors(const double* kept, const double* ws, long long sW, int
   return hipGetLastError();
 }
 
+// Entanglement entropy (base 2) of a bond from the eigenvalues of its Gram matrix (the
+// squared Schmidt coefficients up to normalisation): S = log2 N - (1/N) sum_k l_k log2 l_k,
+// N = sum_k l_k, over the first `keep` values (dropped ones are 0); one thread per
+// trajectory, sums in index order.
+__global__ void k_bond_entropy(const double* __restrict__ ev, long long sE, int keep, double* __restrict__ out,
+                               int stride, int n_traj) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_traj) return;
+  const double* e = ev + t * sE;
+  double nrm = 0.0, a = 0.0;
+  for (int k = 0; k < keep; ++k) {
+    const double l = e[k];
+    if (l > 0.0) {
+      nrm += l;
+      a = fma(l, log2(l), a);
+    }
+  }
+  out[(long long)t * stride] = nrm > 0.0 ? fmax(log2(nrm) - a / nrm, 0.0) : 0.0;
+}
+
+hipError_t bond_entropy(const double* ev, long long sE, int keep, double* out, int stride, int n_traj, hipStream_t st) {
+  hipLaunchKernelGGL(k_bond_entropy, dim3((n_traj + 255) / 256), dim3(256), 0, st, ev, sE, keep, out, stride, n_traj);
+  return hipGetLastError();
+}
+
 // zero columns [c0, c0+w) of rows x ld matrices (prec)
 template <typename T>
 __global__ void k_zero_cols(cplx<T>* X, long long sX, int rows, int ld, int c0, int w, int n_traj) {

@@ -193,6 +193,8 @@ struct mpsb_batch {
   std::vector<unsigned char> any_ev;   // [depth][n]: some trajectory has an event on (layer, qubit)
   Tables tab;
   int traj_base = 0;                   // index of trajectory 0 in the batch (sub-batch of a mixed batch)
+  double* entropy = nullptr;           // bond-entropy output set by mps_batch_set_entropy (whole batch)
+  double* ent_rows = nullptr;          // its rows of this batch while a layer is enqueued
   const double* rep_w = nullptr;       // replay inputs of the layer being enqueued (rows of this batch)
   const int32_t* rep_b = nullptr;
   long long traj_offset = 0;           // global index of the batch's trajectory 0 (branch-draw keys)
@@ -612,7 +614,8 @@ int theta_variant(mpsb_batch* h, int p, int cl, int cm, int cr, const void* Sq, 
 // q+1), else from the by-value channels ch_s / ch_t (-1 = none).
 int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, bool tables, int ch_s, int ch_t,
                   bool has_s, bool has_t, bool left_to_right, int keep, double* discarded, int disc_stride,
-                  int accumulate, int32_t* branch, double* w_record, bool capturing = false) {
+                  int accumulate, int32_t* branch, double* w_record, bool capturing = false,
+                  double* entropy = nullptr) {
   Layout& L = h->L;
   const int p = L.prec == MPSB_FP64 ? 1 : 0, T = L.n_traj;
   int r = move_centre(h, q, q + 1);
@@ -667,6 +670,16 @@ int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, b
   const int full = std::min(2 * bl, 2 * br);
   const bool ident = left_to_right ? bl <= br : br <= bl;
   if (kk >= full) {
+    if (entropy) {
+      // the bond's spectrum for the entropy output: eigenvalues of the Gram matrix of X
+      if (left_to_right)
+        HIPCHK(gemm(p, 1, false, true, 2 * cl, 2 * cl, 2 * cr, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cl, L.s_gram, nullptr, T, h->st, true));
+      else
+        HIPCHK(gemm(p, 1, true, false, 2 * cr, 2 * cr, 2 * cl, X, 2 * cr, L.s_x, X, 2 * cr, L.s_x, gram, 2 * cr, L.s_gram, nullptr, T, h->st, true));
+      HIPCHK(heev_all(h, n, full, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
+                      W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), Z, L.s_z, T));
+      HIPCHK(bond_entropy(W<double>(h, L.o_evals), L.s_evals, full, entropy, disc_stride, T, h->st));
+    }
     // nothing is discarded: an exact split of the live block (an identity, or a QR
     // factorisation through the small Gram: Cholesky up to 128 columns, beyond that its
     // eigen-decomposition with every direction kept), so that no direction of the state,
@@ -735,6 +748,9 @@ int two_site_step(mpsb_batch* h, int layer, int q, int slot, const Mat4& gate, b
   HIPCHK(heev_all(h, n, kk, zero_tol(L), gram, L.s_gram, W<double>(h, L.o_ews), L.s_ews, W<double>(h, L.o_gws), L.s_gws,
               W<double>(h, L.o_evals), L.s_evals, W<double>(h, L.o_kept), Z, L.s_z, T));
   HIPCHK(trunc_factors(W<double>(h, L.o_kept), W<double>(h, L.o_ews), L.s_ews, n, alpha, discarded, disc_stride, accumulate, T, h->st));
+  // the kept eigenvalues are accurate to eps lambda_max in absolute terms, also below the
+  // second-level threshold (only the vectors of those need the re-solve below)
+  if (entropy) HIPCHK(bond_entropy(W<double>(h, L.o_evals), L.s_evals, kk, entropy, disc_stride, T, h->st));
   if (L.prec == MPSB_FP64) {
     // cuts below the Gram's resolution: re-solve the kept subspace from the residual of the
     // well-resolved directions (trajectories whose cut is resolved skip every launch)
@@ -855,7 +871,7 @@ int run_layer(mpsb_batch* h, int layer, double* discarded, int disc_stride, int3
       const int slot = (op.q - par) / 2;
       double* disc = discarded ? discarded + slot : nullptr;
       r = two_site_step(h, layer, op.q, slot, none, true, -1, -1, op.has_s, op.has_t, l2r, L.cap[op.q], disc,
-                        disc_stride, 0, branch, w_record, capturing);
+                        disc_stride, 0, branch, w_record, capturing, h->ent_rows ? h->ent_rows + slot : nullptr);
     } else {
       r = idle_step(h, layer, op.q, true, 0, h->mode, nullptr, branch, w_record, nullptr);
     }
@@ -948,9 +964,27 @@ void destroy_batch(mpsb_batch* h) {
   delete h;
 }
 
+// The Haar Optimal mixing of a channel with r orthogonal Kraus operators (table of
+// unravelings in Sec. "Noisy random circuits"; appendix "Some common unravelings"): H for
+// two, the 4 x 4 matrix the appendix prints for four, 1 for one.  U [4][4] c128, row j =
+// output operator, columns past r zero.
+void haar_optimal_mixing(int r, double* u) {
+  for (int x = 0; x < 32; ++x) u[x] = 0.0;
+  if (r == 1) {
+    u[0] = 1.0;
+  } else if (r == 2) {
+    const double h = std::sqrt(0.5);
+    u[0] = h; u[2] = h; u[8] = h; u[10] = -h;
+  } else if (r == 4) {
+    static const int sg[4][4] = {{1, 1, 1, 1}, {1, 1, -1, -1}, {1, -1, 1, -1}, {1, -1, -1, 1}};
+    for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < 4; ++i) u[2 * (4 * j + i)] = 0.5 * sg[j][i];
+  }
+}
+
 // ---- circuit tables
 struct CircLayout {
-  size_t o_layer, o_gpool, o_gid, o_kraus, o_nk, o_fixed, o_ev, bytes;
+  size_t o_layer, o_gpool, o_gid, o_kraus, o_nk, o_fixed, o_ev, o_scr, bytes;
   int n_pool, mpmax, nmax;
   long long gid_ts, ev_ts;
 };
@@ -973,6 +1007,8 @@ int circuit_layout(int n_traj, int nmax, const mpsb_circuit* c, CircLayout& C) {
   C.o_nk = take(sizeof(int) * (size_t)c->n_channels);
   C.o_fixed = take(sizeof(double) * 32 * (size_t)c->n_channels);
   C.o_ev = take(sizeof(int) * (size_t)ev_n);
+  // scratch of the least unitary mixings: I/2, then U [4][r], p [4], eof per channel
+  C.o_scr = take(c->unravel_mode == MPSB_LEAST_UNITARY ? sizeof(double) * (16 + 40 * (size_t)c->n_channels) : 0);
   C.bytes = o;
   return MPSB_OK;
 }
@@ -991,7 +1027,8 @@ int validate_circuit(int n_traj, const int32_t* width, const mpsb_circuit* c, in
   (void)uniform;
   if (c->depth < 0 || c->depth > 65535) return fail(MPSB_EINVAL, "depth must be in 0..65535");
   if (c->n_channels < 0 || c->n_channels > MPSB_MAX_CHANNELS) return fail(MPSB_EINVAL, "n_channels out of range");
-  if (c->unravel_mode != MPSB_ORTHOGONAL && c->unravel_mode != MPSB_FIXED && c->unravel_mode != MPSB_OPTIMAL)
+  if (c->unravel_mode != MPSB_ORTHOGONAL && c->unravel_mode != MPSB_FIXED && c->unravel_mode != MPSB_OPTIMAL &&
+      c->unravel_mode != MPSB_HAAR_OPT && c->unravel_mode != MPSB_LEAST_UNITARY)
     return fail(MPSB_EINVAL, "unknown unravel mode");
   if (c->n_gates < 0) return fail(MPSB_EINVAL, "n_gates < 0");
   if (c->depth > 0 && (!c->gates || !c->events)) return fail(MPSB_EINVAL, "null gates / events");
@@ -1023,6 +1060,8 @@ int validate_circuit(int n_traj, const int32_t* width, const mpsb_circuit* c, in
   for (int ch = 0; ch < c->n_channels; ++ch) {
     int r = c->n_kraus[ch];
     if (r < 1 || r > 4) return fail(MPSB_EINVAL, "n_kraus must be in 1..4");
+    if (c->unravel_mode == MPSB_HAAR_OPT && r == 3)
+      return fail(MPSB_EINVAL, "the Haar Optimal mixing is defined for 1, 2 or 4 Kraus operators");
     const double* k = c->kraus + (size_t)ch * 32;
     for (int x = 0; x < 32; ++x)
       if (!std::isfinite(k[x])) return fail(MPSB_ENUM, "non-finite Kraus entry");
@@ -1074,6 +1113,7 @@ int enqueue_layer(mpsb_batch* h, int layer, hipStream_t S, double* discarded, in
     w = w_record ? w_record + (size_t)b->traj_base * rs * 32 : nullptr;
     b->rep_w = w_in ? w_in + (size_t)b->traj_base * rs * 32 : nullptr;
     b->rep_b = branch_in ? branch_in + (size_t)b->traj_base * rs : nullptr;
+    b->ent_rows = h->entropy ? h->entropy + (size_t)b->traj_base * dstr : nullptr;
   };
   if (h->sub.empty()) {
     hipStream_t keep = h->st;
@@ -1084,6 +1124,7 @@ int enqueue_layer(mpsb_batch* h, int layer, hipStream_t S, double* discarded, in
     h->st = keep;
     h->rep_w = nullptr;
     h->rep_b = nullptr;
+    h->ent_rows = nullptr;
     if (r) return r;
     HIPCHK(inc_int(h->tab.layer, S));
     return MPSB_OK;
@@ -1101,6 +1142,7 @@ int enqueue_layer(mpsb_batch* h, int layer, hipStream_t S, double* discarded, in
     r = run_layer(b, layer, d, dstr, br, w, capturing);
     b->rep_w = nullptr;
     b->rep_b = nullptr;
+    b->ent_rows = nullptr;
   }
   for (int j = 0; j < NS; ++j) {
     HIPCHK(hipEventRecord(h->join_ev[j], h->streams[j]));
@@ -1292,13 +1334,49 @@ int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c, void* circuit_bu
   std::vector<int> ev(c->events, c->events + (size_t)(c->events_per_traj ? T : 1) * D * nmax);
   std::vector<int> nk(c->n_kraus, c->n_kraus + c->n_channels);
   char* base = (char*)circuit_buf;
+  // the Haar Optimal and least unitary unravelings run as fixed mixings (U [n_channels][4][4])
+  int mode = c->unravel_mode;
+  const double* fixed_host = c->fixed_u;
+  std::vector<double> resolved;
+  if (mode == MPSB_HAAR_OPT) {
+    resolved.assign((size_t)32 * c->n_channels, 0.0);
+    for (int ch = 0; ch < c->n_channels; ++ch) haar_optimal_mixing(c->n_kraus[ch], &resolved[(size_t)ch * 32]);
+    fixed_host = resolved.data();
+    mode = MPSB_FIXED;
+  }
   HIPCHK(hipMemcpyAsync(base + C.o_gpool, pool.data(), sizeof(double) * pool.size(), hipMemcpyHostToDevice, h->st));
   HIPCHK(hipMemcpyAsync(base + C.o_gid, gid.data(), sizeof(int) * gid.size(), hipMemcpyHostToDevice, h->st));
   if (c->n_channels > 0) {
     HIPCHK(hipMemcpyAsync(base + C.o_kraus, c->kraus, sizeof(double) * 32 * c->n_channels, hipMemcpyHostToDevice, h->st));
     HIPCHK(hipMemcpyAsync(base + C.o_nk, nk.data(), sizeof(int) * nk.size(), hipMemcpyHostToDevice, h->st));
-    if (c->fixed_u)
-      HIPCHK(hipMemcpyAsync(base + C.o_fixed, c->fixed_u, sizeof(double) * 32 * c->n_channels, hipMemcpyHostToDevice, h->st));
+    if (mode == MPSB_LEAST_UNITARY) {
+      // the locally entanglement-optimal mixing of each channel for the maximally mixed
+      // reduced state (its Choi state), by the unravelling kernel, in the circuit buffer's
+      // scratch region
+      double* scr = (double*)(base + C.o_scr);
+      const double half[8] = {0.5, 0.0, 0.0, 0.0, 0.0, 0.0, 0.5, 0.0};
+      HIPCHK(hipMemcpyAsync(scr, half, sizeof(half), hipMemcpyHostToDevice, h->st));
+      for (int ch = 0; ch < c->n_channels; ++ch)
+        HIPCHK(launch_unravel_opt(1, scr, (const double*)(base + C.o_kraus) + (size_t)ch * 32, 1, nullptr, c->n_kraus[ch],
+                                  scr + 16 + (size_t)ch * 40, scr + 16 + (size_t)ch * 40 + 32,
+                                  scr + 16 + (size_t)ch * 40 + 36, h->st));
+      std::vector<double> out((size_t)40 * c->n_channels);
+      HIPCHK(hipMemcpyAsync(out.data(), scr + 16, sizeof(double) * out.size(), hipMemcpyDeviceToHost, h->st));
+      HIPCHK(hipStreamSynchronize(h->st));
+      resolved.assign((size_t)32 * c->n_channels, 0.0);
+      for (int ch = 0; ch < c->n_channels; ++ch) {
+        const int r = c->n_kraus[ch];
+        const double* u = &out[(size_t)ch * 40];   // [4][r] c128
+        if (!std::isfinite(u[36])) return fail(MPSB_ENUM, "least unitary mixing of channel " + std::to_string(ch));
+        for (int j = 0; j < 4; ++j)
+          for (int i = 0; i < r; ++i)
+            for (int z = 0; z < 2; ++z) resolved[(size_t)ch * 32 + 2 * (4 * j + i) + z] = u[2 * (j * r + i) + z];
+      }
+      fixed_host = resolved.data();
+      mode = MPSB_FIXED;
+    }
+    if (fixed_host)
+      HIPCHK(hipMemcpyAsync(base + C.o_fixed, fixed_host, sizeof(double) * 32 * c->n_channels, hipMemcpyHostToDevice, h->st));
   }
   HIPCHK(hipMemcpyAsync(base + C.o_ev, ev.data(), sizeof(int) * ev.size(), hipMemcpyHostToDevice, h->st));
   HIPCHK(set_int((int*)(base + C.o_layer), h->next_layer, h->st));
@@ -1311,7 +1389,7 @@ int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c, void* circuit_bu
   tab.gid_ls = mp;
   tab.kraus = (const double*)(base + C.o_kraus);
   tab.nk = (const int*)(base + C.o_nk);
-  tab.fixed = c->fixed_u ? (const double*)(base + C.o_fixed) : nullptr;
+  tab.fixed = fixed_host ? (const double*)(base + C.o_fixed) : nullptr;
   tab.ev = (const int*)(base + C.o_ev);
   tab.ev_ts = C.ev_ts;
   tab.ev_ls = nmax;
@@ -1327,11 +1405,11 @@ int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c, void* circuit_bu
     // last layer with work for this batch (identity gates and no events past a trajectory's depth)
     b->depth = D;
     b->n_channels = c->n_channels;
-    b->mode = c->unravel_mode;
+    b->mode = mode;
     if (b == h) {   // host copy of the channels for sample_kraus (uniform batches only)
       b->kraus.assign(c->kraus, c->kraus + (size_t)c->n_channels * 32);
       b->n_kraus.assign(c->n_kraus, c->n_kraus + c->n_channels);
-      if (c->fixed_u) b->fixed_u.assign(c->fixed_u, c->fixed_u + (size_t)c->n_channels * 32);
+      if (fixed_host) b->fixed_u.assign(fixed_host, fixed_host + (size_t)c->n_channels * 32);
       else b->fixed_u.clear();
     }
     b->any_ev.assign((size_t)D * n, 0);
@@ -1348,8 +1426,14 @@ int mps_batch_set_circuit(mpsb_handle h, const mpsb_circuit* c, void* circuit_bu
     b->has_circuit = true;
   }
   h->depth = D;
-  h->mode = c->unravel_mode;
+  h->mode = mode;
   h->has_circuit = true;
+  return MPSB_OK;
+}
+
+int mps_batch_set_entropy(mpsb_handle h, double* entropy) {
+  if (!h) return fail(MPSB_EINVAL, "null handle");
+  h->entropy = entropy;
   return MPSB_OK;
 }
 
@@ -1379,6 +1463,7 @@ int apply_layer_replay(mpsb_handle h, int layer, const double* w_in, const int32
   if (branch) HIPCHK(hipMemsetAsync(branch, 0xFF, sizeof(int32_t) * T * rs, h->st));
   if (w_record) HIPCHK(hipMemsetAsync(w_record, 0, sizeof(double) * 32 * T * rs, h->st));
   if (discarded) HIPCHK(hipMemsetAsync(discarded, 0, sizeof(double) * T * (rs / 2), h->st));
+  if (h->entropy) HIPCHK(hipMemsetAsync(h->entropy, 0, sizeof(double) * T * (rs / 2), h->st));
   // replay inputs differ per layer, so such layers run as direct launches; recorded outputs
   // are part of the launch sequence, so their addresses are part of the graph signature
   const bool replay = w_in || branch_in;
@@ -1393,8 +1478,8 @@ int apply_layer_replay(mpsb_handle h, int layer, const double* w_in, const int32
   std::string sig;
   for (mpsb_batch* b : bs) sig += (layer < b->depth ? layer_signature(b, layer) : std::string("-")) + "|";
   {
-    char out[80];
-    snprintf(out, sizeof(out), "%p,%p,%p", (void*)discarded, (void*)branch, (void*)w_record);
+    char out[96];
+    snprintf(out, sizeof(out), "%p,%p,%p,%p", (void*)discarded, (void*)branch, (void*)w_record, (void*)h->entropy);
     sig += out;
   }
   auto it = h->graphs.find(sig);

@@ -508,9 +508,15 @@ __device__ int one_event(const EventArgs& ea, int slot, int id, const cd (&rho)[
   int j;
   if (forced >= 0) {
     j = forced;
-    if (!(p[j] > 0.0)) return -1;
+    if (j > 3 || !(p[j] > 0.0)) return -1;
   } else {
     j = sample_branch(p, event_uniform(ea.seed, (uint32_t)(ea.traj_base + (long long)traj), layer, qubit));
+    // no branch of positive weight (a zero or non-finite state): nothing is selected
+    if (j < 0) {
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) Ksel[a][b] = cz();
+      return -2;
+    }
   }
   double inv = 1.0 / sqrt(p[j]);
   for (int a = 0; a < 2; ++a)
@@ -565,7 +571,7 @@ __global__ __launch_bounds__(64) void k_gate_events(EventArgs ea, const double* 
     for (int s = 0; s < 2; ++s)
       for (int s2 = 0; s2 < 2; ++s2) rs[s][s2] = rho[2 * s][2 * s2] + rho[2 * s + 1][2 * s2 + 1];
     int j = one_event(ea, 0, ch_s, rs, traj, layer, q, -1, Ks, p, W);
-    if (j < 0) { atomicOr(status, 2); j = 0; }
+    if (j < 0) { atomicOr(status, j == -1 ? 2 : 1); j = 0; }
     write_record(ea, traj, q, j, W);
     // rho <- (Ks x I) rho (Ks x I)^dag  (Ks already carries 1/sqrt(p))
     cd t1[4][4];
@@ -590,7 +596,7 @@ __global__ __launch_bounds__(64) void k_gate_events(EventArgs ea, const double* 
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) rt[a][b] = (1.0 / tt) * rt[a][b];
     int j = one_event(ea, 1, ch_t, rt, traj, layer, q + 1, -1, Kt, p, W);
-    if (j < 0) { atomicOr(status, 2); j = 0; }
+    if (j < 0) { atomicOr(status, j == -1 ? 2 : 1); j = 0; }
     write_record(ea, traj, q + 1, j, W);
   }
   double* ko = kops + (long long)traj * 16;
@@ -628,7 +634,7 @@ __global__ __launch_bounds__(64) void k_site_event(EventArgs ea, const double* _
   int f = forced ? forced[traj] : -1;
   int j = one_event(ea, ch, id, rho, traj, layer, q, f, Ks, p, W);
   if (j < 0) {
-    atomicOr(status, 2);
+    atomicOr(status, j == -1 ? 2 : 1);
     Ks[0][0] = cd{1, 0}; Ks[0][1] = cz(); Ks[1][0] = cz(); Ks[1][1] = cd{1, 0};
     j = 0;
   }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmpsb.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSUP, ENUM, EKRAUS = 0, -1, -2, -3, -4, -5, -6
 FP32_BULK, FP64 = 0, 1
-ORTHOGONAL, FIXED, OPTIMAL = 0, 1, 3
+ORTHOGONAL, FIXED, HAAR_OPT, OPTIMAL, LEAST_UNITARY = 0, 1, 2, 3, 4
 MAX_CHI = 256
 
 _lib = None
@@ -56,6 +56,7 @@ def lib():
         L.mps_batch_set_circuit.argtypes = [vp, ctypes.POINTER(_Circuit), vp, sz]
         L.mps_circuit_validate.argtypes = [i32, vp, ctypes.POINTER(_Circuit)]
         L.mps_batch_set_graphs.argtypes = [vp, i32]
+        L.mps_batch_set_entropy.argtypes = [vp, vp]
         L.mps_batch_set_autotune.argtypes = [vp, i32]
         L.apply_layer.argtypes = [vp, i32, vp, vp, vp]
         L.apply_layer_replay.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -115,8 +116,9 @@ class CircuitArrays:
         self.depth = circuit.depth
         self.mode = mode
         if fixed_u is not None:
+            fx = np.asarray(fixed_u, dtype=np.complex128)
             fu = np.zeros((circuit.channels.shape[0], 4, 4), dtype=np.complex128)
-            fu[:] = fixed_u
+            fu[..., :fx.shape[-1]] = fx           # 4 x r mixings are zero-padded to 4 x 4
             self.fixed_u = np.ascontiguousarray(fu).view(np.float64)
         else:
             self.fixed_u = None
@@ -202,6 +204,12 @@ class Batch:
         buf = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
         _check(lib().mps_batch_set_circuit(self.h, ctypes.byref(st), _ptr(buf), nb.value))
         self._circ, self._cbuf = ca, buf
+
+    def set_entropy(self, entropy=None):
+        """Per-gate bond entropy output of the following layers: a float64 CUDA tensor
+        [n_traj][W/2] (slot layout of `discarded`), or None to stop."""
+        _check(lib().mps_batch_set_entropy(self.h, _ptr(entropy)))
+        self._entropy = entropy
 
     def set_graphs(self, enable: bool):
         _check(lib().mps_batch_set_graphs(self.h, int(bool(enable))))

@@ -73,6 +73,21 @@ def test_circuit_validation():
     with pytest.raises(M.MpsbError):
         M.validate_circuit(c, M.FIXED, 2 * np.eye(4))
     M.validate_circuit(c, M.FIXED, np.eye(4))
+    # named unravelings: Haar Optimal needs 1, 2 or 4 Kraus operators per channel
+    M.validate_circuit(c, M.HAAR_OPT)
+    M.validate_circuit(c, M.LEAST_UNITARY)
+    three = I.brickwork(6, 3, seed=1, channel=I.dephasing(0.1))
+    three.channels = np.zeros((1, 4, 2, 2), dtype=np.complex128)
+    p = 0.1
+    three.channels[0, :3] = [np.sqrt(1 - p) * np.eye(2), np.sqrt(p) * np.diag([1.0, 0.0]), np.sqrt(p) * np.diag([0.0, 1.0])]
+    three.n_kraus = np.array([3])
+    M.validate_circuit(three, M.OPTIMAL)
+    with pytest.raises(M.MpsbError) as e:
+        M.validate_circuit(three, M.HAAR_OPT)
+    assert e.value.code == M.EINVAL
+    with pytest.raises(M.MpsbError) as e:
+        M.validate_circuit(c, 5)
+    assert e.value.code == M.EINVAL
 
 
 def test_mixed_plan_is_the_sum_of_its_runs():

@@ -57,6 +57,61 @@ def test_haar_optimal_fixed_mixings_reach_choi_eof(p):
         assert np.allclose(nz, 1.0 / len(nz))
 
 
+@pytest.mark.parametrize("p", [0.02, 0.1, 0.3])
+def test_haar_optimal_mode_gives_the_printed_kraus_operators(p):
+    """MODE_HAAR_OPT reproduces the Kraus operators printed in the appendix on common
+    unravelings (dephasing: (1/sqrt2)(sqrt(1-p/2) I +- sqrt(p/2) Z); depolarizing:
+    sqrt(1-3p/4)/2 I + (sqrt(p)/4)(+-X +-Y +-Z) with the printed sign patterns; amplitude
+    damping with the 1/sqrt2 prefactor of the corrected reading: (1/sqrt2) [[1, +-sqrt(g)],
+    [0, sqrt(1-g)]]), in the printed order."""
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
+    Y = np.array([[0, -1j], [1j, 0]])
+    Z = np.diag([1.0, -1.0]).astype(complex)
+    E = np.eye(2, dtype=complex)
+    a, b = math.sqrt(1 - p / 2), math.sqrt(p / 2)
+    expect = {
+        "dephasing": [(a * E + b * Z) / math.sqrt(2), (a * E - b * Z) / math.sqrt(2)],
+        "depolarizing": [0.5 * math.sqrt(1 - 3 * p / 4) * E + math.sqrt(p) / 4 * (s1 * X + s2 * Y + s3 * Z)
+                         for s1, s2, s3 in ((1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1))],
+        "amplitude_damping": [np.array([[1, sg * math.sqrt(p)], [0, math.sqrt(1 - p)]]) / math.sqrt(2)
+                              for sg in (1, -1)],
+    }
+    for name, ks in expect.items():
+        k = CHANNELS[name](p)
+        got = U.mixed_kraus(k, U.mixing(None, k, U.MODE_HAAR_OPT))
+        for j, kj in enumerate(ks):
+            assert np.abs(got[j] - kj).max() < 1e-15, (name, j)
+        assert np.abs(got[len(ks):]).max(initial=0.0) == 0.0
+
+
+@pytest.mark.parametrize("name,rate,eof", _golden_choi())
+def test_least_unitary_mode_reaches_the_choi_eof(name, rate, eof):
+    """MODE_LEAST_UNITARY is the optimal decomposition of the channel's Choi state (appendix
+    on the least unitary unraveling): on rho_q = I/2 its average entanglement equals the
+    closed-form EoF of the Choi state; it is a complete Kraus set; it does not depend on the
+    state it is applied to; and the Haar Optimal unraveling reaches the same value (the
+    paper notes it is one of the least unitary unravelings)."""
+    k = CHANNELS[name](rate)
+    half = np.eye(2) / 2
+    w = U.mixing(half, k, U.MODE_LEAST_UNITARY)
+    kp = U.mixed_kraus(k, w)
+    _, eav = U.average_entanglement(half, kp)
+    assert eav == pytest.approx(eof, abs=1e-12)
+    assert np.allclose(sum(x.conj().T @ x for x in kp), np.eye(2), atol=1e-13)
+    rng = np.random.default_rng(int(rate * 1e4))
+    g = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+    rho = g @ g.conj().T
+    rho /= np.trace(rho).real
+    assert np.array_equal(U.mixing(rho, k, U.MODE_LEAST_UNITARY), w)
+    _, e_haar = U.average_entanglement(half, U.mixed_kraus(k, U.mixing(None, k, U.MODE_HAAR_OPT)))
+    assert e_haar == pytest.approx(eof, abs=1e-12)
+
+
+def test_haar_optimal_mode_rejects_three_operators():
+    with pytest.raises(ValueError):
+        U.haar_optimal_u(3)
+
+
 @pytest.mark.parametrize("s,gamma", [(0.3, 0.1), (0.8, 0.5), (0.6, 0.9)])
 def test_amplitude_damping_computational_schmidt_basis(s, gamma):
     """Remark in the appendix: C = 2 s sqrt(1-s^2) sqrt(1-gamma), attained by
