@@ -295,6 +295,24 @@ int mps_error_accumulate(int n_traj, int slots, const double* discarded, int ste
 int mps_error_estimate(int n_traj, const double* eps_tot, double eps_max, double delta,
                        double* out, void* stream);
 
+/* Noisy circuits of Trotterised time-independent Lindbladians (Sec. "Time-independent
+ * Lindbladian systems"; appendix "Exact decomposition of Trotterized Lindbladian
+ * evolutions").  Host-only (host arrays, no device work), for building the gate and channel
+ * tables of mps_batch_set_circuit:
+ *   mps_trotter_gate: gate [4][4] c128 = exp(-i h dt) of a Hermitian pair term h [4][4] c128
+ *     (MPSB_EINVAL if h is not Hermitian to 1e-12 of its largest entry, MPSB_ENUM for a
+ *     non-finite input);
+ *   mps_jump_channel: the Kraus operators of the single-site jump process exp(tau sum_j L_j),
+ *     L_j = gamma_j (c_j (x) c_j^* - 1/2 c_j^dag c_j (x) I - 1/2 I (x) c_j^T c_j^*) for the n_jumps
+ *     jump operators c [n_jumps][2][2] c128 with rates gamma [n_jumps] >= 0: the eigenvectors of
+ *     its Choi matrix times the square roots of their eigenvalues, in descending eigenvalue
+ *     order, eigenvalues below 1e-14 of the largest left out, each operator's largest-modulus
+ *     entry real positive; kraus [4][2][2] c128 (unused operators zero), *n_kraus their number.
+ *     A Trotter step of length dt applies the jump processes for tau = dt / 2 after each of its
+ *     two brickwork layers. */
+int mps_trotter_gate(const double* h, double dt, double* gate);
+int mps_jump_channel(int n_jumps, const double* c, const double* gamma, double tau, double* kraus, int* n_kraus);
+
 /* Batched locally entanglement-optimal unravelling (Sec. "Locally entanglement-optimal
  * unraveling"; appendix "Practical/closed-form version" of Wootters' decomposition): for
  * each of `batch` qubits with normalised reduced state rho_q [batch][2][2] c128 and the

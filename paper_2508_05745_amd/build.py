@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmpsb.so")
-SOURCES = ["gemm.hip", "eig.hip", "hop.hip", "unravel.hip", "misc.hip", "cost.hip", "static_work.hip", "mpsb.cpp"]
+SOURCES = ["gemm.hip", "eig.hip", "hop.hip", "unravel.hip", "misc.hip", "cost.hip", "static_work.hip", "lindblad.cpp", "mpsb.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MPSB_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -27,6 +27,10 @@ static int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
+namespace mpsb {
+// the thread-local error message of mps_last_error, for the library's other host sources
+int report_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace mpsb
 #define HIPCHK(x)                                                                        \
   do {                                                                                   \
     hipError_t e_ = (x);                                                                 \

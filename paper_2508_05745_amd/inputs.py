@@ -269,6 +269,80 @@ def config_wide(chi: int = 128, n_traj: int = 2048) -> Workload:
                     name=f"n100-d40-dep0.02-chi{chi}-{n_traj}traj")
 
 
+# ----------------------------------------------------------------------------- Lindbladians
+
+
+@dataclasses.dataclass
+class LindbladModel:
+    """A time-independent Lindbladian on an open chain (Sec. "Time-independent Lindbladian
+    systems"): H = sum_i h2 on (i, i+1) + sum_i h1 on i, and on every qubit the single-site
+    jump operators ``jumps`` = [(c [2][2], rate gamma)]; Trotter step dt, ``steps`` steps (two
+    brickwork layers each, every layer followed by the jump processes of every qubit for dt/2).
+
+    The pair terms H_(i,i+1) = h2 + w_i h1 (x) I + w_(i+1) I (x) h1 sum to H: w = 1/2 for a
+    site in two pairs, 1 for the two end sites (in one pair only)."""
+    n: int
+    dt: float
+    steps: int
+    h2: np.ndarray
+    h1: np.ndarray
+    jumps: list
+    name: str = ""
+
+    @property
+    def depth(self) -> int:
+        return 2 * self.steps
+
+    def pair_hamiltonian(self, q: int) -> np.ndarray:
+        wl = 1.0 if q == 0 else 0.5
+        wr = 1.0 if q + 1 == self.n - 1 else 0.5
+        return (np.asarray(self.h2, dtype=np.complex128) + wl * np.kron(self.h1, _I) + wr * np.kron(_I, self.h1))
+
+
+def lindblad_circuit(model: LindbladModel, gates: dict, channel: np.ndarray, name: str = "") -> Circuit:
+    """The brickwork circuit of a Trotterised model from its pair gates (dict q -> 4 x 4) and
+    its jump channel (Kraus stack): layer l acts with gates[q] on the pairs of parity l % 2,
+    then the channel hits every qubit (the idle end qubits included)."""
+    n, depth = model.n, model.depth
+    gt = np.zeros((depth, n // 2, 4, 4), dtype=np.complex128)
+    for l in range(depth):
+        for i, q in enumerate(layer_pairs(n, l)):
+            gt[l, i] = gates[q]
+    tab, nk = _pad_channels([np.asarray(channel, dtype=np.complex128)])
+    events = np.zeros((depth, n), dtype=np.int32)
+    return Circuit(n=n, depth=depth, gates=gt, channels=tab, n_kraus=nk, events=events,
+                   name=name or model.name)
+
+
+def amplitude_damping_rate(gamma_ad_per_layer: float, dt: float) -> float:
+    """Jump rate gamma of c = |0><1| whose dt/2 jump process is amplitude damping with rate
+    gamma_ad (the appendix on typical jump operators: gamma_AD = 1 - exp(-gamma tau))."""
+    return -2.0 * np.log1p(-gamma_ad_per_layer) / dt
+
+
+_SIGMA_MINUS = np.array([[0, 1], [0, 0]], dtype=np.complex128)
+
+
+def lindblad_heisenberg(n: int = 16, steps: int = 300, dt: float = 0.01, gamma_ad: float = 0.002) -> LindbladModel:
+    """The fixed Hamiltonian of the paper's first Lindbladian study: H = sum_i Y_i Y_(i+1) +
+    0.35 X_i + 0.35 Y_i + 0.5 Z_i (open chain), amplitude damping of rate gamma_ad per layer."""
+    return LindbladModel(n=n, dt=dt, steps=steps, h2=np.kron(_Y, _Y), h1=0.35 * _X + 0.35 * _Y + 0.5 * _Z,
+                         jumps=[(_SIGMA_MINUS, amplitude_damping_rate(gamma_ad, dt))],
+                         name=f"lindblad_heisenberg_n{n}_dt{dt}_ad{gamma_ad}")
+
+
+def lindblad_random_ti(n: int = 12, steps: int = 300, dt: float = 0.01, gamma_ad: float = 0.002,
+                       seed: int = 0) -> LindbladModel:
+    """A random translation-invariant Lindbladian of the paper's second study: one random
+    Hermitian 4 x 4 pair term (normally distributed real and imaginary parts, Hermitian part
+    taken) repeated on every pair, amplitude damping of rate gamma_ad per layer."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    return LindbladModel(n=n, dt=dt, steps=steps, h2=0.5 * (g + g.conj().T), h1=np.zeros((2, 2), dtype=np.complex128),
+                         jumps=[(_SIGMA_MINUS, amplitude_damping_rate(gamma_ad, dt))],
+                         name=f"lindblad_random_ti_n{n}_dt{dt}_ad{gamma_ad}_s{seed}")
+
+
 def random_two_site_states(count: int, chi_l: int, chi_r: int, seed: int,
                            dtype=np.complex64) -> np.ndarray:
     """``count`` complex Gaussian two-site tensors theta[a][s][t][b], each normalised to

@@ -68,6 +68,8 @@ def lib():
         L.unravel_opt.argtypes = [i32, vp, vp, i32, vp, i32, vp, vp, vp, vp]
         L.mps_error_accumulate.argtypes = [i32, i32, vp, i32, ctypes.c_double, vp, vp]
         L.mps_error_estimate.argtypes = [i32, vp, ctypes.c_double, ctypes.c_double, vp, vp]
+        L.mps_trotter_gate.argtypes = [vp, ctypes.c_double, vp]
+        L.mps_jump_channel.argtypes = [i32, vp, vp, ctypes.c_double, vp, vp]
         L.unravel_cost.argtypes = [i32, vp, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp]
         L.unravel_cost_grad.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, vp]
         _lib = L
@@ -262,6 +264,39 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------------- Lindbladians
+
+
+def trotter_gate(h, dt: float) -> np.ndarray:
+    """exp(-i h dt) of a Hermitian 4 x 4 pair term (host, mps_trotter_gate)."""
+    hh = np.ascontiguousarray(np.asarray(h, dtype=np.complex128))
+    g = np.zeros((4, 4), dtype=np.complex128)
+    _check(lib().mps_trotter_gate(hh.ctypes.data, ctypes.c_double(dt), g.ctypes.data))
+    return g
+
+
+def jump_channel(jumps, tau: float) -> np.ndarray:
+    """Kraus operators [r][2][2] of the jump processes [(c, gamma)] of one site over time tau
+    (host, mps_jump_channel)."""
+    c = np.zeros((max(len(jumps), 1), 2, 2), dtype=np.complex128)
+    g = np.zeros(max(len(jumps), 1))
+    for i, (x, y) in enumerate(jumps):
+        c[i], g[i] = np.asarray(x, dtype=np.complex128), float(y)
+    k = np.zeros((4, 2, 2), dtype=np.complex128)
+    r = ctypes.c_int()
+    _check(lib().mps_jump_channel(len(jumps), c.ctypes.data, g.ctypes.data, ctypes.c_double(tau), k.ctypes.data,
+                                  ctypes.byref(r)))
+    return k[: r.value].copy()
+
+
+def lindblad_circuit(model):
+    """The model's Trotterised noisy brickwork circuit (inputs.LindbladModel), its gates and
+    jump channel made by the library."""
+    from . import inputs as I
+    gates = {q: trotter_gate(model.pair_hamiltonian(q), model.dt) for q in range(model.n - 1)}
+    return I.lindblad_circuit(model, gates, jump_channel(model.jumps, model.dt / 2))
 
 
 # ------------------------------------------------------------------------- certified error

@@ -182,3 +182,25 @@ def test_error_entry_points_validate_on_the_host():
     assert lib.mps_error_estimate(4, one, ctypes.c_double(1.5), ctypes.c_double(0.05), one, None) == M.EINVAL
     assert lib.mps_error_estimate(4, one, ctypes.c_double(4.0), ctypes.c_double(1.0), one, None) == M.EINVAL
     assert lib.mps_error_estimate(0, one, ctypes.c_double(4.0), ctypes.c_double(0.05), one, None) == M.EINVAL
+
+
+def test_lindblad_constructors_validate_on_the_host():
+    """Error paths of the host-side Lindbladian constructors (no device involved)."""
+    g = np.zeros((4, 4), dtype=np.complex128)
+    g[0, 1] = 1.0                                     # not Hermitian
+    with pytest.raises(M.MpsbError) as e:
+        M.trotter_gate(g, 0.1)
+    assert e.value.code == M.EINVAL
+    g[0, 1] = np.nan
+    with pytest.raises(M.MpsbError) as e:
+        M.trotter_gate(g, 0.1)
+    assert e.value.code == M.ENUM
+    sm = np.array([[0, 1], [0, 0]], dtype=np.complex128)
+    with pytest.raises(M.MpsbError) as e:
+        M.jump_channel([(sm, -1.0)], 0.1)
+    assert e.value.code == M.EINVAL
+    with pytest.raises(M.MpsbError) as e:
+        M.jump_channel([(sm, 1.0)], -0.1)
+    assert e.value.code == M.EINVAL
+    with pytest.raises(M.MpsbError) as e:
+        M.jump_channel([], 0.1)
