@@ -26,6 +26,8 @@ consecutive trajectories with the trajectory offset.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--chi 128] [--traj 2048]
        python bench.py --mixed [--traj 16384] [--steps K] [--warmup W]   (mixed-batch workload)
+       python bench.py --cost [--steps K]        (unravelling cost + adjoint, 65536 states)
+       python bench.py --lindblad                (Trotterised Lindbladian workloads)
 """
 from __future__ import annotations
 
@@ -362,6 +364,116 @@ def bench_mixed(args):
     print(json.dumps(line))
 
 
+def bench_cost(args):
+    """Unravelling cost and adjoint on 65536 independent two-site states (chi 64 on each side,
+    complex Gaussian, normalised, c64, drawn on the device), 4-Kraus depolarizing p = 0.02,
+    mixing parameters N(0, 0.1^2) around Haar reference unitaries: one step = the linear
+    cost of every state (the reduction of its reduced qubit state, HBM-bound: 16 chi^2 bytes
+    read per state) and its adjoint gradient."""
+    import torch
+
+    from paper_2508_05745_amd import inputs as I
+    from paper_2508_05745_amd import mpsb as M
+    B, chi = 65536, 64
+    th = I.random_two_site_states_torch(B, chi, chi, seed=4004)
+    pp = torch.as_tensor(I.random_mixing_params(B, seed=4005)).cuda()
+    uu = torch.as_tensor(I.haar_unitaries(B, seed=4006)).cuda()
+    k = I.depolarizing(0.02)
+    W, K = max(args.warmup, 1), args.steps
+    for _ in range(W):
+        f, rho, k4 = M.unravel_cost(th, k, pp, uu, 0)
+        M.unravel_cost_grad(rho, k4, pp, uu, 0, None)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    t0 = time.perf_counter()
+    for e0, e1, e2 in ev:
+        e0.record()
+        f, rho, k4 = M.unravel_cost(th, k, pp, uu, 0)
+        e1.record()
+        M.unravel_cost_grad(rho, k4, pp, uu, 0, None)
+        e2.record()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fwd = sum(a.elapsed_time(b) for a, b, _ in ev) / K
+    bwd = sum(b.elapsed_time(c) for _, b, c in ev) / K
+    nbytes = B * chi * 4 * chi * 8.0
+    cpu = None
+    if not args.no_cpu:
+        from oracle import cost as CO
+        sample = np.linspace(0, B - 1, 4096).astype(np.int64)
+        ths = th[torch.as_tensor(sample).cuda()].cpu().numpy().astype(np.complex128)
+        params, uref = pp.cpu().numpy(), uu.cpu().numpy()
+        t1, n = time.perf_counter(), 0
+        while n < len(sample) and (time.perf_counter() - t1 < 15.0 or n == 0):
+            r = CO.rho_from_theta(ths[n])
+            CO.grad_torch(r / np.trace(r).real, k, params[sample[n]], uref[sample[n]], 0)
+            n += 1
+        cpu = dict(value=n / (time.perf_counter() - t1), unit="states/s", cores=_cores(), kind="oracle", cpu=cpu_model(),
+                   sample=f"{n} states of the batch (NumPy reduction + torch-CPU complex128 autograd)")
+    line = {
+        "metric": "two-site states/s (unravelling cost + adjoint)", "value": B * K / dt, "unit": "states/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * dt / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 states, fp64 reduction / cost / adjoint",
+        "data": "synthetic (seeded complex-Gaussian states, depolarizing p=0.02)",
+        "config": {"workload": f"cost-{B}states-chi{chi}-dep0.02", "n_states": B, "chi": chi},
+        "roofline": dict(bound="hbm", kernel="k_cost_rho<float> + k_cost_eval (forward)", achieved=nbytes / (fwd * 1e-3) / 1e9,
+                         peak=PEAK["hbm"] / 1e9, unit="GB/s", frac=nbytes / (fwd * 1e-3) / PEAK["hbm"], traffic=None,
+                         bytes_per_launch=nbytes, avg_launch_ms=fwd),
+        "backward_ms": bwd, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def bench_lindblad(args):
+    """Trotterised Lindbladian workloads of the paper's two studies: the fixed Heisenberg-type
+    Hamiltonian with amplitude damping (16 qubits, chi 50, 500 trajectories, 600 layers of
+    dt = 0.01 / 2, amplitude damping 0.002 per layer) and a random translation-invariant one
+    (12 qubits, chi 20, 1000 trajectories, 600 layers); optimal unravelling, FP32-bulk, timed
+    from the first layer through the measurement sweep."""
+    import torch
+
+    from paper_2508_05745_amd import inputs as I
+    from paper_2508_05745_amd import mpsb as M
+    runs = []
+    for m, chi, T in ((I.lindblad_heisenberg(n=16, steps=300, dt=0.01, gamma_ad=0.002), 50, 500),
+                      (I.lindblad_random_ti(n=12, steps=300, dt=0.01, gamma_ad=0.002, seed=1), 20, 1000)):
+        c = M.lindblad_circuit(m)
+        L = min(args.steps, c.depth) if args.steps != 40 else c.depth
+        b = M.Batch(T, c.n, chi, M.FP32_BULK, 2007)
+        b.set_circuit(c, M.OPTIMAL)
+        b.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for l in range(L):
+            b.apply_layer(l)
+        b.expect()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.sync()
+        b.close()
+        gates = T * sum(len(c.pairs(l)) for l in range(L))
+        runs.append(dict(workload=f"{m.name}-chi{chi}-{T}traj", layers=L, value=gates / dt, seconds=dt))
+        print(f"# {runs[-1]['workload']}: {dt:.2f} s, {gates / dt:.0f} gate-steps/s", file=sys.stderr, flush=True)
+    line = {
+        "metric": "trajectory gate-steps/s (Lindbladian workloads)", "value": runs[0]["value"],
+        "unit": "trajectory gate-steps/s", "n_gpus": 1, "steps": runs[0]["layers"], "warmup": 0,
+        "ms_per_step": 1e3 * runs[0]["seconds"] / runs[0]["layers"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 contractions (fp32) + fp64 eig/unravel",
+        "data": "synthetic (the paper's Heisenberg-type and seeded random translation-invariant Lindbladians)",
+        "config": {"workload": runs[0]["workload"], "runs": runs},
+    }
+    print(json.dumps(line))
+
+
+def _cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([d.get("num_threads", 1) for d in threadpool_info()] + [1]))
+    except Exception:
+        return os.cpu_count() or 1
+
+
 def roofline(work, nbytes, prof, wl):
     """Roofline of the dominant kernel class (largest HIP-event time in the profiled pass;
     each class times one kernel instance).  The eigensolver's tridiagonalisation is bounded
@@ -398,6 +510,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mixed", action="store_true", help="the mixed-batch workload instead of the headline one")
+    ap.add_argument("--cost", action="store_true", help="the unravelling cost / adjoint workload (65536 states)")
+    ap.add_argument("--lindblad", action="store_true", help="the Trotterised Lindbladian workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB elementwise copy kernel 4 times (HBM counter scale)")
     args = ap.parse_args()
@@ -410,6 +524,12 @@ def main():
         sys.exit(2)
     if args.mixed:
         bench_mixed(args)
+        return
+    if args.cost:
+        bench_cost(args)
+        return
+    if args.lindblad:
+        bench_lindblad(args)
         return
     import torch
 

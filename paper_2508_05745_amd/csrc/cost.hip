@@ -16,22 +16,35 @@ namespace mpsb {
 using cd = c64d;
 
 // ------------------------------------------------------------------ rho_q reduction
+// One workgroup per state.  Thread e takes elements 2e, 2e + 1 of a row (t, b) run (two
+// complex values per vector load, 2 chi_r even), at rows a and a + ... of both s planes; the
+// row / column position advances by a fixed step, so the loop divides nothing.
 template <typename T>
 __global__ __launch_bounds__(256) void k_cost_rho(int chi_l, int chi_r, const cplx<T>* __restrict__ theta, double* rho) {
   __shared__ double red[4][4];
   const long long per = (long long)chi_l * 4 * chi_r;
   const cplx<T>* th = theta + blockIdx.x * per;
-  const int w = 2 * chi_r;   // (t,b) run length
+  const int w = 2 * chi_r;        // (t,b) run length
+  const int w2 = chi_r;           // pairs per run
+  const int tot = chi_l * w2;     // pairs per s plane
+  const int da = 256 / w2, dr = 256 % w2;
+  int a = threadIdx.x / w2, r = threadIdx.x % w2;
   double r00 = 0, r11 = 0, r01r = 0, r01i = 0;
-  const long long tot = (long long)chi_l * w;
-  for (long long e = threadIdx.x; e < tot; e += 256) {
-    int a = (int)(e / w), tb = (int)(e % w);
-    cplx<T> x0 = th[(long long)a * 2 * w + tb], x1 = th[(long long)a * 2 * w + w + tb];
-    double a0 = x0.re, b0 = x0.im, a1 = x1.re, b1 = x1.im;
-    r00 += a0 * a0 + b0 * b0;
-    r11 += a1 * a1 + b1 * b1;
-    r01r += a0 * a1 + b0 * b1;   // x0 conj(x1)
-    r01i += b0 * a1 - a0 * b1;
+  for (int e = threadIdx.x; e < tot; e += 256) {
+    const cplx<T>* p0 = th + (long long)a * 2 * w + 2 * r;
+    const cplx<T> x0 = p0[0], y0 = p0[1], x1 = p0[w], y1 = p0[w + 1];
+    const double a0 = x0.re, b0 = x0.im, a1 = x1.re, b1 = x1.im;
+    const double c0 = y0.re, d0 = y0.im, c1 = y1.re, d1 = y1.im;
+    r00 += (a0 * a0 + b0 * b0) + (c0 * c0 + d0 * d0);
+    r11 += (a1 * a1 + b1 * b1) + (c1 * c1 + d1 * d1);
+    r01r += (a0 * a1 + b0 * b1) + (c0 * c1 + d0 * d1);   // x0 conj(x1)
+    r01i += (b0 * a1 - a0 * b1) + (d0 * c1 - c0 * d1);
+    a += da;
+    r += dr;
+    if (r >= w2) {
+      r -= w2;
+      ++a;
+    }
   }
   double v[4] = {r00, r11, r01r, r01i};
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;

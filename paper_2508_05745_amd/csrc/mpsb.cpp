@@ -1733,7 +1733,7 @@ int unravel_opt(int batch, const double* rho_q, const double* kraus, int n_k, co
 
 int unravel_cost(int batch, const void* theta_, int chi_l, int chi_r, int prec, const double* kraus,
                  const double* params, const double* u_ref, int kind, double* f_out, double* rho_out, void* stream) {
-  if (batch < 0 || chi_l < 1 || chi_r < 1) return fail(MPSB_EINVAL, "bad sizes");
+  if (batch < 0 || chi_l < 1 || chi_r < 1 || (long long)chi_l * chi_r > (1LL << 26)) return fail(MPSB_EINVAL, "bad sizes");
   if (prec != MPSB_FP32_BULK && prec != MPSB_FP64) return fail(MPSB_EINVAL, "bad precision");
   if (kind != 0 && kind != 1) return fail(MPSB_EINVAL, "kind must be 0 or 1");
   if (batch == 0) return MPSB_OK;
