@@ -234,6 +234,27 @@ int sample_kraus(mpsb_handle h, const int32_t* qubit, int channel, int unravel_m
  * that it does not collide with the POSIX truncate(2) declaration.) */
 int mps_truncate(mpsb_handle h, int chi, double* discarded);
 
+/* Global layering (Sec. "Details of MPS-based trajectory sampling", the first of its two
+ * layerings, Trunc^(n-1) o N^n o U^(n/2)): the layer's gates and noise events with no
+ * truncation below the bond capacities, then every bond truncated to chi by mps_truncate's
+ * left-to-right sweep (discarded [n_traj] FP64 or NULL: its summed discarded weight).  The
+ * intermediate state is exact when the batch's chi is at least 2 chi (a gate can double the
+ * bond it acts on); with a smaller capacity apply_layer's own truncation applies first.
+ * Uniform batches only (MPSB_ENOTSUP otherwise); runs without graphs. */
+int apply_layer_global(mpsb_handle h, int layer, int chi, double* discarded);
+
+/* Output distribution sampling from the trajectories (Lemma "Output distribution sampling
+ * from trajectory sampling": sampling each trajectory's Born distribution samples the
+ * mixture): n_samples computational-basis bitstrings per trajectory, drawn site by site from
+ * the conditional probabilities (the centre is moved to site 0, the rest being
+ * right-orthonormal, so p(s_k = s | drawn prefix) is ||v A_k^s||^2 normalised, v the prefix's
+ * normalised left vector; the products in the state's precision, the probabilities in FP64).
+ * The draw of site k of sample i of trajectory t is the counter uniform of `seed` keyed by
+ * (traj_offset + t, i, k), the layout of the branch keys; s_k = 0 if u < p_0 / (p_0 + p_1).
+ * bits [n_traj][n_samples][n] uint8 device (0 or 1).  1 <= n_samples <= min(65535, 2 chi)
+ * (MPSB_EINVAL otherwise); uniform batches only (MPSB_ENOTSUP). */
+int mps_sample_bitstrings(mpsb_handle h, int n_samples, uint64_t seed, uint8_t* bits);
+
 /* Host-only validation of a circuit for n_traj trajectories of widths width[] (host
  * array): the checks of mps_batch_set_circuit, without a handle or a device. */
 int mps_circuit_validate(int n_traj, const int32_t* width, const mpsb_circuit* c);

@@ -159,6 +159,68 @@ def trajectory(circuit, chi: int, traj: int, seed: int, mode=_unr.MODE_OPTIMAL,
     return m, eps
 
 
+def truncate_sweep(m: MPS, chi: int):
+    """Truncation of every bond to chi by a left-to-right sweep (the approximation
+    subprocedure applied to all bonds): with the centre at site k, the SVD of the centre
+    reshaped (2 d_k) x d_(k+1) keeps its top-chi singular values, renormalised, and moves the
+    centre to k + 1.  Returns the list of discarded weights (one per bond)."""
+    m.move_centre(0)
+    eps = []
+    for k in range(m.n - 1):
+        a = m.t[k]
+        s_, dl, dr = a.shape
+        u_, s, vh = np.linalg.svd(a.reshape(s_ * dl, dr), full_matrices=False)
+        tot = float(np.sum(s ** 2))
+        d = min(chi, s.size)
+        kept = float(np.sum(s[:d] ** 2))
+        eps.append((tot - kept) / tot if tot > 0 else 0.0)
+        s = s[:d] / np.sqrt(kept)
+        m.t[k] = u_[:, :d].reshape(s_, dl, d)
+        m.t[k + 1] = np.einsum("kb,sbc->skc", s[:, None] * vh[:d], m.t[k + 1])
+        m.centre = k + 1
+    m.move_centre(0)
+    return eps
+
+
+def trajectory_global(circuit, chi: int, traj: int, seed: int, mode=_unr.MODE_OPTIMAL,
+                      fixed_u=None, layers=None, record=None, replay=None):
+    """Global layering (Sec. "Details of MPS-based trajectory sampling"): every layer applies
+    its gates and its noise with no truncation (the bond dimension of the acted bonds may
+    reach twice its value), then truncates all bonds to chi with one sweep.  Returns (MPS,
+    discarded weights per layer)."""
+    m = MPS(circuit.n)
+    eps = []
+    for l in range(circuit.depth if layers is None else layers):
+        trajectory(circuit, 1 << 30, traj, seed, mode, fixed_u, record=record, layer_range=[l], m=m,
+                   replay=replay)
+        eps.append(truncate_sweep(m, chi))
+    return m, eps
+
+
+def born_sample(m: MPS, n_samples: int, seed: int, traj: int):
+    """Bitstrings drawn from the Born distribution |<x|psi>|^2 of the MPS (Lemma on output
+    distribution sampling: sampling each trajectory samples the mixture), site by site from
+    the conditional probabilities: with the centre at site 0 the rest is right-orthonormal, so
+    after outcomes s_0..s_(k-1) with the left vector v, p(s_k = s) is proportional to
+    ||v A_k^s||^2.  The uniform of site k of sample i is the counter draw keyed by (traj,
+    i, k) of `seed`; s_k = 0 when u < p_0 / (p_0 + p_1).  Returns (bits [n_samples][n],
+    probability of each drawn bitstring)."""
+    m.move_centre(0)
+    bits = np.zeros((n_samples, m.n), dtype=np.uint8)
+    probs = np.ones(n_samples)
+    for i in range(n_samples):
+        v = np.ones(1, dtype=np.complex128)
+        for k in range(m.n):
+            w = [v @ m.t[k][s] for s in (0, 1)]
+            p = [float(np.vdot(x, x).real) for x in w]
+            u = _rng.uniform(seed, traj, i, k)
+            s = 0 if u < p[0] / (p[0] + p[1]) else 1
+            bits[i, k] = s
+            probs[i] *= p[s] / (p[0] + p[1])
+            v = w[s] / np.sqrt(p[s])
+    return bits, probs
+
+
 def z_expectations(m: MPS):
     """<Z_i>, <Z_i Z_{i+1}> by sweeping the centre left to right."""
     n = m.n

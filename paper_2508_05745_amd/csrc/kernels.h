@@ -92,6 +92,10 @@ hipError_t launch_site_event(const EventArgs& ea, const double* rho1, int q, int
                              double* kops, double* p_out, int* status, hipStream_t st);
 hipError_t launch_site_event_check(const EventArgs& ea, const double* rho1, int slot, const int* forced, int* status,
                                    hipStream_t st);
+// Born sampling: V = 1 for the first site; one site's draw from W = V A_k (see unravel.hip)
+hipError_t born_init(int prec, void* V, long long sV, int S, int n_traj, hipStream_t st);
+hipError_t born_step(int prec, const void* W, long long sW, int S, int dr, void* V, long long sV, uint8_t* bits, int n,
+                     int k, uint64_t seed, long long traj_base, int n_traj, hipStream_t st);
 hipError_t launch_unravel_opt(int batch, const double* rho_q, const double* kraus, int n_k, const int* kraus_id, int r,
                               double* U, double* p, double* eof, hipStream_t st);
 

@@ -1580,6 +1580,39 @@ int sample_kraus(mpsb_handle h, const int32_t* qubit, int channel, int unravel_m
   return idle_step(h, rng_layer, q, false, channel, unravel_mode, d_forced, branch, nullptr, p, true);
 }
 
+int mps_sample_bitstrings(mpsb_handle h, int n_samples, uint64_t seed, uint8_t* bits) {
+  if (!h || !bits) return fail(MPSB_EINVAL, "null argument");
+  if (!h->sub.empty()) return fail(MPSB_ENOTSUP, "mps_sample_bitstrings needs a batch of one width and chi");
+  const Layout& L = h->L;
+  int cmax = 1;
+  for (int c : L.cap) cmax = std::max(cmax, c);
+  if (n_samples < 1 || n_samples > 65535 || n_samples > 2 * cmax)
+    return fail(MPSB_EINVAL, "n_samples must be in 1..min(65535, 2 chi)");
+  const int p = L.prec == MPSB_FP64 ? 1 : 0, T = L.n_traj, S = n_samples;
+  int r = move_centre(h, 0, 0);
+  if (r) return r;
+  // V [S][d_k] (left vectors) in the hop-result region, W [S][2][d_(k+1)] in the theta region
+  char* V = W<char>(h, L.o_tmp);
+  char* Wt = W<char>(h, L.o_x);
+  HIPCHK(born_init(p, V, L.s_tmp, S, T, h->st));
+  for (int k = 0; k < L.n; ++k) {
+    const int a = dl(L, k), b = dr(L, k);
+    HIPCHK(gemm(p, p, false, false, S, 2 * b, a, V, a, L.s_tmp, site_ptr(h, k), 2 * b, L.s_traj, Wt, 2 * b, L.s_x, nullptr,
+                T, h->st));
+    HIPCHK(born_step(p, Wt, L.s_x, S, b, V, L.s_tmp, bits, L.n, k, seed, h->traj_offset, T, h->st));
+  }
+  return MPSB_OK;
+}
+
+int apply_layer_global(mpsb_handle h, int layer, int chi, double* discarded) {
+  if (!h) return fail(MPSB_EINVAL, "null handle");
+  if (!h->sub.empty()) return fail(MPSB_ENOTSUP, "global layering needs a batch of one width and chi");
+  if (chi < 1 || chi > h->L.chi) return fail(MPSB_EINVAL, "chi must be in 1..batch chi");
+  int r = apply_layer_replay(h, layer, nullptr, nullptr, nullptr, nullptr, nullptr);
+  if (r) return r;
+  return mps_truncate(h, chi, discarded);
+}
+
 int mps_truncate(mpsb_handle h, int chi, double* discarded) {
   if (!h) return fail(MPSB_EINVAL, "null handle");
   if (!h->sub.empty()) return fail(MPSB_ENOTSUP, "mps_truncate needs a batch of one width and chi");

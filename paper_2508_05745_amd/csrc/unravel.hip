@@ -725,6 +725,61 @@ hipError_t launch_unravel_opt(int batch, const double* rho_q, const double* krau
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ Born sampling
+// Sampling of computational-basis outcomes from each trajectory's state, site by site, with
+// the centre at site 0 (the rest right-orthonormal): W = V A_k holds, for every sample, the
+// left vector of its drawn prefix times the site tensor, [S][s][b] per trajectory; the
+// conditional probability of s_k = s is ||W_s||^2 / (||W_0||^2 + ||W_1||^2) (FP64 sums in
+// index order); the draw is the counter uniform keyed by (trajectory, sample, site) of the
+// sampling seed; V <- W_s / ||W_s||.  One thread per (trajectory, sample).
+template <typename T>
+__global__ void k_born_init(cplx<T>* V, long long sV, int S, int n_traj) {
+  const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (g >= (long long)n_traj * S) return;
+  V[(g / S) * sV + g % S] = cplx<T>{(T)1, (T)0};
+}
+
+template <typename T>
+__global__ void k_born_step(const cplx<T>* __restrict__ W, long long sW, int S, int dr, cplx<T>* __restrict__ V,
+                            long long sV, uint8_t* __restrict__ bits, int n, int k, uint64_t seed, long long traj_base,
+                            int n_traj) {
+  const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (g >= (long long)n_traj * S) return;
+  const long long t = g / S;
+  const int i = (int)(g % S);
+  const cplx<T>* w = W + t * sW + (long long)i * 2 * dr;
+  double p0 = 0.0, p1 = 0.0;
+  for (int b = 0; b < dr; ++b) p0 += (double)w[b].re * w[b].re + (double)w[b].im * w[b].im;
+  for (int b = 0; b < dr; ++b) p1 += (double)w[dr + b].re * w[dr + b].re + (double)w[dr + b].im * w[dr + b].im;
+  const double tot = p0 + p1;
+  const double u = event_uniform(seed, (uint32_t)(traj_base + t), (uint32_t)i, (uint32_t)k);
+  const int s = (tot > 0.0 && !(u < p0 / tot)) ? 1 : 0;
+  const double ps = s ? p1 : p0;
+  const double sc = ps > 0.0 ? 1.0 / sqrt(ps) : 0.0;
+  bits[g * n + k] = (uint8_t)s;
+  cplx<T>* v = V + t * sV + (long long)i * dr;
+  for (int b = 0; b < dr; ++b) v[b] = cplx<T>{(T)(sc * w[s * dr + b].re), (T)(sc * w[s * dr + b].im)};
+}
+
+hipError_t born_init(int prec, void* V, long long sV, int S, int n_traj, hipStream_t st) {
+  const int nb = (int)(((long long)n_traj * S + 255) / 256);
+  if (prec == 0) hipLaunchKernelGGL(k_born_init<float>, dim3(nb), dim3(256), 0, st, (c32*)V, sV, S, n_traj);
+  else hipLaunchKernelGGL(k_born_init<double>, dim3(nb), dim3(256), 0, st, (c64d*)V, sV, S, n_traj);
+  return hipGetLastError();
+}
+
+hipError_t born_step(int prec, const void* W, long long sW, int S, int dr, void* V, long long sV, uint8_t* bits, int n,
+                     int k, uint64_t seed, long long traj_base, int n_traj, hipStream_t st) {
+  const int nb = (int)(((long long)n_traj * S + 255) / 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_born_step<float>, dim3(nb), dim3(256), 0, st, (const c32*)W, sW, S, dr, (c32*)V, sV, bits, n, k,
+                       seed, traj_base, n_traj);
+  else
+    hipLaunchKernelGGL(k_born_step<double>, dim3(nb), dim3(256), 0, st, (const c64d*)W, sW, S, dr, (c64d*)V, sV, bits,
+                       n, k, seed, traj_base, n_traj);
+  return hipGetLastError();
+}
+
 hipError_t launch_gate_events(const EventArgs& ea, const double* partial, int n_tiles, int q, int has_s, int has_t,
                               double* kops, int* status, hipStream_t st) {
   hipLaunchKernelGGL(k_gate_events, dim3((ea.n_traj + EV_SPREAD - 1) / EV_SPREAD), dim3(64), 0, st, ea, partial, n_tiles, q, has_s, has_t,

@@ -62,6 +62,8 @@ def lib():
         L.apply_layer_replay.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.sample_kraus.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
         L.mps_truncate.argtypes = [vp, i32, vp]
+        L.apply_layer_global.argtypes = [vp, i32, i32, vp]
+        L.mps_sample_bitstrings.argtypes = [vp, i32, u64, vp]
         L.expect.argtypes = [vp, vp, vp, vp]
         L.mps_batch_sync.argtypes = [vp]
         L.mps_batch_destroy.argtypes = [vp]
@@ -236,6 +238,18 @@ class Batch:
 
     def truncate(self, chi: int, discarded=None):
         _check(lib().mps_truncate(self.h, chi, _ptr(discarded)))
+
+    def apply_layer_global(self, layer: int, chi: int, discarded=None):
+        """Global layering: the layer without truncation below the capacities, then every
+        bond truncated to chi (create the batch with capacity >= 2 chi)."""
+        _check(lib().apply_layer_global(self.h, layer, chi, _ptr(discarded)))
+
+    def sample_bitstrings(self, n_samples: int, seed: int):
+        """uint8 CUDA tensor [n_traj][n_samples][n] of Born samples of every trajectory."""
+        import torch
+        bits = torch.empty((self.n_traj, n_samples, self.n), dtype=torch.uint8, device="cuda")
+        _check(lib().mps_sample_bitstrings(self.h, n_samples, ctypes.c_uint64(seed), _ptr(bits)))
+        return bits
 
     def expect(self, per_traj: bool = True):
         """(mean, m2, per_traj) of <Z_i> (n) then <Z_i Z_i+1> (n-1), float64 CUDA tensors.

@@ -132,3 +132,72 @@ def test_trajectory_average_matches_density_matrix():
     se = vals.std(0, ddof=1) / np.sqrt(len(vals)) + 1e-12
     z = np.abs(mean - np.concatenate([zi_ex, zz_ex])) / se
     assert z.max() < 4.5
+
+
+def test_born_sample_probabilities_are_the_born_rule():
+    """The sampler's probability of each drawn bitstring (the product of its conditional
+    probabilities) equals |<x|psi>|^2 of the dense state, and 20000 draws follow the Born
+    distribution (chi^2 over the 64 outcomes)."""
+    from oracle import mps as omps
+    c = I.brickwork(6, 5, seed=61, channel=I.depolarizing(0.05))
+    m, _ = omps.trajectory(c, 8, 3, 17)
+    psi = m.to_vector()
+    bits, probs = omps.born_sample(m, 20000, 99, 3)
+    idx = (bits.astype(np.int64) * (1 << np.arange(5, -1, -1))).sum(1)   # qubit 0 most significant
+    born = np.abs(psi) ** 2
+    assert np.abs(probs - born[idx]).max() < 1e-12
+    counts = np.bincount(idx, minlength=64)
+    exp = born * len(idx)
+    keep = exp > 5
+    chi2 = float(((counts[keep] - exp[keep]) ** 2 / exp[keep]).sum())
+    assert chi2 < keep.sum() + 6 * np.sqrt(2 * keep.sum()), chi2
+
+
+def test_born_samples_of_trajectories_follow_the_mixed_state():
+    """Lemma on output distribution sampling: one Born sample from each of 3000 trajectories
+    follows <x|rho|x> of the exact noisy state (orthogonal unravelling, 4 qubits)."""
+    from oracle import mps as omps
+    c = I.brickwork(4, 4, seed=62, channel=I.amplitude_damping(0.3))
+    rho = dm.run(c)
+    counts = np.zeros(16)
+    T = 3000
+    for t in range(T):
+        m, _ = omps.trajectory(c, 4, t, 18, mode=0)
+        b, _ = omps.born_sample(m, 1, 5, t)
+        counts[int((b[0].astype(np.int64) * (1 << np.arange(3, -1, -1))).sum())] += 1
+    exp = np.real(np.diag(rho)) * T
+    keep = exp > 5
+    chi2 = float(((counts[keep] - exp[keep]) ** 2 / exp[keep]).sum())
+    assert chi2 < keep.sum() + 6 * np.sqrt(2 * keep.sum()), chi2
+
+
+def test_global_layering_without_truncation_equals_statevector():
+    """(A state-independent unravelling: the optimal mixing is not unique, so rounding-level
+    differences of the two representations could pick different optimal branches.)"""
+    from oracle import mps as omps
+    c = I.brickwork(6, 5, seed=63, channel=I.depolarizing(0.1))
+    for t in range(4):
+        m, eps = omps.trajectory_global(c, 8, t, 19, mode=0)
+        psi = sv.trajectory(c, t, 19, mode=0)
+        assert abs(abs(np.vdot(m.to_vector(), psi)) - 1.0) < 1e-12
+        assert max(max(e) for e in eps) < 1e-14
+
+
+def test_truncate_sweep_keeps_the_top_schmidt_values_of_the_first_cut():
+    """The sweep's first bond sees the untruncated state: its kept values are the top-chi
+    Schmidt values of the dense state at that cut, and its discarded weight their complement;
+    afterwards every bond is at most chi and the state has norm 1."""
+    from oracle import mps as omps
+    c = I.brickwork(8, 6, seed=64, channel=I.depolarizing(0.02))
+    m, _ = omps.trajectory(c, 16, 0, 20)
+    psi = m.to_vector()
+    s = np.linalg.svd(psi.reshape(2, -1), compute_uv=False)
+    s2 = np.linalg.svd(psi.reshape(4, -1), compute_uv=False)
+    eps = omps.truncate_sweep(m, 1)
+    assert abs(eps[0] - s[1] ** 2 / np.sum(s ** 2)) < 1e-13
+    assert max(m.bond_dims()) <= 1
+    assert abs(np.linalg.norm(m.to_vector()) - 1.0) < 1e-13
+    m2, _ = omps.trajectory(c, 16, 0, 20)
+    eps2 = omps.truncate_sweep(m2, 3)
+    assert eps2[0] == 0.0 or abs(eps2[0]) < 1e-15       # the first cut has rank <= 2
+    assert abs(eps2[1] - np.sum(s2[3:] ** 2) / np.sum(s2 ** 2)) < 1e-12
