@@ -113,3 +113,76 @@ def grad_fd(rho_q, kraus, params, u_ref, kind, h=1e-4):
         g[k] = (cost_params(rho_q, kraus, params + e, u_ref, kind)
                 - cost_params(rho_q, kraus, params - e, u_ref, kind)) / (2 * h)
     return g
+
+
+# --------------------------------------------------------------------- internal-bond cost
+#
+# The other reading of "the expected two-site entanglement": the entanglement across the
+# two-site block's internal bond (a, s) : (t, b) after the noise event on site s.  Branch j
+# of theta is theta_j = (K'_j on s) theta with weight p_j = ||theta_j||^2; its bond entropy is
+# taken from the Gram matrix Gamma_j = theta_j theta_j^dag over (a, s):
+#
+#   f_lin^B(U) = sum_j p_j (1 - Tr Gamma_j^2 / p_j^2),   f_R2^B(U) = sum_j p_j (-log2 Tr Gamma_j^2 / p_j^2)
+#
+# computed here from the definition (branch tensors and their Gram matrices).
+
+
+def bond_cost(theta: np.ndarray, kraus: np.ndarray, u: np.ndarray, kind: int) -> float:
+    t = theta.astype(np.complex128)
+    t = t / np.linalg.norm(t)
+    kp = np.einsum("ji,iab->jab", u, pad_kraus(kraus))
+    cl, cr = t.shape[0], t.shape[3]
+    f = 0.0
+    for k in kp:
+        tj = np.einsum("xs,astb->axtb", k, t).reshape(2 * cl, 2 * cr)
+        g = tj @ tj.conj().T
+        p = float(np.trace(g).real)
+        if p <= P_TINY:
+            continue
+        pur = float(np.trace(g @ g).real)
+        if kind == KIND_LINEAR:
+            f += p - pur / p
+        else:
+            f += -p * np.log2(pur / (p * p))
+    return f
+
+
+def bond_cost_params(theta, kraus, params, u_ref, kind) -> float:
+    return bond_cost(theta, kraus, unitary(params, u_ref), kind)
+
+
+def bond_grad_torch(theta: np.ndarray, kraus: np.ndarray, params: np.ndarray, u_ref: np.ndarray, kind: int):
+    """(f^B, df^B/dparams) by torch CPU autograd in complex128 on the definition."""
+    import torch
+    th = torch.tensor(params, dtype=torch.float64, requires_grad=True)
+    gen = torch.tensor(generators())
+    h = torch.einsum("k,kab->ab", th.to(torch.complex128), gen)
+    u = torch.linalg.matrix_exp(1j * h) @ torch.tensor(u_ref)
+    kp = torch.einsum("ji,iab->jab", u, torch.tensor(pad_kraus(kraus)))
+    t = torch.tensor(theta.astype(np.complex128))
+    t = t / torch.linalg.vector_norm(t)
+    cl, cr = t.shape[0], t.shape[3]
+    f = torch.zeros((), dtype=torch.float64)
+    for j in range(4):
+        tj = torch.einsum("xs,astb->axtb", kp[j], t).reshape(2 * cl, 2 * cr)
+        g = tj @ tj.conj().T
+        p = torch.real(torch.trace(g))
+        if float(p) <= P_TINY:
+            continue
+        pur = torch.real(torch.trace(g @ g))
+        if kind == KIND_LINEAR:
+            f = f + p - pur / p
+        else:
+            f = f - p * torch.log2(pur / (p * p))
+    f.backward()
+    return float(f), th.grad.numpy().copy()
+
+
+def bond_grad_fd(theta, kraus, params, u_ref, kind, h=1e-4):
+    g = np.zeros(16)
+    for k in range(16):
+        e = np.zeros(16)
+        e[k] = h
+        g[k] = (bond_cost_params(theta, kraus, params + e, u_ref, kind)
+                - bond_cost_params(theta, kraus, params - e, u_ref, kind)) / (2 * h)
+    return g

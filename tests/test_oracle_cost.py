@@ -105,3 +105,43 @@ def test_renyi2_cost_special_values():
             uu = I.haar_unitary(rng, 4)
             assert abs(CO.cost(pure, kk, uu, CO.KIND_RENYI2)) < 1e-13
             assert abs(CO.cost(pure, kk, uu, CO.KIND_LINEAR)) < 1e-13
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_bond_cost_equals_qubit_cost_for_two_qubits(kind):
+    """With chi_L = chi_R = 1 the block is two qubits, its internal bond separates the noisy
+    qubit from the rest of the block, and the internal-bond cost equals the noisy-qubit cost."""
+    rng = np.random.default_rng(31 + kind)
+    for _ in range(10):
+        th = I.random_two_site_states(1, 1, 1, seed=int(rng.integers(1 << 30)), dtype=np.complex128)[0]
+        k = I.depolarizing(0.2) if _ % 2 else I.amplitude_damping(0.3)
+        u = I.haar_unitaries(1, seed=int(rng.integers(1 << 30)))[0]
+        rho = CO.rho_from_theta(th)
+        assert abs(CO.bond_cost(th, k, u, kind) - CO.cost(rho / np.trace(rho).real, k, u, kind)) < 1e-13
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_bond_cost_gradient_finite_differences(kind):
+    rng = np.random.default_rng(41 + kind)
+    th = I.random_two_site_states(1, 3, 4, seed=5, dtype=np.complex128)[0]
+    k = I.depolarizing(0.1)
+    for _ in range(3):
+        params = rng.normal(0, 0.3, 16)
+        u_ref = I.haar_unitaries(1, seed=int(rng.integers(1 << 30)))[0]
+        f, g = CO.bond_grad_torch(th, k, params, u_ref, kind)
+        assert abs(f - CO.bond_cost_params(th, k, params, u_ref, kind)) < 1e-13
+        gfd = CO.bond_grad_fd(th, k, params, u_ref, kind)
+        assert np.linalg.norm(g - gfd) < 1e-7 * max(1.0, np.linalg.norm(g))
+
+
+def test_bond_cost_of_a_product_block_is_the_qubit_cost_of_its_left_part():
+    """theta = phi (x) chi with phi on (a, s) and chi on (t, b): every branch stays a product
+    across the internal bond after noise on s, so the bond's entanglement is that of (a : s)
+    inside phi; with chi_L = 1 (phi a single qubit) that is zero for every mixing."""
+    rng = np.random.default_rng(7)
+    phi = rng.standard_normal((1, 2)) + 1j * rng.standard_normal((1, 2))
+    chi = rng.standard_normal((2, 3)) + 1j * rng.standard_normal((2, 3))
+    th = np.einsum("as,tb->astb", phi, chi)
+    u = I.haar_unitaries(1, seed=3)[0]
+    for kind in (0, 1):
+        assert abs(CO.bond_cost(th, I.depolarizing(0.3), u, kind)) < 1e-14
