@@ -368,36 +368,45 @@ def bench_cost(args):
     """Unravelling cost and adjoint on 65536 independent two-site states (chi 64 on each side,
     complex Gaussian, normalised, c64, drawn on the device), 4-Kraus depolarizing p = 0.02,
     mixing parameters N(0, 0.1^2) around Haar reference unitaries: one step = the linear
-    cost of every state (the reduction of its reduced qubit state, HBM-bound: 16 chi^2 bytes
-    read per state) and its adjoint gradient."""
+    cost of every state and its adjoint gradient.  Between the noisy qubit and the rest of the
+    block (default) the forward is the reduction of the reduced qubit state, HBM-bound (16 chi^2
+    bytes read per state); across the block's internal bond (--bond) it is the block Gram
+    matrix, matrix-core bound (4 (2 chi)^3 FP64 flops of a Hermitian product per state)."""
     import torch
 
     from paper_2508_05745_amd import inputs as I
     from paper_2508_05745_amd import mpsb as M
-    B, chi = 65536, 64
+    bond = bool(getattr(args, "bond", False))
+    B, chi = (16384, 64) if bond else (65536, 64)
     th = I.random_two_site_states_torch(B, chi, chi, seed=4004)
     pp = torch.as_tensor(I.random_mixing_params(B, seed=4005)).cuda()
     uu = torch.as_tensor(I.haar_unitaries(B, seed=4006)).cuda()
     k = I.depolarizing(0.02)
+
+    def fwd_bwd():
+        if bond:
+            f, rho, nm, k4 = M.unravel_cost_bond(th, k, pp, uu, 0)
+            return lambda: M.unravel_cost_bond_grad(rho, nm, k4, pp, uu, 0, None)
+        f, rho, k4 = M.unravel_cost(th, k, pp, uu, 0)
+        return lambda: M.unravel_cost_grad(rho, k4, pp, uu, 0, None)
+
     W, K = max(args.warmup, 1), args.steps
     for _ in range(W):
-        f, rho, k4 = M.unravel_cost(th, k, pp, uu, 0)
-        M.unravel_cost_grad(rho, k4, pp, uu, 0, None)
+        fwd_bwd()()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(K)]
     t0 = time.perf_counter()
     for e0, e1, e2 in ev:
         e0.record()
-        f, rho, k4 = M.unravel_cost(th, k, pp, uu, 0)
+        bwd_call = fwd_bwd()
         e1.record()
-        M.unravel_cost_grad(rho, k4, pp, uu, 0, None)
+        bwd_call()
         e2.record()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     fwd = sum(a.elapsed_time(b) for a, b, _ in ev) / K
     bwd = sum(b.elapsed_time(c) for _, b, c in ev) / K
-    nbytes = B * chi * 4 * chi * 8.0
     cpu = None
     if not args.no_cpu:
         from oracle import cost as CO
@@ -406,21 +415,36 @@ def bench_cost(args):
         params, uref = pp.cpu().numpy(), uu.cpu().numpy()
         t1, n = time.perf_counter(), 0
         while n < len(sample) and (time.perf_counter() - t1 < 15.0 or n == 0):
-            r = CO.rho_from_theta(ths[n])
-            CO.grad_torch(r / np.trace(r).real, k, params[sample[n]], uref[sample[n]], 0)
+            if bond:
+                CO.bond_grad_torch(ths[n], k, params[sample[n]], uref[sample[n]], 0)
+            else:
+                r = CO.rho_from_theta(ths[n])
+                CO.grad_torch(r / np.trace(r).real, k, params[sample[n]], uref[sample[n]], 0)
             n += 1
+        how = "branch Gram matrices + torch-CPU complex128 autograd" if bond else "NumPy reduction + torch-CPU complex128 autograd"
         cpu = dict(value=n / (time.perf_counter() - t1), unit="states/s", cores=_cores(), kind="oracle", cpu=cpu_model(),
-                   sample=f"{n} states of the batch (NumPy reduction + torch-CPU complex128 autograd)")
+                   sample=f"{n} states of the batch ({how})")
+    if bond:
+        flops = B * 4.0 * (2 * chi) ** 3
+        roof = dict(bound="mfma", kernel="k_bond_moments<float> + k_cost_eval (forward)",
+                    achieved=flops / (fwd * 1e-3) / 1e12, peak=PEAK["fp64"] / 1e12, unit="TFLOP/s",
+                    frac=flops / (fwd * 1e-3) / PEAK["fp64"], traffic=None, flops_per_launch=flops, avg_launch_ms=fwd)
+        metric, wl = "two-site states/s (internal-bond unravelling cost + adjoint)", f"bondcost-{B}states-chi{chi}-dep0.02"
+        dtype = "c64 states, fp64 Gram (matrix cores) / cost / adjoint"
+    else:
+        nbytes = B * chi * 4 * chi * 8.0
+        roof = dict(bound="hbm", kernel="k_cost_rho<float> + k_cost_eval (forward)", achieved=nbytes / (fwd * 1e-3) / 1e9,
+                    peak=PEAK["hbm"] / 1e9, unit="GB/s", frac=nbytes / (fwd * 1e-3) / PEAK["hbm"], traffic=None,
+                    bytes_per_launch=nbytes, avg_launch_ms=fwd)
+        metric, wl = "two-site states/s (unravelling cost + adjoint)", f"cost-{B}states-chi{chi}-dep0.02"
+        dtype = "c64 states, fp64 reduction / cost / adjoint"
     line = {
-        "metric": "two-site states/s (unravelling cost + adjoint)", "value": B * K / dt, "unit": "states/s",
+        "metric": metric, "value": B * K / dt, "unit": "states/s",
         "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * dt / K, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "c64 states, fp64 reduction / cost / adjoint",
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic (seeded complex-Gaussian states, depolarizing p=0.02)",
-        "config": {"workload": f"cost-{B}states-chi{chi}-dep0.02", "n_states": B, "chi": chi},
-        "roofline": dict(bound="hbm", kernel="k_cost_rho<float> + k_cost_eval (forward)", achieved=nbytes / (fwd * 1e-3) / 1e9,
-                         peak=PEAK["hbm"] / 1e9, unit="GB/s", frac=nbytes / (fwd * 1e-3) / PEAK["hbm"], traffic=None,
-                         bytes_per_launch=nbytes, avg_launch_ms=fwd),
-        "backward_ms": bwd, "cpu_baseline": cpu,
+        "config": {"workload": wl, "n_states": B, "chi": chi},
+        "roofline": roof, "backward_ms": bwd, "cpu_baseline": cpu,
     }
     print(json.dumps(line))
 
@@ -511,6 +535,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mixed", action="store_true", help="the mixed-batch workload instead of the headline one")
     ap.add_argument("--cost", action="store_true", help="the unravelling cost / adjoint workload (65536 states)")
+    ap.add_argument("--bond", action="store_true",
+                    help="with --cost: the cost across the block's internal bond (16384 states)")
     ap.add_argument("--lindblad", action="store_true", help="the Trotterised Lindbladian workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB elementwise copy kernel 4 times (HBM counter scale)")

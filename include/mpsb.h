@@ -378,6 +378,33 @@ int unravel_cost_grad(int batch, const double* rho_q, const double* kraus,
                       const double* params, const double* u_ref, int kind,
                       const double* grad_f, double* grad_out, void* stream);
 
+/* The same objective taken across the two-site block's internal bond (a, s) : (t, b) instead
+ * of between the noisy qubit and the rest: branch j of the block is theta_j = (K'_j on s)
+ * theta with p_j = ||theta_j||^2 / ||theta||^2, and its bond purity is Tr Gamma_j^2 / p_j^2 with
+ * Gamma_j = theta_j theta_j^dag over (a, s) (Sec. "Locally entanglement-optimal unraveling",
+ * eq. target_optimal_unitary, applied to the bond that the truncation acts on; linear or
+ * Renyi-2 entropy as in unravel_cost):
+ *   kind 0: f = sum_j (p_j - Tr Gamma_j^2 / p_j),   kind 1: f = sum_j -p_j log2(Tr Gamma_j^2 / p_j^2)
+ * (branches with p_j <= 1e-300 contribute 0).  The block Gram Gamma = theta theta^dag
+ * (2 chi_l x 2 chi_l, FP64 accumulation on the matrix cores; O(chi_l^2 chi_r) work per state)
+ * is reduced to rho_out [batch][2][2] c128 (the noisy qubit's reduced state) and the moment
+ * matrix n_out [batch][4][4] c128, N[(w,x)][(y,z)] = sum_{a,a'} Gamma[(a,w),(a',x)]
+ * conj(Gamma[(a,y),(a',z)]) / ||theta||^4, from which Tr Gamma_j^2 = sum E[s1][s2] E[s3][s4]
+ * N[(s2,s3)][(s1,s4)] with E = K'_j^dag K'_j.  With chi_l = chi_r = 1 it equals unravel_cost.
+ * Arguments, layouts and errors as in unravel_cost (theta [batch][chi_l][2][2][chi_r], noise on
+ * the first physical index; a zero theta gives NaN).  Device pointers. */
+int unravel_cost_bond(int batch, const void* theta, int chi_l, int chi_r, int prec,
+                      const double* kraus, const double* params, const double* u_ref, int kind,
+                      double* f_out, double* rho_out, double* n_out, void* stream);
+
+/* Adjoint of unravel_cost_bond with respect to the 16 mixing parameters, from the rho_q and
+ * N that it wrote (theta is not re-read): grad_out [batch][16] = grad_f[b] d f_b / d params_b
+ * (grad_f NULL: 1), through U = exp(i H) U_ref (eq. unitarity_kraus); d Tr Gamma_j^2 / d U_ji
+ * = 2 sum (K'_j^dag K_i)[s1][s2] E_j[s3][s4] N[(s2,s3)][(s1,s4)].  Device pointers. */
+int unravel_cost_bond_grad(int batch, const double* rho_q, const double* n_mom,
+                           const double* kraus, const double* params, const double* u_ref,
+                           int kind, const double* grad_f, double* grad_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -167,7 +167,7 @@ def bond_grad_torch(theta: np.ndarray, kraus: np.ndarray, params: np.ndarray, u_
         tj = torch.einsum("xs,astb->axtb", kp[j], t).reshape(2 * cl, 2 * cr)
         g = tj @ tj.conj().T
         p = torch.real(torch.trace(g))
-        if float(p) <= P_TINY:
+        if float(p.detach()) <= P_TINY:
             continue
         pur = torch.real(torch.trace(g @ g))
         if kind == KIND_LINEAR:

@@ -71,6 +71,181 @@ hipError_t cost_rho(int batch, const void* theta, int chi_l, int chi_r, int prec
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ internal-bond moments
+// For the cost taken across the block's internal bond (a, s) : (t, b), the purity of branch j
+// needs the block Gram Gamma[(a,s),(a',s')] = sum_{t,b} theta[a,s,t,b] conj(theta[a',s',t,b])
+// (2 chi_l x 2 chi_l, a contraction over 2 chi_r).  Only its 2 x 2 blocks gamma_{aa'} enter,
+// through the 4 x 4 Hermitian moment matrix
+//   N[(w,x),(y,z)] = sum_{a,a'} gamma_{aa'}[w][x] conj(gamma_{aa'}[y][z]),
+// with Tr Gamma_j^2 = sum E_{s1 s2} E_{s3 s4} N[(s2,s3),(s1,s4)], E_j = K'_j^dag K'_j, and
+// rho_q = sum_a gamma_{aa}.  One workgroup (4 waves) per state; the waves take the 32 x 32
+// tiles (I <= J) of Gamma in turn, each tile a complex product on the FP64 MFMA 16x16x4
+// (operands straight from global memory, two complex values per lane per load); the tile goes
+// through LDS, each lane folds 4 of its 2 x 2 blocks into its moments (tile (J, I) = tile
+// (I, J)^dag is folded in at the same time), and the workgroup reduces the moments in a fixed
+// order (deterministic).
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+__device__ inline v4d_t mfma64(double a, double b, v4d_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+template <typename T>
+__device__ inline void load_pair(const cplx<T>* __restrict__ th, int row, int k, int n, int K, long long ld, cd (&v)[2]) {
+  v[0] = cd{0, 0};
+  v[1] = cd{0, 0};
+  if (row < n && k < K) {            // K is even and k is even: both elements are in the row
+    const cplx<T>* q = th + row * ld + k;
+    const cplx<T> x = q[0], y = q[1];
+    v[0] = cd{(double)x.re, (double)x.im};
+    v[1] = cd{(double)y.re, (double)y.im};
+  }
+}
+
+// acc += g g^dag for the 4-vector g (16 doubles: 4 real diagonal entries, then the 6 entries
+// (0,1) (0,2) (0,3) (1,2) (1,3) (2,3) as re, im)
+__device__ inline void fold(double (&m)[16], const cd (&g)[4]) {
+  for (int i = 0; i < 4; ++i) m[i] += norm2(g[i]);
+  int o = 4;
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j) {
+      const cd z = g[i] * conj(g[j]);
+      m[o] += z.re;
+      m[o + 1] += z.im;
+      o += 2;
+    }
+}
+
+constexpr int BT = 32, BS = BT + 1;   // tile edge; LDS row stride (doubles)
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_bond_moments(int chi_l, int chi_r, const cplx<T>* __restrict__ theta,
+                                                      double* rho, double* nmom) {
+  __shared__ double tre[4][BT * BS], tim[4][BT * BS];
+  const int n = 2 * chi_l, K = 2 * chi_r;
+  const int nt = (n + BT - 1) / BT, npairs = nt * (nt + 1) / 2;
+  const cplx<T>* th = theta + (long long)blockIdx.x * n * K;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  double m[16], r[4];
+  for (int i = 0; i < 16; ++i) m[i] = 0;
+  for (int i = 0; i < 4; ++i) r[i] = 0;
+  double* sre = tre[wv];
+  double* sim = tim[wv];
+  for (int tp = wv; tp < npairs; tp += 4) {
+    int I = 0, rem = tp;              // tp -> (I, J), I <= J, row-major over the upper triangle
+    while (rem >= nt - I) { rem -= nt - I; ++I; }
+    const int J = I + rem;
+    v4d_t ar[2][2], ai[2][2];
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y) ar[x][y] = ai[x][y] = v4d_t{0, 0, 0, 0};
+    const int rI = BT * I + li, rJ = BT * J + li;
+    cd xa[2][2], xb[2][2], na[2][2], nb[2][2];
+    for (int h = 0; h < 2; ++h) {
+      load_pair(th, rI + 16 * h, 2 * lq, n, K, K, xa[h]);
+      load_pair(th, rJ + 16 * h, 2 * lq, n, K, K, xb[h]);
+    }
+    for (int k0 = 0; k0 < K; k0 += 8) {
+      const int kn = k0 + 8 + 2 * lq;
+      for (int h = 0; h < 2; ++h) {
+        load_pair(th, rI + 16 * h, kn, n, K, K, na[h]);
+        load_pair(th, rJ + 16 * h, kn, n, K, K, nb[h]);
+      }
+      for (int e = 0; e < 2; ++e)
+        for (int x = 0; x < 2; ++x)
+          for (int y = 0; y < 2; ++y) {
+            // Gamma_IJ = X_I X_J^dag: re = Xr Xr^T + Xi Xi^T, im = Xi Xr^T - Xr Xi^T
+            const cd a = xa[x][e], b = xb[y][e];
+            ar[x][y] = mfma64(a.re, b.re, ar[x][y]);
+            ar[x][y] = mfma64(a.im, b.im, ar[x][y]);
+            ai[x][y] = mfma64(a.im, b.re, ai[x][y]);
+            ai[x][y] = mfma64(-a.re, b.im, ai[x][y]);
+          }
+      for (int h = 0; h < 2; ++h)
+        for (int e = 0; e < 2; ++e) {
+          xa[h][e] = na[h][e];
+          xb[h][e] = nb[h][e];
+        }
+    }
+    // D[i][j] of a 16 x 16 product sits in lane j + 16 (i % 4), register i / 4
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y)
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * x + 4 * v + lq, j = 16 * y + li;
+          sre[i * BS + j] = ar[x][y][v];
+          sim[i * BS + j] = ai[x][y][v];
+        }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q = 0; q < 4; ++q) {
+      const int blk = lane + 64 * q, al = blk >> 4, bl = blk & 15;
+      cd g[4];
+      for (int w = 0; w < 2; ++w)
+        for (int x = 0; x < 2; ++x) {
+          const int o = (2 * al + w) * BS + 2 * bl + x;
+          g[2 * w + x] = cd{sre[o], sim[o]};
+        }
+      fold(m, g);
+      if (I != J) {   // block (a', a) = gamma^dag: entries conj(gamma[x][w])
+        const cd gm[4] = {conj(g[0]), conj(g[2]), conj(g[1]), conj(g[3])};
+        fold(m, gm);
+      } else if (al == bl) {
+        r[0] += g[0].re;
+        r[1] += g[3].re;
+        r[2] += g[1].re;
+        r[3] += g[1].im;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // fixed-order reduction: within each wave by shuffles, then the 4 waves in order
+  __shared__ double red[4][20];
+  for (int x = 0; x < 20; ++x) {
+    double s = x < 16 ? m[x] : r[x - 16];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) red[wv][x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 20) {
+    const int x = threadIdx.x;
+    red[0][x] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
+  }
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    // normalised by ||theta||^2 (rho) and ||theta||^4 (N)
+    const double tr = red[0][16] + red[0][17];
+    const double s1 = 1.0 / tr, s2 = s1 * s1;
+    if (threadIdx.x < 8) {
+      const double v[8] = {red[0][16], 0.0, red[0][18], red[0][19], red[0][18], -red[0][19], red[0][17], 0.0};
+      rho[blockIdx.x * 8 + threadIdx.x] = s1 * v[threadIdx.x];
+    }
+    // N[(p),(q)] with p, q in 0..3 (p = 2 w + x, q = 2 y + z), full Hermitian 4 x 4, c128
+    for (int e = threadIdx.x; e < 16; e += 32) {
+      const int p = e >> 2, q = e & 3;
+      double re, im;
+      if (p == q) { re = red[0][p]; im = 0.0; }
+      else {
+        const int lo = p < q ? p : q, hi = p < q ? q : p;
+        const int o = 4 + 2 * (lo * (7 - lo) / 2 + (hi - lo - 1));
+        re = red[0][o];
+        im = p < q ? red[0][o + 1] : -red[0][o + 1];
+      }
+      nmom[blockIdx.x * 32 + 2 * e] = s2 * re;
+      nmom[blockIdx.x * 32 + 2 * e + 1] = s2 * im;
+    }
+  }
+}
+
+hipError_t bond_moments(int batch, const void* theta, int chi_l, int chi_r, int prec, double* rho, double* nmom,
+                        hipStream_t st) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_bond_moments<float>, dim3(batch), dim3(256), 0, st, chi_l, chi_r, (const c32*)theta, rho, nmom);
+  else
+    hipLaunchKernelGGL(k_bond_moments<double>, dim3(batch), dim3(256), 0, st, chi_l, chi_r, (const c64d*)theta, rho,
+                       nmom);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ small complex matrices
 template <int N>
 __device__ void mm(const cd (&a)[N][N], const cd (&b)[N][N], cd (&c)[N][N]) {
@@ -128,11 +303,25 @@ __device__ void generator(int k, cd (&g)[4][4]) {
 
 struct CostState {
   cd U[4][4], Kp[4][2][2], K[4][2][2], rho[2][2], sig[4][2][2];
+  cd N[4][4], E[4][2][2];   // internal-bond cost only
   double p[4], P[4];
 };
 
-__device__ void cost_setup(const double* rho_in, const double* kraus, const double* params, const double* uref,
-                           CostState& cs, cd (&Xh)[4][4]) {
+// Q(A, B) = sum A[s1][s2] B[s3][s4] N[(s2,s3)][(s1,s4)]: Tr Gamma_j^2 = Q(E_j, E_j), symmetric in
+// its two arguments (cyclicity of the trace)
+__device__ inline cd bond_q(const cd (&a)[2][2], const cd (&b)[2][2], const cd (&N)[4][4]) {
+  cd s = {0, 0};
+  for (int s1 = 0; s1 < 2; ++s1)
+    for (int s2 = 0; s2 < 2; ++s2)
+      for (int s3 = 0; s3 < 2; ++s3)
+        for (int s4 = 0; s4 < 2; ++s4) s = s + (a[s1][s2] * b[s3][s4]) * N[2 * s2 + s3][2 * s1 + s4];
+  return s;
+}
+
+// nm == nullptr: the noisy qubit against the rest of the block (P_j = Tr sigma~_j^2); else the
+// block's internal bond, nm the moment matrix N [4][4] c128 (P_j = Q(E_j, E_j)).
+__device__ void cost_setup(const double* rho_in, const double* nm, const double* kraus, const double* params,
+                           const double* uref, CostState& cs, cd (&Xh)[4][4]) {
   for (int x = 0; x < 4; ++x) cs.rho[x >> 1][x & 1] = cd{rho_in[2 * x], rho_in[2 * x + 1]};
   // normalise rho (the reduction of an unnormalised theta is allowed)
   double tr = cs.rho[0][0].re + cs.rho[1][1].re;
@@ -185,18 +374,30 @@ __device__ void cost_setup(const double* rho_in, const double* kraus, const doub
       for (int b = 0; b < 2; ++b) P += (cs.sig[j][a][b] * cs.sig[j][b][a]).re;
     cs.P[j] = P;
   }
+  if (nm) {
+    for (int x = 0; x < 16; ++x) cs.N[x >> 2][x & 3] = cd{nm[2 * x], nm[2 * x + 1]};
+    for (int j = 0; j < 4; ++j) {
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          cd e = {0, 0};
+          for (int x = 0; x < 2; ++x) cfma(e, conj(cs.Kp[j][x][a]), cs.Kp[j][x][b]);
+          cs.E[j][a][b] = e;
+        }
+      cs.P[j] = bond_q(cs.E[j], cs.E[j], cs.N).re;
+    }
+  }
 }
 
 constexpr double P_TINY = 1e-300;
 constexpr double LN2 = 0.69314718055994530942;
 
-__global__ void k_cost_eval(int batch, const double* rho, const double* kraus, const double* params, const double* uref,
-                            int kind, double* f) {
+__global__ void k_cost_eval(int batch, const double* rho, const double* nm, const double* kraus, const double* params,
+                            const double* uref, int kind, double* f) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
   CostState cs;
   cd Xh[4][4];
-  cost_setup(rho + b * 8, kraus, params + b * 16, uref + b * 32, cs, Xh);
+  cost_setup(rho + b * 8, nm ? nm + b * 32 : nullptr, kraus, params + b * 16, uref + b * 32, cs, Xh);
   double acc = 0;
   for (int j = 0; j < 4; ++j) {
     double p = cs.p[j], P = cs.P[j];
@@ -207,13 +408,13 @@ __global__ void k_cost_eval(int batch, const double* rho, const double* kraus, c
   f[b] = acc;
 }
 
-__global__ void k_cost_grad(int batch, const double* rho, const double* kraus, const double* params, const double* uref,
-                            int kind, const double* grad_f, double* grad) {
+__global__ void k_cost_grad(int batch, const double* rho, const double* nm, const double* kraus, const double* params,
+                            const double* uref, int kind, const double* grad_f, double* grad) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
   CostState cs;
   cd Xh[4][4];
-  cost_setup(rho + b * 8, kraus, params + b * 16, uref + b * 32, cs, Xh);
+  cost_setup(rho + b * 8, nm ? nm + b * 32 : nullptr, kraus, params + b * 16, uref + b * 32, cs, Xh);
   // G[j][i] = g_p Tr(K_i rho K'_j^dag) + g_P 2 Tr(sigma~_j K_i rho K'_j^dag)
   cd G[4][4];
   for (int j = 0; j < 4; ++j) {
@@ -239,9 +440,20 @@ __global__ void k_cost_grad(int batch, const double* rho, const double* kraus, c
           B[a][c] = s;
         }
       cd trB = B[0][0] + B[1][1];
-      cd trSB = {0, 0};
-      for (int a = 0; a < 2; ++a)
-        for (int m = 0; m < 2; ++m) trSB = trSB + cs.sig[j][a][m] * B[m][a];
+      cd trSB = {0, 0};   // d P_j / d U_ji / 2
+      if (nm) {
+        cd D[2][2];       // K'_j^dag K_i
+        for (int a = 0; a < 2; ++a)
+          for (int c = 0; c < 2; ++c) {
+            cd e = {0, 0};
+            for (int x = 0; x < 2; ++x) cfma(e, conj(cs.Kp[j][x][a]), cs.K[i][x][c]);
+            D[a][c] = e;
+          }
+        trSB = bond_q(D, cs.E[j], cs.N);
+      } else {
+        for (int a = 0; a < 2; ++a)
+          for (int m = 0; m < 2; ++m) trSB = trSB + cs.sig[j][a][m] * B[m][a];
+      }
       G[j][i] = gp * trB + (2.0 * gP) * trSB;
     }
   }
@@ -277,15 +489,16 @@ __global__ void k_cost_grad(int batch, const double* rho, const double* kraus, c
   }
 }
 
-hipError_t cost_eval(int batch, const double* rho, const double* kraus, const double* params, const double* u_ref,
-                     int kind, double* f, hipStream_t st) {
-  hipLaunchKernelGGL(k_cost_eval, dim3((batch + 63) / 64), dim3(64), 0, st, batch, rho, kraus, params, u_ref, kind, f);
+hipError_t cost_eval(int batch, const double* rho, const double* nm, const double* kraus, const double* params,
+                     const double* u_ref, int kind, double* f, hipStream_t st) {
+  hipLaunchKernelGGL(k_cost_eval, dim3((batch + 63) / 64), dim3(64), 0, st, batch, rho, nm, kraus, params, u_ref, kind,
+                     f);
   return hipGetLastError();
 }
 
-hipError_t cost_grad(int batch, const double* rho, const double* kraus, const double* params, const double* u_ref,
-                     int kind, const double* grad_f, double* grad, hipStream_t st) {
-  hipLaunchKernelGGL(k_cost_grad, dim3((batch + 63) / 64), dim3(64), 0, st, batch, rho, kraus, params, u_ref, kind,
+hipError_t cost_grad(int batch, const double* rho, const double* nm, const double* kraus, const double* params,
+                     const double* u_ref, int kind, const double* grad_f, double* grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_cost_grad, dim3((batch + 63) / 64), dim3(64), 0, st, batch, rho, nm, kraus, params, u_ref, kind,
                      grad_f, grad);
   return hipGetLastError();
 }

@@ -159,9 +159,11 @@ hipError_t obs_reduce(const double* per_traj, int n_obs, int n_traj, double* mea
 
 // unravelling cost
 hipError_t cost_rho(int batch, const void* theta, int chi_l, int chi_r, int prec, double* rho, hipStream_t st);
-hipError_t cost_eval(int batch, const double* rho, const double* kraus, const double* params, const double* u_ref,
-                     int kind, double* f, hipStream_t st);
-hipError_t cost_grad(int batch, const double* rho, const double* kraus, const double* params, const double* u_ref,
-                     int kind, const double* grad_f, double* grad, hipStream_t st);
+hipError_t cost_eval(int batch, const double* rho, const double* nm, const double* kraus, const double* params,
+                     const double* u_ref, int kind, double* f, hipStream_t st);
+hipError_t cost_grad(int batch, const double* rho, const double* nm, const double* kraus, const double* params,
+                     const double* u_ref, int kind, const double* grad_f, double* grad, hipStream_t st);
+hipError_t bond_moments(int batch, const void* theta, int chi_l, int chi_r, int prec, double* rho, double* nmom,
+                        hipStream_t st);
 
 }  // namespace mpsb

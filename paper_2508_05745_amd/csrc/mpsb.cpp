@@ -1773,7 +1773,7 @@ int unravel_cost(int batch, const void* theta_, int chi_l, int chi_r, int prec, 
   if (!theta_ || !kraus || !params || !u_ref || !f_out || !rho_out) return fail(MPSB_EINVAL, "null pointer");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(cost_rho(batch, theta_, chi_l, chi_r, prec == MPSB_FP64 ? 1 : 0, rho_out, st));
-  HIPCHK(cost_eval(batch, rho_out, kraus, params, u_ref, kind, f_out, st));
+  HIPCHK(cost_eval(batch, rho_out, nullptr, kraus, params, u_ref, kind, f_out, st));
   return MPSB_OK;
 }
 
@@ -1783,7 +1783,33 @@ int unravel_cost_grad(int batch, const double* rho_q, const double* kraus, const
   if (kind != 0 && kind != 1) return fail(MPSB_EINVAL, "kind must be 0 or 1");
   if (batch == 0) return MPSB_OK;
   if (!rho_q || !kraus || !params || !u_ref || !grad_out) return fail(MPSB_EINVAL, "null pointer");
-  HIPCHK(cost_grad(batch, rho_q, kraus, params, u_ref, kind, grad_f, grad_out, (hipStream_t)stream));
+  HIPCHK(cost_grad(batch, rho_q, nullptr, kraus, params, u_ref, kind, grad_f, grad_out, (hipStream_t)stream));
+  return MPSB_OK;
+}
+
+int unravel_cost_bond(int batch, const void* theta_, int chi_l, int chi_r, int prec, const double* kraus,
+                      const double* params, const double* u_ref, int kind, double* f_out, double* rho_out,
+                      double* n_out, void* stream) {
+  if (batch < 0 || batch > (1 << 30) || chi_l < 1 || chi_r < 1 || (long long)chi_l * chi_r > (1LL << 26))
+    return fail(MPSB_EINVAL, "bad sizes");
+  if (prec != MPSB_FP32_BULK && prec != MPSB_FP64) return fail(MPSB_EINVAL, "bad precision");
+  if (kind != 0 && kind != 1) return fail(MPSB_EINVAL, "kind must be 0 or 1");
+  if (batch == 0) return MPSB_OK;
+  if (!theta_ || !kraus || !params || !u_ref || !f_out || !rho_out || !n_out) return fail(MPSB_EINVAL, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(bond_moments(batch, theta_, chi_l, chi_r, prec == MPSB_FP64 ? 1 : 0, rho_out, n_out, st));
+  HIPCHK(cost_eval(batch, rho_out, n_out, kraus, params, u_ref, kind, f_out, st));
+  return MPSB_OK;
+}
+
+int unravel_cost_bond_grad(int batch, const double* rho_q, const double* n_mom, const double* kraus,
+                           const double* params, const double* u_ref, int kind, const double* grad_f,
+                           double* grad_out, void* stream) {
+  if (batch < 0) return fail(MPSB_EINVAL, "bad sizes");
+  if (kind != 0 && kind != 1) return fail(MPSB_EINVAL, "kind must be 0 or 1");
+  if (batch == 0) return MPSB_OK;
+  if (!rho_q || !n_mom || !kraus || !params || !u_ref || !grad_out) return fail(MPSB_EINVAL, "null pointer");
+  HIPCHK(cost_grad(batch, rho_q, n_mom, kraus, params, u_ref, kind, grad_f, grad_out, (hipStream_t)stream));
   return MPSB_OK;
 }
 

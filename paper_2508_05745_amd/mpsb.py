@@ -74,6 +74,8 @@ def lib():
         L.mps_jump_channel.argtypes = [i32, vp, vp, ctypes.c_double, vp, vp]
         L.unravel_cost.argtypes = [i32, vp, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp]
         L.unravel_cost_grad.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, vp]
+        L.unravel_cost_bond.argtypes = [i32, vp, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp]
+        L.unravel_cost_bond_grad.argtypes = [i32, vp, vp, vp, vp, vp, i32, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -392,35 +394,74 @@ def unravel_cost_grad(rho, kraus4, params, u_ref, kind: int, grad_f):
     return g
 
 
-def _autograd_function():
+def unravel_cost_bond(theta, kraus, params, u_ref, kind: int = 0):
+    """The cost across the block's internal bond.  theta: [B, chi_l, 2, 2, chi_r] complex64 /
+    complex128 CUDA tensor.  Returns (f [B], rho_q [B,2,2], N [B,4,4], kraus padded to 4)."""
+    import torch
+    prec = FP32_BULK if theta.dtype == torch.complex64 else FP64
+    B, cl, cr = theta.shape[0], theta.shape[1], theta.shape[4]
+    k = torch.zeros((4, 2, 2), dtype=torch.complex128, device="cuda")
+    kk = torch.as_tensor(kraus).to(device="cuda", dtype=torch.complex128)
+    k[: kk.shape[0]] = kk
+    f = torch.empty((B,), dtype=torch.float64, device="cuda")
+    rho = torch.empty((B, 2, 2), dtype=torch.complex128, device="cuda")
+    nm = torch.empty((B, 4, 4), dtype=torch.complex128, device="cuda")
+    params = params.contiguous()
+    u_ref = u_ref.to(torch.complex128).contiguous()
+    _check(lib().unravel_cost_bond(B, _ptr(theta.contiguous()), cl, cr, prec, _ptr(k), _ptr(params),
+                                   _ptr(u_ref), kind, _ptr(f), _ptr(rho), _ptr(nm), _stream()))
+    return f, rho, nm, k
+
+
+def unravel_cost_bond_grad(rho, nm, kraus4, params, u_ref, kind: int, grad_f):
+    import torch
+    B = rho.shape[0]
+    g = torch.empty((B, 16), dtype=torch.float64, device="cuda")
+    _check(lib().unravel_cost_bond_grad(B, _ptr(rho.contiguous()), _ptr(nm.contiguous()),
+                                        _ptr(kraus4.contiguous()), _ptr(params.contiguous()),
+                                        _ptr(u_ref.contiguous()), kind,
+                                        _ptr(None if grad_f is None else grad_f.contiguous()),
+                                        _ptr(g), _stream()))
+    return g
+
+
+def _autograd_function(bond: bool):
     import torch
 
     class UnravelCost(torch.autograd.Function):
         """f(params) = expected linear (kind 0) / Renyi-2 (kind 1) entropy of the unravelling
-        of `kraus` on the reduced states of `theta`; differentiable w.r.t. params only (the
-        adjoint is the library's unravel_cost_grad, theta is not re-read)."""
+        of `kraus` on the states `theta` (between the noisy qubit and the rest of the block,
+        or across the block's internal bond); differentiable w.r.t. params only (the adjoint
+        is the library's unravel_cost_grad / unravel_cost_bond_grad, theta is not re-read)."""
 
         @staticmethod
         def forward(ctx, params, theta, kraus, u_ref, kind):
-            f, rho, k4 = unravel_cost(theta, kraus, params, u_ref, kind)
-            ctx.save_for_backward(rho, k4, params, u_ref.to(torch.complex128))
+            if bond:
+                f, rho, nm, k4 = unravel_cost_bond(theta, kraus, params, u_ref, kind)
+            else:
+                f, rho, k4 = unravel_cost(theta, kraus, params, u_ref, kind)
+                nm = rho
+            ctx.save_for_backward(rho, nm, k4, params, u_ref.to(torch.complex128))
             ctx.kind = kind
             return f
 
         @staticmethod
         def backward(ctx, grad_f):
-            rho, k4, params, u_ref = ctx.saved_tensors
-            g = unravel_cost_grad(rho, k4, params, u_ref, ctx.kind, grad_f.to(torch.float64))
+            rho, nm, k4, params, u_ref = ctx.saved_tensors
+            gf = grad_f.to(torch.float64)
+            if bond:
+                g = unravel_cost_bond_grad(rho, nm, k4, params, u_ref, ctx.kind, gf)
+            else:
+                g = unravel_cost_grad(rho, k4, params, u_ref, ctx.kind, gf)
             return g, None, None, None, None
 
     return UnravelCost
 
 
-_UC = None
+_UC = {}
 
 
-def UnravelCost():
-    global _UC
-    if _UC is None:
-        _UC = _autograd_function()
-    return _UC
+def UnravelCost(bond: bool = False):
+    if bond not in _UC:
+        _UC[bond] = _autograd_function(bond)
+    return _UC[bond]

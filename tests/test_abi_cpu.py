@@ -150,6 +150,14 @@ def test_unravel_entry_points_validate_on_the_host():
     assert lib.unravel_cost(4, one, 8, 8, 0, one, one, one, 2, one, one, None) == M.EINVAL
     assert lib.unravel_cost_grad(4, one, one, one, one, 5, None, one, None) == M.EINVAL
     assert lib.unravel_cost_grad(4, None, one, one, one, 0, None, one, None) == M.EINVAL
+    assert lib.unravel_cost_bond(4, one, 8, 8, 3, one, one, one, 0, one, one, one, None) == M.EINVAL
+    assert lib.unravel_cost_bond(4, one, 8, 8, 1, one, one, one, 2, one, one, one, None) == M.EINVAL
+    assert lib.unravel_cost_bond(4, one, 0, 8, 1, one, one, one, 0, one, one, one, None) == M.EINVAL
+    assert lib.unravel_cost_bond(4, one, 1 << 14, 1 << 13, 1, one, one, one, 0, one, one, one, None) == M.EINVAL
+    assert lib.unravel_cost_bond(4, one, 8, 8, 1, one, one, one, 0, one, one, None, None) == M.EINVAL
+    assert lib.unravel_cost_bond(0, None, 8, 8, 1, None, None, None, 0, None, None, None, None) == M.OK
+    assert lib.unravel_cost_bond_grad(4, one, None, one, one, one, 0, None, one, None) == M.EINVAL
+    assert lib.unravel_cost_bond_grad(4, one, one, one, one, one, 3, None, one, None) == M.EINVAL
 
 
 def test_static_batch_rejects_oversized_and_mixed_plans():
