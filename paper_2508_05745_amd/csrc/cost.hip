@@ -78,25 +78,37 @@ hipError_t cost_rho(int batch, const void* theta, int chi_l, int chi_r, int prec
 // through the 4 x 4 Hermitian moment matrix
 //   N[(w,x),(y,z)] = sum_{a,a'} gamma_{aa'}[w][x] conj(gamma_{aa'}[y][z]),
 // with Tr Gamma_j^2 = sum E_{s1 s2} E_{s3 s4} N[(s2,s3),(s1,s4)], E_j = K'_j^dag K'_j, and
-// rho_q = sum_a gamma_{aa}.  One workgroup (4 waves) per state; the waves take the 32 x 32
-// tiles (I <= J) of Gamma in turn, each tile a complex product on the FP64 MFMA 16x16x4
-// (operands straight from global memory, two complex values per lane per load); the tile goes
-// through LDS, each lane folds 4 of its 2 x 2 blocks into its moments (tile (J, I) = tile
-// (I, J)^dag is folded in at the same time), and the workgroup reduces the moments in a fixed
-// order (deterministic).
+// rho_q = sum_a gamma_{aa}.  One workgroup per state, of one wave (large batches) or four (the
+// tile pairs dealt to the waves longest first); a wave takes its 32 x 32 tiles (I <= J) of Gamma
+// one at a time, each a complex product on the FP64 MFMA 16x16x4 with operands straight from
+// global memory (two complex values per lane per load, the next chunk in flight during the
+// current one's products); the tile goes through LDS, each lane folds 4 of its 2 x 2 blocks into
+// its moments (tile (J, I) = tile (I, J)^dag is accounted for by symmetry), and the workgroup
+// reduces the moments in a fixed order (deterministic).
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 __device__ inline v4d_t mfma64(double a, double b, v4d_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
+// Raw elements (row, k), (row, k + 1) (K and k even: both in the row), or element (0, 0) when
+// outside the block (masked to zero where used).  The load is unconditional so that it can be
+// in flight while other products run.
 template <typename T>
-__device__ inline void load_pair(const cplx<T>* __restrict__ th, int row, int k, int n, int K, long long ld, cd (&v)[2]) {
-  v[0] = cd{0, 0};
-  v[1] = cd{0, 0};
-  if (row < n && k < K) {            // K is even and k is even: both elements are in the row
-    const cplx<T>* q = th + row * ld + k;
-    const cplx<T> x = q[0], y = q[1];
-    v[0] = cd{(double)x.re, (double)x.im};
-    v[1] = cd{(double)y.re, (double)y.im};
-  }
+struct RawPair {
+  cplx<T> x, y;
+  bool ok;
+};
+template <typename T>
+__device__ inline RawPair<T> load_pair(const cplx<T>* __restrict__ th, int row, int k, int n, int K, long long ld) {
+  RawPair<T> r;
+  r.ok = row < n && k < K;
+  const cplx<T>* q = th + (r.ok ? row * ld + k : 0);
+  r.x = q[0];
+  r.y = q[1];
+  return r;
+}
+template <typename T>
+__device__ inline cd elem(const RawPair<T>& r, int e) {
+  const cplx<T> v = e ? r.y : r.x;
+  return r.ok ? cd{(double)v.re, (double)v.im} : cd{0, 0};
 }
 
 // acc += g g^dag for the 4-vector g (16 doubles: 4 real diagonal entries, then the 6 entries
@@ -115,79 +127,142 @@ __device__ inline void fold(double (&m)[16], const cd (&g)[4]) {
 
 constexpr int BT = 32, BS = BT + 1;   // tile edge; LDS row stride (doubles)
 
-template <typename T>
-__global__ __launch_bounds__(256, 2) void k_bond_moments(int chi_l, int chi_r, const cplx<T>* __restrict__ theta,
-                                                      double* rho, double* nmom) {
-  __shared__ double tre[4][BT * BS], tim[4][BT * BS];
+// Owner wave of tile pair tp of an nt x nt tile grid among NW waves: the pairs are dealt
+// longest first (off-diagonal tiles cost 4 sub-products, diagonal ones 3) to the least loaded
+// wave, lowest index on ties -- the same deterministic schedule in every wave.
+template <int NW>
+__device__ inline int tile_owner(int tp, int nt) {
+  static_assert(NW == 1 || NW == 4, "one or four waves");
+  if (NW == 1) return 0;
+  int l0 = 0, l1 = 0, l2 = 0, l3 = 0;               // loads of the four waves
+  for (int pass = 0; pass < 2; ++pass)              // off-diagonal pairs, then diagonal ones
+    for (int I = 0; I < nt; ++I)
+      for (int J = I; J < nt; ++J) {
+        const bool diag = I == J;
+        if (diag != (pass == 1)) continue;
+        int best = 0, lb = l0;
+        if (l1 < lb) { best = 1; lb = l1; }
+        if (l2 < lb) { best = 2; lb = l2; }
+        if (l3 < lb) { best = 3; lb = l3; }
+        const int c = diag ? 3 : 4;
+        l0 += best == 0 ? c : 0;
+        l1 += best == 1 ? c : 0;
+        l2 += best == 2 ? c : 0;
+        l3 += best == 3 ? c : 0;
+        if (I * nt - I * (I - 1) / 2 + (J - I) == tp) return best;   // row-major index of (I, J)
+      }
+  return 0;
+}
+
+// The moments are kept as two packed sums (4 real diagonal entries, then 6 complex off-diagonal
+// ones): blocks whose mirror block (a', a) = gamma^dag is not in a computed tile go to mb, the
+// others to ms; the mirrors' share is P conj(mb) P^T (P swapping entries 1 and 2), added once at
+// the end.  G3: the complex product with three real products per step (T1 = Xr Yr^T, T2 = Xi Yi^T,
+// T3 = (Xr + Xi)(Yr - Yi)^T; re = T1 + T2, im = T3 - T1 + T2) instead of four.
+template <typename T, int NW, bool G3>
+__global__ __launch_bounds__(64 * NW, 2) void k_bond_moments(int chi_l, int chi_r,
+                                                                   const cplx<T>* __restrict__ theta, double* rho,
+                                                                   double* nmom) {
+  __shared__ double tre[NW][BT * BS], tim[NW][BT * BS];
   const int n = 2 * chi_l, K = 2 * chi_r;
   const int nt = (n + BT - 1) / BT, npairs = nt * (nt + 1) / 2;
   const cplx<T>* th = theta + (long long)blockIdx.x * n * K;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
-  double m[16], r[4];
-  for (int i = 0; i < 16; ++i) m[i] = 0;
+  double ms[16], mb[16], r[4];
+  for (int i = 0; i < 16; ++i) ms[i] = mb[i] = 0;
   for (int i = 0; i < 4; ++i) r[i] = 0;
   double* sre = tre[wv];
   double* sim = tim[wv];
-  for (int tp = wv; tp < npairs; tp += 4) {
+  for (int tp = 0; tp < npairs; ++tp) {
+    if (tile_owner<NW>(tp, nt) != wv) continue;
     int I = 0, rem = tp;              // tp -> (I, J), I <= J, row-major over the upper triangle
     while (rem >= nt - I) { rem -= nt - I; ++I; }
     const int J = I + rem;
-    v4d_t ar[2][2], ai[2][2];
+    const bool diag = I == J;         // sub-product (1, 0) of a diagonal tile is (0, 1)^dag: skipped
+    v4d_t ar[2][2], ai[2][2], a3[2][2];
     for (int x = 0; x < 2; ++x)
-      for (int y = 0; y < 2; ++y) ar[x][y] = ai[x][y] = v4d_t{0, 0, 0, 0};
+      for (int y = 0; y < 2; ++y) ar[x][y] = ai[x][y] = a3[x][y] = v4d_t{0, 0, 0, 0};
     const int rI = BT * I + li, rJ = BT * J + li;
-    cd xa[2][2], xb[2][2], na[2][2], nb[2][2];
-    for (int h = 0; h < 2; ++h) {
-      load_pair(th, rI + 16 * h, 2 * lq, n, K, K, xa[h]);
-      load_pair(th, rJ + 16 * h, 2 * lq, n, K, K, xb[h]);
-    }
-    for (int k0 = 0; k0 < K; k0 += 8) {
-      const int kn = k0 + 8 + 2 * lq;
+    // two register buffers of the operands: chunk c (8 complex columns) is loaded into buffer
+    // c % 2 while the products of chunk c - 1 run
+    RawPair<T> ra[2][2], rb[2][2];
+    auto load = [&](int buf, int k) {
       for (int h = 0; h < 2; ++h) {
-        load_pair(th, rI + 16 * h, kn, n, K, K, na[h]);
-        load_pair(th, rJ + 16 * h, kn, n, K, K, nb[h]);
+        ra[buf][h] = load_pair(th, rI + 16 * h, k + 2 * lq, n, K, K);
+        rb[buf][h] = load_pair(th, rJ + 16 * h, k + 2 * lq, n, K, K);
       }
-      for (int e = 0; e < 2; ++e)
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y) {
-            // Gamma_IJ = X_I X_J^dag: re = Xr Xr^T + Xi Xi^T, im = Xi Xr^T - Xr Xi^T
-            const cd a = xa[x][e], b = xb[y][e];
-            ar[x][y] = mfma64(a.re, b.re, ar[x][y]);
-            ar[x][y] = mfma64(a.im, b.im, ar[x][y]);
-            ai[x][y] = mfma64(a.im, b.re, ai[x][y]);
-            ai[x][y] = mfma64(-a.re, b.im, ai[x][y]);
-          }
-      for (int h = 0; h < 2; ++h)
-        for (int e = 0; e < 2; ++e) {
-          xa[h][e] = na[h][e];
-          xb[h][e] = nb[h][e];
+    };
+    auto products = [&](int buf) {
+      for (int e = 0; e < 2; ++e) {
+        cd a[2], b[2];
+        for (int h = 0; h < 2; ++h) {
+          a[h] = elem(ra[buf][h], e);
+          b[h] = elem(rb[buf][h], e);
         }
+        if (G3) {
+          for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y) {
+              if (diag && x == 1 && y == 0) continue;
+              ar[x][y] = mfma64(a[x].re, b[y].re, ar[x][y]);
+              ai[x][y] = mfma64(a[x].im, b[y].im, ai[x][y]);
+              a3[x][y] = mfma64(a[x].re + a[x].im, b[y].re - b[y].im, a3[x][y]);
+            }
+        } else {
+          // Gamma_IJ = X_I X_J^dag: re = Xr Xr^T + Xi Xi^T, im = Xi Xr^T - Xr Xi^T
+          for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y) {
+              if (diag && x == 1 && y == 0) continue;
+              ar[x][y] = mfma64(a[x].re, b[y].re, ar[x][y]);
+              ai[x][y] = mfma64(a[x].im, b[y].re, ai[x][y]);
+            }
+          for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y) {
+              if (diag && x == 1 && y == 0) continue;
+              ar[x][y] = mfma64(a[x].im, b[y].im, ar[x][y]);
+              ai[x][y] = mfma64(-a[x].re, b[y].im, ai[x][y]);
+            }
+        }
+      }
+    };
+    load(0, 0);
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      load(1, k0 + 8);
+      products(0);
+      load(0, k0 + 16);
+      products(1);
     }
     // D[i][j] of a 16 x 16 product sits in lane j + 16 (i % 4), register i / 4
     for (int x = 0; x < 2; ++x)
       for (int y = 0; y < 2; ++y)
         for (int v = 0; v < 4; ++v) {
           const int i = 16 * x + 4 * v + lq, j = 16 * y + li;
-          sre[i * BS + j] = ar[x][y][v];
-          sim[i * BS + j] = ai[x][y][v];
+          if (G3) {
+            sre[i * BS + j] = ar[x][y][v] + ai[x][y][v];
+            sim[i * BS + j] = (a3[x][y][v] - ar[x][y][v]) + ai[x][y][v];
+          } else {
+            sre[i * BS + j] = ar[x][y][v];
+            sim[i * BS + j] = ai[x][y][v];
+          }
         }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int q = 0; q < 4; ++q) {
       const int blk = lane + 64 * q, al = blk >> 4, bl = blk & 15;
+      // in a diagonal tile the lower-left quadrant (not computed) is the mirror of the
+      // upper-right one
+      const bool lower_left = diag && al >= 8 && bl < 8;
+      const bool mirrored = !diag || (al < 8 && bl >= 8);
       cd g[4];
       for (int w = 0; w < 2; ++w)
         for (int x = 0; x < 2; ++x) {
           const int o = (2 * al + w) * BS + 2 * bl + x;
-          g[2 * w + x] = cd{sre[o], sim[o]};
+          g[2 * w + x] = lower_left ? cd{0, 0} : cd{sre[o], sim[o]};
         }
-      fold(m, g);
-      if (I != J) {   // block (a', a) = gamma^dag: entries conj(gamma[x][w])
-        const cd gm[4] = {conj(g[0]), conj(g[2]), conj(g[1]), conj(g[3])};
-        fold(m, gm);
-      } else if (al == bl) {
+      if (mirrored) fold(mb, g);
+      else fold(ms, g);
+      if (diag && al == bl) {
         r[0] += g[0].re;
         r[1] += g[3].re;
         r[2] += g[1].re;
@@ -198,51 +273,69 @@ __global__ __launch_bounds__(256, 2) void k_bond_moments(int chi_l, int chi_r, c
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  // fixed-order reduction: within each wave by shuffles, then the 4 waves in order
-  __shared__ double red[4][20];
-  for (int x = 0; x < 20; ++x) {
-    double s = x < 16 ? m[x] : r[x - 16];
+  // fixed-order reduction: within each wave by shuffles, then the waves in order
+  __shared__ double red[NW][36];
+  for (int x = 0; x < 36; ++x) {
+    double s = x < 16 ? ms[x] : (x < 32 ? mb[x - 16] : r[x - 32]);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if (lane == 0) red[wv][x] = s;
   }
   __syncthreads();
-  if (threadIdx.x < 20) {
+  if (threadIdx.x < 36) {
     const int x = threadIdx.x;
-    red[0][x] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
+    double s = red[0][x];
+    for (int w = 1; w < NW; ++w) s += red[w][x];
+    red[0][x] = s;
   }
   __syncthreads();
   if (threadIdx.x < 32) {
+    const double* Ms = red[0];
+    const double* Mb = red[0] + 16;
+    const double* R = red[0] + 32;
     // normalised by ||theta||^2 (rho) and ||theta||^4 (N)
-    const double tr = red[0][16] + red[0][17];
+    const double tr = R[0] + R[1];
     const double s1 = 1.0 / tr, s2 = s1 * s1;
     if (threadIdx.x < 8) {
-      const double v[8] = {red[0][16], 0.0, red[0][18], red[0][19], red[0][18], -red[0][19], red[0][17], 0.0};
+      const double v[8] = {R[0], 0.0, R[2], R[3], R[2], -R[3], R[1], 0.0};
       rho[blockIdx.x * 8 + threadIdx.x] = s1 * v[threadIdx.x];
     }
+    // entry (p, q) of a packed Hermitian 4 x 4
+    auto entry = [](const double* M, int p, int q) {
+      if (p == q) return cd{M[p], 0.0};
+      const int lo = p < q ? p : q, hi = p < q ? q : p;
+      const int o = 4 + 2 * (lo * (7 - lo) / 2 + (hi - lo - 1));
+      return cd{M[o], p < q ? M[o + 1] : -M[o + 1]};
+    };
     // N[(p),(q)] with p, q in 0..3 (p = 2 w + x, q = 2 y + z), full Hermitian 4 x 4, c128
     for (int e = threadIdx.x; e < 16; e += 32) {
       const int p = e >> 2, q = e & 3;
-      double re, im;
-      if (p == q) { re = red[0][p]; im = 0.0; }
-      else {
-        const int lo = p < q ? p : q, hi = p < q ? q : p;
-        const int o = 4 + 2 * (lo * (7 - lo) / 2 + (hi - lo - 1));
-        re = red[0][o];
-        im = p < q ? red[0][o + 1] : -red[0][o + 1];
-      }
-      nmom[blockIdx.x * 32 + 2 * e] = s2 * re;
-      nmom[blockIdx.x * 32 + 2 * e + 1] = s2 * im;
+      const int pp = p == 1 ? 2 : (p == 2 ? 1 : p), qq = q == 1 ? 2 : (q == 2 ? 1 : q);
+      const cd v = entry(Ms, p, q) + entry(Mb, p, q) + conj(entry(Mb, pp, qq));
+      nmom[blockIdx.x * 32 + 2 * e] = s2 * v.re;
+      nmom[blockIdx.x * 32 + 2 * e + 1] = s2 * v.im;
     }
   }
 }
 
 hipError_t bond_moments(int batch, const void* theta, int chi_l, int chi_r, int prec, double* rho, double* nmom,
                         hipStream_t st) {
-  if (prec == 0)
-    hipLaunchKernelGGL(k_bond_moments<float>, dim3(batch), dim3(256), 0, st, chi_l, chi_r, (const c32*)theta, rho, nmom);
-  else
-    hipLaunchKernelGGL(k_bond_moments<double>, dim3(batch), dim3(256), 0, st, chi_l, chi_r, (const c64d*)theta, rho,
-                       nmom);
+  // one wave per state once the batch fills the chip (two waves per SIMD), four otherwise; the
+  // three-product complex step (measured 5-20% faster than four products)
+  if (batch >= 2048) {
+    if (prec == 0)
+      hipLaunchKernelGGL((k_bond_moments<float, 1, true>), dim3(batch), dim3(64), 0, st, chi_l, chi_r,
+                         (const c32*)theta, rho, nmom);
+    else
+      hipLaunchKernelGGL((k_bond_moments<double, 1, true>), dim3(batch), dim3(64), 0, st, chi_l, chi_r,
+                         (const c64d*)theta, rho, nmom);
+  } else {
+    if (prec == 0)
+      hipLaunchKernelGGL((k_bond_moments<float, 4, true>), dim3(batch), dim3(256), 0, st, chi_l, chi_r,
+                         (const c32*)theta, rho, nmom);
+    else
+      hipLaunchKernelGGL((k_bond_moments<double, 4, true>), dim3(batch), dim3(256), 0, st, chi_l, chi_r,
+                         (const c64d*)theta, rho, nmom);
+  }
   return hipGetLastError();
 }
 

@@ -100,3 +100,28 @@ def test_bond_autograd_function_and_edges():
     assert out[0].numel() == 0
     with pytest.raises(M.MpsbError):
         M.unravel_cost_bond(torch.as_tensor(th).cuda(), k, pp.detach(), torch.as_tensor(uref).cuda(), 2)
+
+
+def test_bond_cost_at_full_size_sampled():
+    """The benchmark's workload and launch shape (16384 chi-64 c64 states drawn on the device,
+    one wave per state): sampled states against the oracle, and every cost finite and within
+    the bounds of a linear entropy across a cut of dimension 2 chi: 0 <= f <= 1 - 1 / (2 chi)."""
+    import torch
+
+    from paper_2508_05745_amd import mpsb as M
+    B, chi = 16384, 64
+    th = I.random_two_site_states_torch(B, chi, chi, seed=4004)
+    pp = torch.as_tensor(I.random_mixing_params(B, seed=4005)).cuda()
+    uu = torch.as_tensor(I.haar_unitaries(B, seed=4006)).cuda()
+    k = I.depolarizing(0.02)
+    f, rho, nm, k4 = M.unravel_cost_bond(th, k, pp, uu, 0)
+    g = M.unravel_cost_bond_grad(rho, nm, k4, pp, uu, 0, None)
+    fc = f.cpu().numpy()
+    assert np.isfinite(fc).all() and fc.min() >= 0.0 and fc.max() <= 1.0 - 1.0 / (2 * chi)
+    sample = [0, 1, 4095, 8191, 12000, B - 1]
+    ths = th[torch.as_tensor(sample).cuda()].cpu().numpy()
+    gc, params, uref = g.cpu().numpy(), pp.cpu().numpy(), uu.cpu().numpy()
+    for i, b in enumerate(sample):
+        f_ref, g_ref = CO.bond_grad_torch(ths[i], k, params[b], uref[b], 0)
+        assert abs(fc[b] - f_ref) < 1e-12
+        assert np.linalg.norm(gc[b] - g_ref) <= 1e-10 * max(1.0, np.linalg.norm(g_ref))
