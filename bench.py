@@ -335,7 +335,9 @@ def bench_mixed(args):
     n_traj = args.traj if args.traj != 2048 else 16384
     wl = I.config_mixed(n_traj)
     mc = wl.circuit
-    W, K = args.warmup, args.steps
+    W = args.warmup
+    # default: every layer after the warm-up ones (the deepest trajectory's depth)
+    K = mc.depth - W if args.steps == 40 else min(args.steps, mc.depth - W)
     b = M.Batch(mc.n_traj, mc.widths, mc.chis, M.FP32_BULK, wl.seed)
     b.set_circuit(mc, M.OPTIMAL)
     for l in range(W):
@@ -345,13 +347,19 @@ def bench_mixed(args):
     t0 = time.perf_counter()
     for l in range(W, W + K):
         b.apply_layer(l)
-    torch.cuda.synchronize()
+        # a layer of the whole batch takes seconds: waiting for it costs the next layer's
+        # launch latency only, and lets the run report its progress
+        torch.cuda.synchronize()
+        print(f"#   layer {l}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     dt = time.perf_counter() - t0
     b.sync()
     gates = int((mc.gate_id[:, W:W + K, :] >= 0).sum())
     per_chi = {int(c): int((mc.gate_id[mc.chis == c][:, W:W + K, :] >= 0).sum()) for c in np.unique(mc.chis)}
     n_sub = int(np.count_nonzero(np.diff(mc.widths) != 0) + np.count_nonzero(np.diff(mc.chis) != 0) + 1)
     b.close()
+    cpu, oracle_err = None, None
+    if not args.no_cpu:
+        cpu, oracle_err = mixed_oracle_check(wl)
     line = {
         "metric": "trajectory gate-steps/s (mixed batch)", "value": gates / dt, "unit": "trajectory gate-steps/s",
         "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * dt / K, "higher_is_better": True,
@@ -360,8 +368,72 @@ def bench_mixed(args):
         "config": {"workload": wl.name, "n_traj": mc.n_traj, "max_width": mc.n, "max_depth": mc.depth,
                    "sub_batches_upper_bound": n_sub, "timed_layers": [W, W + K - 1],
                    "gate_steps_timed": gates, "gate_steps_per_chi": per_chi},
+        "oracle_error": oracle_err, "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+
+
+def mixed_oracle_check(wl):
+    """Untimed second pass of the whole mixed batch (same seeds, recording every mixing and
+    branch), then the oracle MPS replays one trajectory of each chi class (the middle one of
+    the class, sorted by width) from layer 0: its branches must match, its mixings are checked
+    for completeness and optimality, and its final observables give the trajectory's error."""
+    import torch
+
+    from oracle import mps as omps
+    from oracle import sv as osv
+    from paper_2508_05745_amd import mpsb as M
+    mc = wl.circuit
+    sample = []
+    for chi in np.unique(mc.chis):
+        idx = np.flatnonzero(mc.chis == chi)
+        sample.append(int(idx[len(idx) // 2]))
+    st = torch.as_tensor(sample).cuda()
+    b = M.Batch(mc.n_traj, mc.widths, mc.chis, M.FP32_BULK, wl.seed)
+    b.set_circuit(mc, M.OPTIMAL)
+    T, W = mc.n_traj, mc.n
+    w = torch.zeros((T, W, 4, 4), dtype=torch.complex128, device="cuda")
+    br = torch.zeros((T, W), dtype=torch.int32, device="cuda")
+    ws, brs = [], []
+    for l in range(mc.depth):
+        b.apply_layer(l, branch=br, w_record=w)
+        ws.append(w[st].cpu().numpy())
+        brs.append(br[st].cpu().numpy())
+        if l % 4 == 3:
+            print(f"#   recorded pass: layer {l}", file=sys.stderr, flush=True)
+    _, _, pt = b.expect()
+    pt = pt[st].cpu().numpy()
+    b.sync()
+    b.close()
+    del w, br
+    errs, steps, secs = [], 0, 0.0
+    for i, t in enumerate(sample):
+        c = mc.trajectory_circuit(t)
+        wl_, js = [], []
+        for l in range(c.depth):
+            for kind, q in osv.sweep_ops(c, l):
+                for x in osv.event_qubits(c, l, kind, q):
+                    wl_.append(ws[l][i, x].T.copy())
+                    js.append(int(brs[l][i, x]))
+        rp = osv.Replay(wl_)
+        got = []
+        t0 = time.perf_counter()
+        m, _ = omps.trajectory(c, int(mc.chis[t]), t, wl.seed, mode=3, record=got, replay=rp)
+        secs += time.perf_counter() - t0
+        steps += sum(len(c.pairs(l)) for l in range(c.depth))
+        zi, zz = omps.z_expectations(m)
+        ref = np.concatenate([zi, zz])
+        nobs = 2 * c.n - 1
+        errs.append(dict(traj=t, width=int(c.n), depth=int(c.depth), chi=int(mc.chis[t]),
+                         fp32_bulk_max_abs=float(np.abs(pt[i][:nobs] - ref).max()),
+                         branches_match=js == [r["j"] for r in got], replay_max_eof_gap=float(rp.max_gap),
+                         replay_max_incomplete=float(rp.max_incomplete)))
+        print(f"#   oracle trajectory {t} (chi {mc.chis[t]}, width {c.n}): {secs:.1f} s, "
+              f"max |d<O>| {errs[-1]['fp32_bulk_max_abs']:.1e}", file=sys.stderr, flush=True)
+    base = dict(value=steps / secs, unit="trajectory gate-steps/s", cores=_cores(), kind="oracle", cpu=cpu_model(),
+                sample=f"{len(sample)} trajectories (one per chi class) of an untimed recorded FP32-bulk pass "
+                       f"replayed by the oracle (NumPy/LAPACK complex128) through all their layers")
+    return base, errs
 
 
 def bench_cost(args):
