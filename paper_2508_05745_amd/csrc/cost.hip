@@ -339,66 +339,72 @@ hipError_t bond_moments(int batch, const void* theta, int chi_l, int chi_r, int 
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ small complex matrices
-template <int N>
-__device__ void mm(const cd (&a)[N][N], const cd (&b)[N][N], cd (&c)[N][N]) {
-  for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) {
-      cd s = {0, 0};
-      for (int k = 0; k < N; ++k) cfma(s, a[i][k], b[k][j]);
-      c[i][j] = s;
-    }
+// ------------------------------------------------------------------ 4 x 4 matrices on 16 lanes
+// A state's 4 x 4 complex matrices are spread over a group of 16 lanes: lane g of the group
+// holds entry (g >> 2, g & 3).  Products exchange rows and columns by lane shuffles within the
+// group (no per-lane 4 x 4 or 8 x 8 arrays, which would not fit in registers).  Every lane of a
+// group follows the same control flow (group-uniform loop counts).
+__device__ inline cd gsh(cd x, int src) { return cd{__shfl(x.re, src, 16), __shfl(x.im, src, 16)}; }
+
+__device__ inline cd gmm(cd a, cd b, int g) {   // (A B)[i][j]
+  const int i = g >> 2, j = g & 3;
+  cd s = {0, 0};
+  for (int k = 0; k < 4; ++k) cfma(s, gsh(a, 4 * i + k), gsh(b, 4 * k + j));
+  return s;
 }
 
-// exp(A) by scaling and squaring with a degree-18 Taylor polynomial (||A/2^s||_1 <= 1/4).
-template <int N>
-__device__ void expm(const cd (&a)[N][N], cd (&out)[N][N]) {
-  double nrm = 0;
-  for (int j = 0; j < N; ++j) {
-    double c = 0;
-    for (int i = 0; i < N; ++i) c += sqrt(norm2(a[i][j]));
-    nrm = fmax(nrm, c);
-  }
+// max over the columns of the column sums of v (v >= 0 per entry), in every lane of the group
+__device__ inline double gcolmax(double v) {
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 8, 16);
+  v = fmax(v, __shfl_xor(v, 1, 16));
+  return fmax(v, __shfl_xor(v, 2, 16));
+}
+
+// exp(A) by scaling and squaring with a degree-18 Taylor polynomial (||A / 2^s||_1 <= 1/4)
+__device__ cd gexpm(cd a, int g) {
+  double nrm = gcolmax(sqrt(norm2(a)));
   int s = 0;
   while (nrm > 0.25 && s < 60) { nrm *= 0.5; ++s; }
   const double sc = ldexp(1.0, -s);
-  cd x[N][N], term[N][N], tmp[N][N];
-  for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) {
-      x[i][j] = sc * a[i][j];
-      term[i][j] = (i == j) ? cd{1, 0} : cd{0, 0};
-      out[i][j] = term[i][j];
-    }
+  const cd x = sc * a;
+  const cd one = (g >> 2) == (g & 3) ? cd{1, 0} : cd{0, 0};
+  cd term = one, out = one;
   for (int k = 1; k <= 18; ++k) {
-    mm<N>(term, x, tmp);
+    term = (1.0 / k) * gmm(term, x, g);
+    out = out + term;
+  }
+  for (int r = 0; r < s; ++r) out = gmm(out, out, g);
+  return out;
+}
+
+// Frechet derivative L(A, E) of the exponential: the upper-right block of
+// exp([[A, E], [0, A]]), by the same scaling (the 8 x 8 block's 1-norm) and Taylor degree,
+// kept in its 4 x 4 blocks: term_k = [[T_k, F_k], [0, T_k]] with T_k = T_{k-1} A / k,
+// F_k = (F_{k-1} A + T_{k-1} E) / k, and a squaring maps [[P, Q], [0, P]] to
+// [[P^2, P Q + Q P], [0, P^2]].
+__device__ cd gfrechet(cd a, cd e, int g) {
+  double nrm = gcolmax(sqrt(norm2(a)) + sqrt(norm2(e)));
+  int s = 0;
+  while (nrm > 0.25 && s < 60) { nrm *= 0.5; ++s; }
+  const double sc = ldexp(1.0, -s);
+  const cd x = sc * a, y = sc * e;
+  const cd one = (g >> 2) == (g & 3) ? cd{1, 0} : cd{0, 0};
+  cd T = one, F = {0, 0}, P = one, Q = {0, 0};
+  for (int k = 1; k <= 18; ++k) {
     const double f = 1.0 / k;
-    for (int i = 0; i < N; ++i)
-      for (int j = 0; j < N; ++j) {
-        term[i][j] = f * tmp[i][j];
-        out[i][j] = out[i][j] + term[i][j];
-      }
+    const cd Fn = f * (gmm(F, x, g) + gmm(T, y, g));
+    T = f * gmm(T, x, g);
+    F = Fn;
+    P = P + T;
+    Q = Q + F;
   }
-  for (int k = 0; k < s; ++k) {
-    mm<N>(out, out, tmp);
-    for (int i = 0; i < N; ++i)
-      for (int j = 0; j < N; ++j) out[i][j] = tmp[i][j];
+  for (int r = 0; r < s; ++r) {
+    Q = gmm(P, Q, g) + gmm(Q, P, g);
+    P = gmm(P, P, g);
   }
+  return Q;
 }
-
-__device__ void generator(int k, cd (&g)[4][4]) {
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) g[i][j] = cd{0, 0};
-  const int pj[6] = {0, 0, 0, 1, 1, 2}, pk[6] = {1, 2, 3, 2, 3, 3};
-  if (k < 4) g[k][k] = cd{1, 0};
-  else if (k < 10) { int a = pj[k - 4], b = pk[k - 4]; g[a][b] = cd{1, 0}; g[b][a] = cd{1, 0}; }
-  else { int a = pj[k - 10], b = pk[k - 10]; g[b][a] = cd{0, 1}; g[a][b] = cd{0, -1}; }
-}
-
-struct CostState {
-  cd U[4][4], Kp[4][2][2], K[4][2][2], rho[2][2], sig[4][2][2];
-  cd N[4][4], E[4][2][2];   // internal-bond cost only
-  double p[4], P[4];
-};
 
 // Q(A, B) = sum A[s1][s2] B[s3][s4] N[(s2,s3)][(s1,s4)]: Tr Gamma_j^2 = Q(E_j, E_j), symmetric in
 // its two arguments (cyclicity of the trace)
@@ -411,187 +417,175 @@ __device__ inline cd bond_q(const cd (&a)[2][2], const cd (&b)[2][2], const cd (
   return s;
 }
 
-// nm == nullptr: the noisy qubit against the rest of the block (P_j = Tr sigma~_j^2); else the
-// block's internal bond, nm the moment matrix N [4][4] c128 (P_j = Q(E_j, E_j)).
-__device__ void cost_setup(const double* rho_in, const double* nm, const double* kraus, const double* params,
-                           const double* uref, CostState& cs, cd (&Xh)[4][4]) {
-  for (int x = 0; x < 4; ++x) cs.rho[x >> 1][x & 1] = cd{rho_in[2 * x], rho_in[2 * x + 1]};
-  // normalise rho (the reduction of an unnormalised theta is allowed)
-  double tr = cs.rho[0][0].re + cs.rho[1][1].re;
-  for (int x = 0; x < 4; ++x) cs.rho[x >> 1][x & 1] = (1.0 / tr) * cs.rho[x >> 1][x & 1];
-  for (int i = 0; i < 4; ++i)
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) cs.K[i][a][b] = cd{kraus[2 * (4 * i + 2 * a + b)], kraus[2 * (4 * i + 2 * a + b) + 1]};
-  cd H[4][4], X[4][4], E[4][4], Ur[4][4];
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
-      H[i][j] = cd{0, 0};
-      Ur[i][j] = cd{uref[2 * (4 * i + j)], uref[2 * (4 * i + j) + 1]};
-    }
-  for (int k = 0; k < 16; ++k) {
-    cd g[4][4];
-    generator(k, g);
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) H[i][j] = H[i][j] + params[k] * g[i][j];
-  }
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) X[i][j] = cd{-H[i][j].im, H[i][j].re};   // iH
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) Xh[i][j] = conj(X[j][i]);                // (iH)^dag
-  expm<4>(X, E);
-  mm<4>(E, Ur, cs.U);
-  for (int j = 0; j < 4; ++j) {
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
-        cd s = {0, 0};
-        for (int i = 0; i < 4; ++i) cfma(s, cs.U[j][i], cs.K[i][a][b]);
-        cs.Kp[j][a][b] = s;
-      }
-    // sigma~ = K' rho K'^dag
-    cd t[2][2];
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
-        cd s = {0, 0};
-        for (int m = 0; m < 2; ++m) cfma(s, cs.Kp[j][a][m], cs.rho[m][b]);
-        t[a][b] = s;
-      }
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
-        cd s = {0, 0};
-        for (int m = 0; m < 2; ++m) cfma_conj(s, t[a][m], cs.Kp[j][b][m]);
-        cs.sig[j][a][b] = s;
-      }
-    cs.p[j] = cs.sig[j][0][0].re + cs.sig[j][1][1].re;
-    double P = 0;
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) P += (cs.sig[j][a][b] * cs.sig[j][b][a]).re;
-    cs.P[j] = P;
-  }
-  if (nm) {
-    for (int x = 0; x < 16; ++x) cs.N[x >> 2][x & 3] = cd{nm[2 * x], nm[2 * x + 1]};
-    for (int j = 0; j < 4; ++j) {
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-          cd e = {0, 0};
-          for (int x = 0; x < 2; ++x) cfma(e, conj(cs.Kp[j][x][a]), cs.Kp[j][x][b]);
-          cs.E[j][a][b] = e;
-        }
-      cs.P[j] = bond_q(cs.E[j], cs.E[j], cs.N).re;
-    }
-  }
-}
+__device__ inline int pair_index(int a, int c) { return a * (7 - a) / 2 + (c - a - 1); }   // a < c
 
 constexpr double P_TINY = 1e-300;
 constexpr double LN2 = 0.69314718055994530942;
 
-__global__ void k_cost_eval(int batch, const double* rho, const double* nm, const double* kraus, const double* params,
-                            const double* uref, int kind, double* f) {
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
-  CostState cs;
-  cd Xh[4][4];
-  cost_setup(rho + b * 8, nm ? nm + b * 32 : nullptr, kraus, params + b * 16, uref + b * 32, cs, Xh);
-  double acc = 0;
-  for (int j = 0; j < 4; ++j) {
-    double p = cs.p[j], P = cs.P[j];
-    if (!(p > P_TINY)) continue;
-    if (kind == 0) acc += p - P / p;
-    else acc += -p * log(P / (p * p)) / LN2;
+// Per lane (j, i) = (g >> 2, g & 3) of a state's group: X = iH entry, U_ji, the branch j it
+// serves (K'_j, sigma~_j, E_j, p_j, P_j).
+struct Branch {
+  cd h, U;
+  cd Ki[2][2];   // K_i of the lane's column i
+  cd Kp[2][2], rho[2][2], sig[2][2], E[2][2], N[4][4];
+  double p, P;
+};
+
+__device__ __forceinline__ void branch_setup(int g, const double* rho_in, const double* nm, const double* kraus, const double* params,
+                             const double* uref, Branch& br) {
+  const int a = g >> 2, c = g & 3;
+  for (int x = 0; x < 4; ++x) br.rho[x >> 1][x & 1] = cd{rho_in[2 * x], rho_in[2 * x + 1]};
+  // normalise rho (the reduction of an unnormalised theta is allowed)
+  const double tr = br.rho[0][0].re + br.rho[1][1].re;
+  for (int x = 0; x < 4; ++x) br.rho[x >> 1][x & 1] = (1.0 / tr) * br.rho[x >> 1][x & 1];
+  auto kraus_at = [&](int i, int x, int y) { return cd{kraus[2 * (4 * i + 2 * x + y)], kraus[2 * (4 * i + 2 * x + y) + 1]}; };
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) br.Ki[x][y] = kraus_at(c, x, y);
+  // H = sum_k params_k L_k: E_kk (k < 4), E_pq + E_qp (4 + pair), i (E_qp - E_pq) (10 + pair)
+  if (a == c) br.h = cd{params[a], 0.0};
+  else {
+    const int lo = a < c ? a : c, hi = a < c ? c : a, pi = pair_index(lo, hi);
+    br.h = cd{params[4 + pi], a < c ? -params[10 + pi] : params[10 + pi]};
   }
-  f[b] = acc;
+  const cd x = cd{-br.h.im, br.h.re};   // iH
+  const cd ex = gexpm(x, g);
+  // U = exp(iH) U_ref
+  cd u = {0, 0};
+  for (int k = 0; k < 4; ++k) cfma(u, gsh(ex, 4 * a + k), cd{uref[2 * (4 * k + c)], uref[2 * (4 * k + c) + 1]});
+  br.U = u;
+  // branch j = a: K'_j = sum_m U_jm K_m
+  cd row[4];
+  for (int m = 0; m < 4; ++m) row[m] = gsh(u, 4 * a + m);
+  for (int x2 = 0; x2 < 2; ++x2)
+    for (int y = 0; y < 2; ++y) {
+      cd s = {0, 0};
+      for (int m = 0; m < 4; ++m) cfma(s, row[m], kraus_at(m, x2, y));
+      br.Kp[x2][y] = s;
+    }
+  cd t[2][2];
+  for (int x2 = 0; x2 < 2; ++x2)
+    for (int y = 0; y < 2; ++y) {
+      cd s = {0, 0};
+      for (int m = 0; m < 2; ++m) cfma(s, br.Kp[x2][m], br.rho[m][y]);
+      t[x2][y] = s;
+    }
+  for (int x2 = 0; x2 < 2; ++x2)
+    for (int y = 0; y < 2; ++y) {
+      cd s = {0, 0};
+      for (int m = 0; m < 2; ++m) cfma_conj(s, t[x2][m], br.Kp[y][m]);
+      br.sig[x2][y] = s;
+    }
+  br.p = br.sig[0][0].re + br.sig[1][1].re;
+  if (nm) {
+    for (int e = 0; e < 16; ++e) br.N[e >> 2][e & 3] = cd{nm[2 * e], nm[2 * e + 1]};
+    for (int x2 = 0; x2 < 2; ++x2)
+      for (int y = 0; y < 2; ++y) {
+        cd s = {0, 0};
+        for (int m = 0; m < 2; ++m) cfma(s, conj(br.Kp[m][x2]), br.Kp[m][y]);
+        br.E[x2][y] = s;
+      }
+    br.P = bond_q(br.E, br.E, br.N).re;
+  } else {
+    double P = 0;
+    for (int x2 = 0; x2 < 2; ++x2)
+      for (int y = 0; y < 2; ++y) P += (br.sig[x2][y] * br.sig[y][x2]).re;
+    br.P = P;
+  }
 }
 
-__global__ void k_cost_grad(int batch, const double* rho, const double* nm, const double* kraus, const double* params,
-                            const double* uref, int kind, const double* grad_f, double* grad) {
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
-  CostState cs;
-  cd Xh[4][4];
-  cost_setup(rho + b * 8, nm ? nm + b * 32 : nullptr, kraus, params + b * 16, uref + b * 32, cs, Xh);
-  // G[j][i] = g_p Tr(K_i rho K'_j^dag) + g_P 2 Tr(sigma~_j K_i rho K'_j^dag)
-  cd G[4][4];
-  for (int j = 0; j < 4; ++j) {
-    double p = cs.p[j], P = cs.P[j];
-    double gp = 0, gP = 0;
-    if (p > P_TINY) {
-      if (kind == 0) { gp = 1.0 + P / (p * p); gP = -1.0 / p; }
-      else { gp = -log(P / (p * p)) / LN2 + 2.0 / LN2; gP = -p / (P * LN2); }
-    }
-    for (int i = 0; i < 4; ++i) {
-      // B = K_i rho K'_j^dag
-      cd t[2][2], B[2][2];
-      for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 2; ++c) {
-          cd s = {0, 0};
-          for (int m = 0; m < 2; ++m) cfma(s, cs.K[i][a][m], cs.rho[m][c]);
-          t[a][c] = s;
-        }
-      for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 2; ++c) {
-          cd s = {0, 0};
-          for (int m = 0; m < 2; ++m) cfma_conj(s, t[a][m], cs.Kp[j][c][m]);
-          B[a][c] = s;
-        }
-      cd trB = B[0][0] + B[1][1];
-      cd trSB = {0, 0};   // d P_j / d U_ji / 2
-      if (nm) {
-        cd D[2][2];       // K'_j^dag K_i
-        for (int a = 0; a < 2; ++a)
-          for (int c = 0; c < 2; ++c) {
-            cd e = {0, 0};
-            for (int x = 0; x < 2; ++x) cfma(e, conj(cs.Kp[j][x][a]), cs.K[i][x][c]);
-            D[a][c] = e;
-          }
-        trSB = bond_q(D, cs.E[j], cs.N);
-      } else {
-        for (int a = 0; a < 2; ++a)
-          for (int m = 0; m < 2; ++m) trSB = trSB + cs.sig[j][a][m] * B[m][a];
-      }
-      G[j][i] = gp * trB + (2.0 * gP) * trSB;
-    }
+// nm == nullptr: the noisy qubit against the rest of the block (P_j = Tr sigma~_j^2); else the
+// block's internal bond, nm the moment matrix N [4][4] c128 per state (P_j = Q(E_j, E_j)).
+__global__ __launch_bounds__(256) void k_cost_eval(int batch, const double* rho, const double* nm, const double* kraus,
+                                                   const double* params, const double* uref, int kind, double* f) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x, g = threadIdx.x & 15;
+  const int b = gid >> 4, bb = b < batch ? b : batch - 1;   // every lane of a group works
+  Branch br;
+  branch_setup(g, rho + bb * 8, nm ? nm + bb * 32 : nullptr, kraus, params + bb * 16, uref + bb * 32, br);
+  double term = 0;
+  if (br.p > P_TINY) term = kind == 0 ? br.p - br.P / br.p : -br.p * log(br.P / (br.p * br.p)) / LN2;
+  // the 4 lanes of row j hold branch j's term: a quarter from each, summed over the group
+  double v = 0.25 * term;
+  v += __shfl_xor(v, 1, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 8, 16);
+  if (g == 0 && b < batch) f[b] = v;
+}
+
+__global__ __launch_bounds__(256) void k_cost_grad(int batch, const double* rho, const double* nm, const double* kraus,
+                                                   const double* params, const double* uref, int kind,
+                                                   const double* grad_f, double* grad) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x, g = threadIdx.x & 15;
+  const int b = gid >> 4, bb = b < batch ? b : batch - 1;
+  const int a = g >> 2, c = g & 3;
+  Branch br;
+  branch_setup(g, rho + bb * 8, nm ? nm + bb * 32 : nullptr, kraus, params + bb * 16, uref + bb * 32, br);
+  // G[j][i] = g_p Tr(K_i rho K'_j^dag) + g_P d P_j / d U_ji, lane (j, i) = (a, c)
+  const double p = br.p, P = br.P;
+  double gp = 0, gP = 0;
+  if (p > P_TINY) {
+    if (kind == 0) { gp = 1.0 + P / (p * p); gP = -1.0 / p; }
+    else { gp = -log(P / (p * p)) / LN2 + 2.0 / LN2; gP = -p / (P * LN2); }
   }
-  // M = U_ref G^T ; block exponential for L(X^dag, M^dag)
-  cd Ur[4][4], Mt[4][4];
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) Ur[i][j] = cd{uref[b * 32 + 2 * (4 * i + j)], uref[b * 32 + 2 * (4 * i + j) + 1]};
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
+  cd t[2][2], B[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
       cd s = {0, 0};
-      for (int k = 0; k < 4; ++k) cfma(s, Ur[i][k], G[j][k]);
-      Mt[i][j] = s;
+      for (int m = 0; m < 2; ++m) cfma(s, br.Ki[x][m], br.rho[m][y]);
+      t[x][y] = s;
     }
-  cd Bk[8][8], Eb[8][8];
-  for (int i = 0; i < 8; ++i)
-    for (int j = 0; j < 8; ++j) Bk[i][j] = cd{0, 0};
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
-      Bk[i][j] = Xh[i][j];
-      Bk[4 + i][4 + j] = Xh[i][j];
-      Bk[i][4 + j] = conj(Mt[j][i]);   // M^dag
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      cd s = {0, 0};
+      for (int m = 0; m < 2; ++m) cfma_conj(s, t[x][m], br.Kp[y][m]);
+      B[x][y] = s;
     }
-  expm<8>(Bk, Eb);
-  const double gf = grad_f ? grad_f[b] : 1.0;
-  for (int k = 0; k < 16; ++k) {
-    cd g[4][4];
-    generator(k, g);
-    // Tr(Y^dag i g) = sum_{a,c} conj(Y[a][c]) (i g[a][c])
-    cd s = {0, 0};
-    for (int a = 0; a < 4; ++a)
-      for (int c = 0; c < 4; ++c) s = s + cmulc(Eb[a][4 + c], cd{-g[a][c].im, g[a][c].re});
-    grad[b * 16 + k] = gf * 2.0 * s.re;
+  const cd trB = B[0][0] + B[1][1];
+  cd trSB = {0, 0};   // d P_j / d U_ji / 2
+  if (nm) {
+    cd D[2][2];       // K'_j^dag K_i
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y) {
+        cd e = {0, 0};
+        for (int m = 0; m < 2; ++m) cfma(e, conj(br.Kp[m][x]), br.Ki[m][y]);
+        D[x][y] = e;
+      }
+    trSB = bond_q(D, br.E, br.N);
+  } else {
+    for (int x = 0; x < 2; ++x)
+      for (int m = 0; m < 2; ++m) trSB = trSB + br.sig[x][m] * B[m][x];
+  }
+  const cd G = gp * trB + (2.0 * gP) * trSB;
+  // M = U_ref G^T, E = M^dag; L(X^dag, E) with X^dag = (iH)^dag = -iH
+  const double* ur = uref + bb * 32;
+  cd mt = {0, 0};
+  for (int k = 0; k < 4; ++k) cfma(mt, cd{ur[2 * (4 * a + k)], ur[2 * (4 * a + k) + 1]}, gsh(G, 4 * c + k));
+  const cd e = conj(gsh(mt, 4 * c + a));
+  const cd L = gfrechet(cd{br.h.im, -br.h.re}, e, g);
+  // d f / d params_k = 2 Re sum conj(L) (i L_k): i E_kk -> Im L_kk; i (E_pq + E_qp) -> Im L_pq +
+  // Im L_qp; i * i (E_qp - E_pq) -> Re L_pq - Re L_qp (p < q)
+  const cd Lt = gsh(L, 4 * c + a);
+  const double gf = grad_f ? grad_f[bb] : 1.0;
+  if (b < batch) {
+    if (a == c) grad[b * 16 + a] = gf * 2.0 * L.im;
+    else if (a < c) {
+      const int pi = pair_index(a, c);
+      grad[b * 16 + 4 + pi] = gf * 2.0 * (L.im + Lt.im);
+      grad[b * 16 + 10 + pi] = gf * 2.0 * (L.re - Lt.re);
+    }
   }
 }
 
 hipError_t cost_eval(int batch, const double* rho, const double* nm, const double* kraus, const double* params,
                      const double* u_ref, int kind, double* f, hipStream_t st) {
-  hipLaunchKernelGGL(k_cost_eval, dim3((batch + 63) / 64), dim3(64), 0, st, batch, rho, nm, kraus, params, u_ref, kind,
+  hipLaunchKernelGGL(k_cost_eval, dim3((batch + 15) / 16), dim3(256), 0, st, batch, rho, nm, kraus, params, u_ref, kind,
                      f);
   return hipGetLastError();
 }
 
 hipError_t cost_grad(int batch, const double* rho, const double* nm, const double* kraus, const double* params,
                      const double* u_ref, int kind, const double* grad_f, double* grad, hipStream_t st) {
-  hipLaunchKernelGGL(k_cost_grad, dim3((batch + 63) / 64), dim3(64), 0, st, batch, rho, nm, kraus, params, u_ref, kind,
+  hipLaunchKernelGGL(k_cost_grad, dim3((batch + 15) / 16), dim3(256), 0, st, batch, rho, nm, kraus, params, u_ref, kind,
                      grad_f, grad);
   return hipGetLastError();
 }
