@@ -348,6 +348,10 @@ int unravel_opt(int batch, const double* rho_q, const double* kraus, int n_k,
                 const int32_t* kraus_id, int r, double* U, double* p, double* eof,
                 void* stream);
 
+/* Largest batch of the unravelling-cost calls (unravel_cost*, their adjoints): larger batches
+ * fail with MPSB_EINVAL. */
+#define MPSB_MAX_COST_BATCH (1 << 26)
+
 /* Expected entanglement of an unravelling, as a function of the mixing (differentiable
  * cost).  The mixing is the unitary freedom of a Kraus representation (Preliminaries,
  * eq. unitarity_kraus: K'_j = sum_i U_ji K_i describes the same channel); the cost is the

@@ -1766,7 +1766,8 @@ int unravel_opt(int batch, const double* rho_q, const double* kraus, int n_k, co
 
 int unravel_cost(int batch, const void* theta_, int chi_l, int chi_r, int prec, const double* kraus,
                  const double* params, const double* u_ref, int kind, double* f_out, double* rho_out, void* stream) {
-  if (batch < 0 || chi_l < 1 || chi_r < 1 || (long long)chi_l * chi_r > (1LL << 26)) return fail(MPSB_EINVAL, "bad sizes");
+  if (batch < 0 || batch > MPSB_MAX_COST_BATCH || chi_l < 1 || chi_r < 1 || (long long)chi_l * chi_r > (1LL << 26))
+    return fail(MPSB_EINVAL, "bad sizes");
   if (prec != MPSB_FP32_BULK && prec != MPSB_FP64) return fail(MPSB_EINVAL, "bad precision");
   if (kind != 0 && kind != 1) return fail(MPSB_EINVAL, "kind must be 0 or 1");
   if (batch == 0) return MPSB_OK;
@@ -1779,7 +1780,7 @@ int unravel_cost(int batch, const void* theta_, int chi_l, int chi_r, int prec, 
 
 int unravel_cost_grad(int batch, const double* rho_q, const double* kraus, const double* params, const double* u_ref,
                       int kind, const double* grad_f, double* grad_out, void* stream) {
-  if (batch < 0) return fail(MPSB_EINVAL, "bad sizes");
+  if (batch < 0 || batch > MPSB_MAX_COST_BATCH) return fail(MPSB_EINVAL, "bad sizes");
   if (kind != 0 && kind != 1) return fail(MPSB_EINVAL, "kind must be 0 or 1");
   if (batch == 0) return MPSB_OK;
   if (!rho_q || !kraus || !params || !u_ref || !grad_out) return fail(MPSB_EINVAL, "null pointer");
@@ -1790,7 +1791,7 @@ int unravel_cost_grad(int batch, const double* rho_q, const double* kraus, const
 int unravel_cost_bond(int batch, const void* theta_, int chi_l, int chi_r, int prec, const double* kraus,
                       const double* params, const double* u_ref, int kind, double* f_out, double* rho_out,
                       double* n_out, void* stream) {
-  if (batch < 0 || batch > (1 << 30) || chi_l < 1 || chi_r < 1 || (long long)chi_l * chi_r > (1LL << 26))
+  if (batch < 0 || batch > MPSB_MAX_COST_BATCH || chi_l < 1 || chi_r < 1 || (long long)chi_l * chi_r > (1LL << 26))
     return fail(MPSB_EINVAL, "bad sizes");
   if (prec != MPSB_FP32_BULK && prec != MPSB_FP64) return fail(MPSB_EINVAL, "bad precision");
   if (kind != 0 && kind != 1) return fail(MPSB_EINVAL, "kind must be 0 or 1");
@@ -1805,7 +1806,7 @@ int unravel_cost_bond(int batch, const void* theta_, int chi_l, int chi_r, int p
 int unravel_cost_bond_grad(int batch, const double* rho_q, const double* n_mom, const double* kraus,
                            const double* params, const double* u_ref, int kind, const double* grad_f,
                            double* grad_out, void* stream) {
-  if (batch < 0) return fail(MPSB_EINVAL, "bad sizes");
+  if (batch < 0 || batch > MPSB_MAX_COST_BATCH) return fail(MPSB_EINVAL, "bad sizes");
   if (kind != 0 && kind != 1) return fail(MPSB_EINVAL, "kind must be 0 or 1");
   if (batch == 0) return MPSB_OK;
   if (!rho_q || !n_mom || !kraus || !params || !u_ref || !grad_out) return fail(MPSB_EINVAL, "null pointer");

@@ -158,6 +158,11 @@ def test_unravel_entry_points_validate_on_the_host():
     assert lib.unravel_cost_bond(0, None, 8, 8, 1, None, None, None, 0, None, None, None, None) == M.OK
     assert lib.unravel_cost_bond_grad(4, one, None, one, one, one, 0, None, one, None) == M.EINVAL
     assert lib.unravel_cost_bond_grad(4, one, one, one, one, one, 3, None, one, None) == M.EINVAL
+    big = (1 << 26) + 1   # above MPSB_MAX_COST_BATCH
+    assert lib.unravel_cost(big, one, 1, 1, 1, one, one, one, 0, one, one, None) == M.EINVAL
+    assert lib.unravel_cost_grad(big, one, one, one, one, 0, None, one, None) == M.EINVAL
+    assert lib.unravel_cost_bond(big, one, 1, 1, 1, one, one, one, 0, one, one, one, None) == M.EINVAL
+    assert lib.unravel_cost_bond_grad(big, one, one, one, one, one, 0, None, one, None) == M.EINVAL
 
 
 def test_static_batch_rejects_oversized_and_mixed_plans():
