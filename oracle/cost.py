@@ -94,7 +94,7 @@ def grad_torch(rho_q: np.ndarray, kraus: np.ndarray, params: np.ndarray, u_ref: 
     for j in range(4):
         sig = kp[j] @ rho @ kp[j].conj().T
         p = torch.real(torch.trace(sig))
-        if float(p) <= P_TINY:
+        if float(p.detach()) <= P_TINY:
             continue
         pur = torch.real(torch.trace(sig @ sig))
         if kind == KIND_LINEAR:
@@ -102,7 +102,7 @@ def grad_torch(rho_q: np.ndarray, kraus: np.ndarray, params: np.ndarray, u_ref: 
         else:
             f = f - p * torch.log2(pur / (p * p))
     f.backward()
-    return float(f), th.grad.numpy().copy()
+    return float(f.detach()), th.grad.numpy().copy()
 
 
 def grad_fd(rho_q, kraus, params, u_ref, kind, h=1e-4):
@@ -175,7 +175,7 @@ def bond_grad_torch(theta: np.ndarray, kraus: np.ndarray, params: np.ndarray, u_
         else:
             f = f - p * torch.log2(pur / (p * p))
     f.backward()
-    return float(f), th.grad.numpy().copy()
+    return float(f.detach()), th.grad.numpy().copy()
 
 
 def bond_grad_fd(theta, kraus, params, u_ref, kind, h=1e-4):
