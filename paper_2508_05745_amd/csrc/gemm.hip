@@ -34,6 +34,42 @@ __device__ inline void load_gate(const Mat4& gate, const GateRef& gref, int traj
   }
 }
 
+// The two-site RDM is Hermitian: per theta entry only its upper triangle is accumulated
+// (Re v_x conj(v_y) for x <= y, Im for x < y; index o of (x, y) = 4 x - x (x - 1) / 2 + y - x),
+// and the workgroup's sums (red[w][0..9] real, red[w][10..19] imaginary, one row per wave) are
+// written out as the full 4 x 4 c128 by symmetry.
+__device__ inline void rdm_upper_acc(double (&rr)[10], double (&ri)[10], const double (&vr)[4], const double (&vi)[4]) {
+  int o = 0;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = x; y < 4; ++y) {
+      rr[o] += vr[x] * vr[y] + vi[x] * vi[y];
+      if (y > x) ri[o] += vi[x] * vr[y] - vr[x] * vi[y];
+      ++o;
+    }
+}
+
+__device__ inline void rdm_reduce_write(const double (&rr)[10], const double (&ri)[10], double (&red)[4][32], double* p) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int x = 0; x < 20; ++x) {
+    double v = (x < 10) ? rr[x] : ri[x - 10];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][x] = v;
+  }
+  __syncthreads();
+  if (tid < 32) {
+    const int x = (tid & 15) >> 2, y = tid & 3, lo = x < y ? x : y, hi = x < y ? y : x;
+    const int o = lo * 4 - lo * (lo - 1) / 2 + (hi - lo);
+    double v;
+    if (tid < 16) v = red[0][o] + red[1][o] + red[2][o] + red[3][o];
+    else v = x == y ? 0.0 : (x < y ? 1.0 : -1.0) * (red[0][10 + o] + red[1][10 + o] + red[2][10 + o] + red[3][10 + o]);
+    if (tid < 16) p[2 * (tid & 15)] = v; else p[2 * (tid & 15) + 1] = v;
+  }
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <typename T> struct MfmaAcc;
@@ -294,9 +330,9 @@ __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, 
   // epilogue: lane holds rows a = a0 + 16 wa + row(kq, i), column b = b0 + 16 wb + r16
   double gg[32];
   load_gate(gate, gref, traj, gg);
-  double rr[16], ri[16];
+  double rr[10], ri[10];
 #pragma unroll
-  for (int x = 0; x < 16; ++x) rr[x] = ri[x] = 0.0;
+  for (int x = 0; x < 10; ++x) rr[x] = ri[x] = 0.0;
   const int b = b0 + 16 * wb + r16;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -320,35 +356,15 @@ __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, 
       vr[x] = (double)o.re;
       vi[x] = (double)o.im;
     }
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        rr[4 * x + y] += vr[x] * vr[y] + vi[x] * vi[y];
-        ri[4 * x + y] += vi[x] * vr[y] - vr[x] * vi[y];
-      }
+    rdm_upper_acc(rr, ri, vr, vi);
   }
-#pragma unroll
-  for (int x = 0; x < 32; ++x) {
-    double v = (x < 16) ? rr[x] : ri[x - 16];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) red[wv][x] = v;
-  }
-  __syncthreads();
-  if (tid < 32) {
-    double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    int tile = blockIdx.y * gridDim.x + blockIdx.x;
-    int x = tid & 15;
-    double* p = partial + ((long long)traj * n_tiles + tile) * 32;
-    if (tid < 16) p[2 * x] = v; else p[2 * x + 1] = v;
-  }
+  rdm_reduce_write(rr, ri, red, partial + ((long long)traj * n_tiles + blockIdx.y * gridDim.x + blockIdx.x) * 32);
 }
 
 // Large-tile FP32 variant for the bulk bonds (chi_L, chi_R >= 64): 64 values of a x 64
 // values of b per workgroup (128 rows x 128 columns of theta), 2 x 2 waves of 32 x 32 values,
 // each wave 2 x 2 MFMA sub-tiles of 16 x 16 for each of the four (s,t) blocks (128
-// accumulator registers per lane).  The next K block of 16 is loaded into registers while
+// accumulator registers per lane, within the 256 registers of two waves per SIMD).  The next K block of 16 is loaded into registers while
 // the current one is multiplied out of LDS.  The site tensors are stored in LDS as [k][s][a]
 // and [k][t][b] with a row pitch of 144 floats, so that the four k-rows a wave reads at once
 // fall in different bank halves.  Workgroup ids are remapped so that all tiles of one
@@ -356,7 +372,7 @@ __global__ __launch_bounds__(256) void k_theta(int chi_l, int chi_m, int chi_r, 
 // and share the trajectory's site tensors in that XCD's L2.
 constexpr int TL_P = 144;
 
-__global__ __launch_bounds__(256) void k_theta_l(int chi_l, int chi_m, int chi_r, const c32* __restrict__ Cs,
+__global__ __launch_bounds__(256, 2) void k_theta_l(int chi_l, int chi_m, int chi_r, const c32* __restrict__ Cs,
                                                  const c32* __restrict__ Bs, long long s_traj, c32* __restrict__ out,
                                                  long long s_out, Mat4 gate, GateRef gref, double* __restrict__ partial, int tiles_a,
                                                  int tiles_b) {
@@ -463,9 +479,9 @@ __global__ __launch_bounds__(256) void k_theta_l(int chi_l, int chi_m, int chi_r
   // epilogue: lane holds a = a0 + 32 wa + 16 ia + 4 kq + i, b = b0 + 32 wb + 16 jb + r16
   double gg[32];
   load_gate(gate, gref, traj, gg);
-  double rr[16], ri[16];
+  double rr[10], ri[10];
 #pragma unroll
-  for (int x = 0; x < 16; ++x) rr[x] = ri[x] = 0.0;
+  for (int x = 0; x < 10; ++x) rr[x] = ri[x] = 0.0;
 #pragma unroll
   for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
@@ -493,29 +509,10 @@ __global__ __launch_bounds__(256) void k_theta_l(int chi_l, int chi_m, int chi_r
           vr[x] = (double)o.re;
           vi[x] = (double)o.im;
         }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) {
-            rr[4 * x + y] += vr[x] * vr[y] + vi[x] * vi[y];
-            ri[4 * x + y] += vi[x] * vr[y] - vr[x] * vi[y];
-          }
+        rdm_upper_acc(rr, ri, vr, vi);
       }
     }
-#pragma unroll
-  for (int x = 0; x < 32; ++x) {
-    double v = (x < 16) ? rr[x] : ri[x - 16];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) red[wv][x] = v;
-  }
-  __syncthreads();
-  if (tid < 32) {
-    double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    int x = tid & 15;
-    double* p = partial + ((long long)traj * nt + tile) * 32;
-    if (tid < 16) p[2 * x] = v; else p[2 * x + 1] = v;
-  }
+  rdm_reduce_write(rr, ri, red, partial + ((long long)traj * nt + tile) * 32);
 }
 
 int theta_variant_ok(int prec, int variant, int chi_l, int chi_r) {
