@@ -368,7 +368,9 @@ int unravel_opt(int batch, const double* rho_q, const double* kraus, int n_k,
  * params[k] L_k) U_ref, the 16 generators L_k being E_kk (k<4), then for the pairs
  * (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) the symmetric E_jk + E_kj and the antisymmetric
  * i(E_kj - E_jk).  kraus [4][2][2] c128 (zero padded), params [batch][16] FP64, u_ref
- * [batch][4][4] c128, f_out [batch] FP64.  Device pointers. */
+ * [batch][4][4] c128, f_out [batch] FP64.  Device pointers.  MPSB_EINVAL for batch < 0 or
+ * above MPSB_MAX_COST_BATCH, chi_l or chi_r < 1, chi_l chi_r > 2^26, another precision or kind,
+ * or a null pointer (batch > 0). */
 int unravel_cost(int batch, const void* theta, int chi_l, int chi_r, int prec,
                  const double* kraus, const double* params, const double* u_ref, int kind,
                  double* f_out, double* rho_out, void* stream);
