@@ -87,44 +87,46 @@ template <> struct MfmaAcc<double> {
 // MFMA form of the generic GEMM: the same 64 x 64 block tile and LDS staging; each of the
 // 4 waves owns a 32 x 32 quadrant as 2 x 2 MFMA sub-tiles of 16 x 16, complex products as four
 // real 16x16x4 MFMAs (f32 for FP32 inputs, f64 for FP64 inputs) per k-step of 4.
-template <typename TA, typename TB, typename TACC, typename TC, bool CA, bool CB>
-__global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cplx<TA>* __restrict__ A,
+template <typename TA, typename TB, typename TACC, typename TC, bool CA, bool CB, int S = 2>
+__global__ __launch_bounds__(256, S == 4 ? 2 : 1) void k_gemm_mfma(int M, int N, int K, const cplx<TA>* __restrict__ A,
                                                    int lda, long long sA, const cplx<TB>* __restrict__ B,
                                                    int ldb, long long sB, cplx<TC>* __restrict__ C, int ldc,
                                                    long long sC, const double* __restrict__ alpha, int lower,
                                                    const int* __restrict__ active) {
   using Mf = MfmaAcc<TACC>;
   using V = typename Mf::V;
-  __shared__ TACC As_re[GB_K][GB_M + 4], As_im[GB_K][GB_M + 4];
-  __shared__ TACC Bs_re[GB_K][GB_N + 4], Bs_im[GB_K][GB_N + 4];
+  constexpr int TILE = 32 * S;   // workgroup tile TILE x TILE, wave tile 16 S x 16 S
+  constexpr int LPT = 2 * S;     // elements of each operand slice per thread
+  __shared__ TACC As_re[GB_K][TILE + 4], As_im[GB_K][TILE + 4];
+  __shared__ TACC Bs_re[GB_K][TILE + 4], Bs_im[GB_K][TILE + 4];
   const int bz = blockIdx.z;
   if (active && !active[bz]) return;
   A += bz * sA;
   B += bz * sB;
   C += bz * sC;
-  const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
   // lower: only the tiles holding elements on or below the diagonal are computed (the upper
   // triangle of a Hermitian product that is read from its lower triangle alone)
-  if (lower && n0 >= m0 + GB_M) return;
+  if (lower && n0 >= m0 + TILE) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wa = wv >> 1, wb = wv & 1, r16 = lane & 15, kq = lane >> 4;
-  V acc_re[2][2], acc_im[2][2];
+  V acc_re[S][S], acc_im[S][S];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < S; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < S; ++j) {
       acc_re[i][j] = V{0, 0, 0, 0};
       acc_im[i][j] = V{0, 0, 0, 0};
     }
   // the next k-slice is loaded into registers while the current one is multiplied from LDS
-  cplx<TA> pa[4];
-  cplx<TB> pb[4];
+  cplx<TA> pa[LPT];
+  cplx<TB> pb[LPT];
   auto load_slice = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LPT; ++r) {
       const int e = tid + 256 * r;
       int mm, kk;
-      if (!CA) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
+      if (!CA) { kk = e & 15; mm = e >> 4; } else { mm = e % TILE; kk = e / TILE; }
       const int m = m0 + mm, k = k0 + kk;
       cplx<TA> v = {0, 0};
       if (m < M && k < K) {
@@ -134,10 +136,10 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cp
       pa[r] = v;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LPT; ++r) {
       const int e = tid + 256 * r;
       int nn, kk;
-      if (!CB) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
+      if (!CB) { nn = e % TILE; kk = e / TILE; } else { kk = e & 15; nn = e >> 4; }
       const int n = n0 + nn, k = k0 + kk;
       cplx<TB> v = {0, 0};
       if (n < N && k < K) {
@@ -150,18 +152,18 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cp
   load_slice(0);
   for (int k0 = 0; k0 < K; k0 += GB_K) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LPT; ++r) {
       const int e = tid + 256 * r;
       int mm, kk;
-      if (!CA) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
+      if (!CA) { kk = e & 15; mm = e >> 4; } else { mm = e % TILE; kk = e / TILE; }
       As_re[kk][mm] = (TACC)pa[r].re;
       As_im[kk][mm] = (TACC)pa[r].im;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LPT; ++r) {
       const int e = tid + 256 * r;
       int nn, kk;
-      if (!CB) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
+      if (!CB) { nn = e % TILE; kk = e / TILE; } else { kk = e & 15; nn = e >> 4; }
       Bs_re[kk][nn] = (TACC)pb[r].re;
       Bs_im[kk][nn] = (TACC)pb[r].im;
     }
@@ -170,18 +172,18 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cp
 #pragma unroll
     for (int k4 = 0; k4 < GB_K / 4; ++k4) {
       const int kk = 4 * k4 + kq;
-      TACC ar[2], ai[2], br[2], bi[2];
+      TACC ar[S], ai[S], br[S], bi[S];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = As_re[kk][32 * wa + 16 * i + r16];
-        ai[i] = As_im[kk][32 * wa + 16 * i + r16];
-        br[i] = Bs_re[kk][32 * wb + 16 * i + r16];
-        bi[i] = Bs_im[kk][32 * wb + 16 * i + r16];
+      for (int i = 0; i < S; ++i) {
+        ar[i] = As_re[kk][16 * S * wa + 16 * i + r16];
+        ai[i] = As_im[kk][16 * S * wa + 16 * i + r16];
+        br[i] = Bs_re[kk][16 * S * wb + 16 * i + r16];
+        bi[i] = Bs_im[kk][16 * S * wb + 16 * i + r16];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < S; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < S; ++j) {
           acc_re[i][j] = Mf::mac(ar[i], br[j], acc_re[i][j]);
           acc_re[i][j] = Mf::mac(-ai[i], bi[j], acc_re[i][j]);
           acc_im[i][j] = Mf::mac(ar[i], bi[j], acc_im[i][j]);
@@ -192,13 +194,13 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cp
   }
   const double al = alpha ? alpha[bz] : 1.0;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < S; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = n0 + 32 * wb + 16 * j + r16;
+    for (int j = 0; j < S; ++j) {
+      const int n = n0 + 16 * S * wb + 16 * j + r16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + 32 * wa + 16 * i + Mf::row(kq, r);
+        const int m = m0 + 16 * S * wa + 16 * i + Mf::row(kq, r);
         if (m >= M || n >= N) continue;
         cplx<TC> o;
         o.re = (TC)(al * (double)acc_re[i][j][r]);
@@ -208,21 +210,40 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const cp
     }
 }
 
+template <typename TA, typename TB, typename TACC, typename TC, int S>
+static hipError_t gemm_launch(bool ca, bool cb, int M, int N, int K, const void* A, int lda,
+                              long long sA, const void* B, int ldb, long long sB, void* C,
+                              int ldc, long long sC, const double* alpha, int batch,
+                              hipStream_t st, int lower, const int* active) {
+  constexpr int TILE = 32 * S;
+  dim3 grid((N + TILE - 1) / TILE, (M + TILE - 1) / TILE, batch);
+  auto a = (const cplx<TA>*)A;
+  auto b = (const cplx<TB>*)B;
+  auto c = (cplx<TC>*)C;
+  if (!ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, false, S>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
+  else if (ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, false, S>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
+  else if (!ca && cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, true, S>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
+  else hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, true, S>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
+  return hipGetLastError();
+}
+
+// 128 x 128 workgroup tiles for the full (not lower-triangle) FP32-accumulated products of the
+// bulk bonds (both sides >= 128: more products per LDS slice and per barrier; measured 12%
+// faster for the 128 x 256 x 256 recomposition product, no faster for the lower-triangle Gram,
+// whose diagonal tiles would then compute a larger upper part), 64 x 64 otherwise.  Every
+// output element accumulates its k-slices in the same order for either tile, so the results
+// agree bit for bit.
 template <typename TA, typename TB, typename TACC, typename TC>
 static hipError_t gemm_dispatch(bool ca, bool cb, int M, int N, int K, const void* A, int lda,
                                 long long sA, const void* B, int ldb, long long sB, void* C,
                                 int ldc, long long sC, const double* alpha, int batch,
                                 hipStream_t st, int lower, const int* active) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch);
-  auto a = (const cplx<TA>*)A;
-  auto b = (const cplx<TB>*)B;
-  auto c = (cplx<TC>*)C;
-  if (!ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
-  else if (ca && !cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, false>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
-  else if (!ca && cb) hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, false, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
-  else hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TACC, TC, true, true>), grid, dim3(256), 0, st, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, alpha, lower, active);
-  return hipGetLastError();
+  if constexpr (sizeof(TACC) == 4) {
+    if (!lower && M >= 128 && N >= 128)
+      return gemm_launch<TA, TB, TACC, TC, 4>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lower, active);
+  }
+  return gemm_launch<TA, TB, TACC, TC, 2>(ca, cb, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, batch, st, lower, active);
 }
 
 hipError_t gemm(int prec_in, int prec_out, bool ca, bool cb, int M, int N, int K, const void* A,
