@@ -357,9 +357,9 @@ def bench_mixed(args):
     per_chi = {int(c): int((mc.gate_id[mc.chis == c][:, W:W + K, :] >= 0).sum()) for c in np.unique(mc.chis)}
     n_sub = int(np.count_nonzero(np.diff(mc.widths) != 0) + np.count_nonzero(np.diff(mc.chis) != 0) + 1)
     b.close()
-    cpu, oracle_err = None, None
+    cpu, oracle_err, sched = None, None, None
     if not args.no_cpu:
-        cpu, oracle_err = mixed_oracle_check(wl)
+        cpu, oracle_err, sched = mixed_oracle_check(wl)
     line = {
         "metric": "trajectory gate-steps/s (mixed batch)", "value": gates / dt, "unit": "trajectory gate-steps/s",
         "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * dt / K, "higher_is_better": True,
@@ -368,7 +368,7 @@ def bench_mixed(args):
         "config": {"workload": wl.name, "n_traj": mc.n_traj, "max_width": mc.n, "max_depth": mc.depth,
                    "sub_batches_upper_bound": n_sub, "timed_layers": [W, W + K - 1],
                    "gate_steps_timed": gates, "gate_steps_per_chi": per_chi},
-        "oracle_error": oracle_err, "cpu_baseline": cpu,
+        "oracle_error": oracle_err, "cpu_baseline": cpu, "schedule": sched,
     }
     print(json.dumps(line))
 
@@ -395,8 +395,14 @@ def mixed_oracle_check(wl):
     w = torch.zeros((T, W, 4, 4), dtype=torch.complex128, device="cuda")
     br = torch.zeros((T, W), dtype=torch.int32, device="cuda")
     ws, brs = [], []
+    sched = None
     for l in range(mc.depth):
+        if l == SCHED_LAYERS[0]:
+            b.profile(2)
         b.apply_layer(l, branch=br, w_record=w)
+        if l == SCHED_LAYERS[1]:
+            sched = schedule_report(mc, *b.schedule_read())
+            b.profile(0)
         ws.append(w[st].cpu().numpy())
         brs.append(br[st].cpu().numpy())
         if l % 4 == 3:
@@ -433,7 +439,42 @@ def mixed_oracle_check(wl):
     base = dict(value=steps / secs, unit="trajectory gate-steps/s", cores=_cores(), kind="oracle", cpu=cpu_model(),
                 sample=f"{len(sample)} trajectories (one per chi class) of an untimed recorded FP32-bulk pass "
                        f"replayed by the oracle (NumPy/LAPACK complex128) through all their layers")
-    return base, errs
+    return base, errs, sched
+
+
+# layers of the mixed batch's recorded pass whose member schedule is timed (every member has
+# work in them: depths start at 16)
+SCHED_LAYERS = (8, 11)
+
+
+def schedule_report(mc, first, count, stream, busy, elapsed, layers):
+    """Per-chi-class rates and stream utilisation from the member schedule of timed layers.
+    A member's gate-steps are the real gates (not the identity padding past a trajectory's own
+    depth) of its trajectories in those layers.  rate of a chi class = its trajectory gate-steps / its members' summed busy time (the rate
+    of the class on the stream slots it occupied); utilisation = summed busy time / (streams x
+    elapsed)."""
+    lo, hi = SCHED_LAYERS
+    ns = min(4, len(first))
+    per = {}
+    total = 0
+    for f, c, ms in zip(first, count, busy):
+        chi = int(mc.chis[f])
+        g = int((mc.gate_id[f:f + c, lo:hi + 1, :] >= 0).sum())
+        d = per.setdefault(chi, [0, 0.0, 0])
+        d[0] += g
+        d[1] += ms
+        d[2] += 1
+        total += g
+    return {
+        "layers": [lo, hi], "members": int(len(first)), "streams": ns, "assignment": "round-robin over the members sorted by (chi, width)",
+        "elapsed_ms": elapsed, "busy_ms": float(np.sum(busy)),
+        "utilisation_busy_over_streams_x_elapsed": float(np.sum(busy) / (ns * elapsed)) if elapsed > 0 else None,
+        "rate_all": total / (elapsed * 1e-3) if elapsed > 0 else None,
+        "per_chi": {str(k): {"gate_steps": v[0], "busy_ms": v[1], "members": v[2],
+                             "rate_on_its_streams": v[0] / (v[1] * 1e-3) if v[1] > 0 else None}
+                    for k, v in sorted(per.items())},
+        "note": "direct launches with an event pair around every member's layer (no layer graphs)",
+    }
 
 
 def bench_cost(args):

@@ -273,7 +273,8 @@ int mps_circuit_validate(int n_traj, const int32_t* width, const mpsb_circuit* c
 int expect(mpsb_handle h, double* mean, double* m2, double* per_traj);
 
 /* Optional per-kernel-class timing with HIP events recorded on the batch stream (for
- * roofline reports).  mps_profile(h, 1) resets and starts, (h, 0) stops.  mps_profile_read
+ * roofline reports).  mps_profile(h, 1) resets and starts, (h, 0) stops (bit 1 of the
+ * argument adds the schedule timing described below).  mps_profile_read
  * synchronises and returns, per class, the summed milliseconds and the number of timed
  * launches (host arrays of n entries); the return value is the number of classes.  Class
  * order: 0 theta contraction + gate + two-site RDM, 1 noise events (unravel + sample),
@@ -286,6 +287,21 @@ int expect(mpsb_handle h, double* mean, double* m2, double* per_traj);
  * truncation eigensolver). */
 int mps_profile(mpsb_handle h, int enable);
 int mps_profile_read(mpsb_handle h, double* ms, long long* count, int n);
+
+/* Schedule timing of a batch's members (the uniform sub-batches of a mixed batch, or the batch
+ * itself), for the per-chi-class rates and the stream utilisation of mixed batches.  Enabled by
+ * bit 1 of mps_profile's argument (2: schedule only, 3: with the kernel classes; 0..3, else
+ * MPSB_EINVAL; like bit 0 it turns layer graphs off).  Each timed layer records an event pair
+ * around the whole layer on the caller's stream and one around every member's share of it on
+ * the private stream it was assigned (members with work in the layer are dealt round-robin to
+ * up to four streams in trajectory order).  mps_schedule_read
+ * synchronises and writes, for the first n members (host arrays of n entries, in trajectory
+ * order): the index of the member's first trajectory, its trajectory count, the stream of its
+ * last timed layer (-1 if none) and its summed milliseconds; elapsed_ms and layers (each may be
+ * NULL) get the summed wall time of the timed layers and their number.  The return value is
+ * the number of members; null arrays with n > 0 give MPSB_EINVAL. */
+int mps_schedule_read(mpsb_handle h, int* first, int* count, int* stream, double* busy_ms, double* elapsed_ms,
+                      long long* layers, int n);
 
 /* Blocks until all work of the handle is done; reports asynchronous device errors. */
 int mps_batch_sync(mpsb_handle h);

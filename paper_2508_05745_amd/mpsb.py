@@ -65,6 +65,9 @@ def lib():
         L.apply_layer_global.argtypes = [vp, i32, i32, vp]
         L.mps_sample_bitstrings.argtypes = [vp, i32, u64, vp]
         L.expect.argtypes = [vp, vp, vp, vp]
+        L.mps_profile.argtypes = [vp, i32]
+        L.mps_profile_read.argtypes = [vp, vp, vp, i32]
+        L.mps_schedule_read.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32]
         L.mps_batch_sync.argtypes = [vp]
         L.mps_batch_destroy.argtypes = [vp]
         L.unravel_opt.argtypes = [i32, vp, vp, i32, vp, i32, vp, vp, vp, vp]
@@ -222,6 +225,26 @@ class Batch:
 
     def set_autotune(self, enable: bool):
         _check(lib().mps_batch_set_autotune(self.h, int(bool(enable))))
+
+    def profile(self, mode: int):
+        """0 off, 1 kernel classes, 2 member schedule, 3 both (resets the sums)."""
+        _check(lib().mps_profile(self.h, int(mode)))
+
+    def schedule_read(self):
+        """Member schedule sums since profile(2|3): per member (first trajectory, trajectory
+        count, stream, busy ms) as numpy arrays, then the summed layer wall time (ms) and the
+        number of timed layers."""
+        n = lib().mps_schedule_read(self.h, None, None, None, None, None, None, 0)
+        _check(min(n, 0))
+        first = np.zeros(n, dtype=np.int32)
+        count = np.zeros(n, dtype=np.int32)
+        stream = np.zeros(n, dtype=np.int32)
+        busy = np.zeros(n, dtype=np.float64)
+        el = ctypes.c_double()
+        layers = ctypes.c_longlong()
+        _check(min(0, lib().mps_schedule_read(self.h, first.ctypes.data, count.ctypes.data, stream.ctypes.data,
+                                              busy.ctypes.data, ctypes.byref(el), ctypes.byref(layers), n)))
+        return first, count, stream, busy, el.value, layers.value
 
     def apply_layer(self, layer: int, discarded=None, branch=None, w_record=None, w_in=None, branch_in=None):
         """w_in / branch_in (record layouts, device tensors): follow recorded mixings / branches."""

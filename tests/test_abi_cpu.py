@@ -217,3 +217,12 @@ def test_lindblad_constructors_validate_on_the_host():
     assert e.value.code == M.EINVAL
     with pytest.raises(M.MpsbError) as e:
         M.jump_channel([], 0.1)
+
+
+def test_profile_and_schedule_read_validate_on_the_host():
+    """Null handles are rejected before any device work (the handle-level checks that need a
+    device are in the GPU schedule test)."""
+    lib = M.lib()
+    assert lib.mps_profile(None, 2) == M.EINVAL
+    assert lib.mps_profile_read(None, None, None, 0) == M.EINVAL
+    assert lib.mps_schedule_read(None, None, None, None, None, None, None, 0) == M.EINVAL

@@ -81,3 +81,32 @@ def test_tridiag_roofline_is_fp64_flops():
     flops = 16.0 / 3.0 * 256 ** 3 * 2048                     # one m = 256 Gram per trajectory per launch
     assert abs(r["flops_per_launch"] - flops) / flops < 0.02
     assert abs(r["frac"] - r["achieved"] / 78.6) < 1e-12
+
+
+def test_schedule_report_rates_and_utilisation():
+    """Two chi classes, three members; gate-steps come from the gate table (identity -1 past a
+    trajectory's depth is not counted), rates from the members' busy time, utilisation from
+    the summed busy time over streams x elapsed."""
+    import numpy as np
+
+    class MC:
+        pass
+
+    mc = MC()
+    mc.chis = np.array([16, 16, 64, 64, 64])
+    lo, hi = bench.SCHED_LAYERS
+    L = hi + 2
+    mc.gate_id = np.full((5, L, 3), -1)
+    mc.gate_id[:, lo:hi + 1, :2] = 7            # two real gates per trajectory and timed layer
+    mc.gate_id[4, hi, :] = -1                   # trajectory 4 ends before the last timed layer
+    nl = hi - lo + 1
+    first, count = np.array([0, 2, 4]), np.array([2, 2, 1])
+    busy = np.array([2.0, 6.0, 4.0])
+    r = bench.schedule_report(mc, first, count, np.array([0, 1, 2]), busy, 5.0, nl)
+    assert r["members"] == 3 and r["streams"] == 3
+    assert r["per_chi"]["16"]["gate_steps"] == 2 * 2 * nl
+    assert r["per_chi"]["64"]["gate_steps"] == 2 * 2 * nl + 2 * (nl - 1)
+    assert abs(r["per_chi"]["16"]["rate_on_its_streams"] - 4 * nl / 2e-3) < 1e-6
+    assert abs(r["utilisation_busy_over_streams_x_elapsed"] - 12.0 / 15.0) < 1e-12
+    tot = 4 * nl + 4 * nl + 2 * (nl - 1)
+    assert abs(r["rate_all"] - tot / 5e-3) < 1e-6

@@ -166,3 +166,32 @@ def test_trajectory_offset_waves_reproduce_one_batch(prec):
     b = run(T // 2, T // 2)
     assert np.array_equal(np.concatenate([a[1], b[1]]), whole[1])
     assert np.array_equal(np.concatenate([a[0], b[0]]), whole[0])
+
+
+def test_mixed_schedule_timing():
+    """Schedule timing (mps_profile bit 1) of a mixed batch: the members partition the
+    trajectories in order, every timed layer is counted, members with work have positive busy
+    time on one of at most four streams, the busy times fit in four streams' share of the
+    elapsed time, and the timed run (direct launches, streams dealt round-robin) gives the
+    untimed run's observables bit for bit."""
+    from paper_2508_05745_amd import mpsb as M
+    mc = I.mixed_brickwork(40, seed=11, widths=(5, 10), depths=(3, 7), chis=(4, 8, 16), pool_size=64)
+    plain = _run_mixed(mc, 23, 0, False)
+    b = M.Batch(mc.n_traj, mc.widths, mc.chis, 0, 23)
+    b.set_circuit(mc, M.OPTIMAL)
+    b.profile(2)
+    for l in range(mc.depth):
+        b.apply_layer(l)
+    first, count, stream, busy, elapsed, layers = b.schedule_read()
+    _, _, pt = b.expect()
+    b.sync()
+    b.profile(0)
+    b.close()
+    runs = 1 + int(np.count_nonzero((np.diff(mc.widths) != 0) | (np.diff(mc.chis) != 0)))
+    assert len(first) == runs
+    assert first[0] == 0 and np.array_equal(first[1:], np.cumsum(count)[:-1]) and count.sum() == mc.n_traj
+    assert layers == mc.depth and elapsed > 0
+    assert (busy > 0).all() and ((stream >= 0) & (stream < 4)).all()
+    assert busy.sum() <= 4 * elapsed * 1.05 + 0.5
+    print(f"{runs} members, {layers} layers: busy {busy.sum():.2f} ms over {elapsed:.2f} ms elapsed", flush=True)
+    assert np.array_equal(np.nan_to_num(pt.cpu().numpy(), nan=7.0), np.nan_to_num(plain["per_traj"], nan=7.0))
