@@ -268,8 +268,12 @@ int mps_circuit_validate(int n_traj, const int32_t* width, const mpsb_circuit* c
  * leaves the centre at site n-2; the state itself is unchanged).  Device
  * outputs: mean [2n-1] and m2 [2n-1] (sum of squared deviations) over trajectories,
  * reduced in a fixed order (bitwise reproducible), or both NULL; per_traj [n_traj][2W-1]
- * (or NULL), rows NaN-padded past a trajectory's own 2n-1 entries.  A mixed batch
- * reports per_traj only (mean = m2 = NULL, else MPSB_ENOTSUP). */
+ * (or NULL), rows NaN-padded past a trajectory's own 2n-1 entries.  For a mixed batch
+ * (widths up to W) mean and m2 have 2W-1 entries in the widest trajectory's layout (<Z_i> at
+ * i, <Z_i Z_(i+1)> at W + i), each over the trajectories that have that observable (width
+ * > i, resp. > i + 1; NaN where none has it); the members' fixed-order reductions are merged
+ * on the host in trajectory order (pairwise mean / M2 update), so the result is bitwise
+ * reproducible too. */
 int expect(mpsb_handle h, double* mean, double* m2, double* per_traj);
 
 /* Optional per-kernel-class timing with HIP events recorded on the batch stream (for

@@ -155,7 +155,9 @@ hipError_t fill_nan(double* per_traj, int stride, int c0, int n_traj, hipStream_
 hipError_t err_accumulate(int n_traj, int slots, const double* disc, int kind, double weight, double* eps_tot,
                           hipStream_t st);
 hipError_t err_estimate(int n_traj, const double* eps_tot, double eps_max, double delta, double* out, hipStream_t st);
-hipError_t obs_reduce(const double* per_traj, int n_obs, int n_traj, double* mean, double* m2, hipStream_t st);
+// rows of per_traj are stride doubles apart (stride >= n_obs)
+hipError_t obs_reduce(const double* per_traj, int n_obs, int stride, int n_traj, double* mean, double* m2,
+                      hipStream_t st);
 
 // unravelling cost
 hipError_t cost_rho(int batch, const void* theta, int chi_l, int chi_r, int prec, double* rho, hipStream_t st);

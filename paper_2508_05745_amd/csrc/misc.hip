@@ -195,12 +195,13 @@ hipError_t obs_pair(const double* partial, int n_tiles, int i, int n, double* pe
   return hipGetLastError();
 }
 
-__global__ void k_obs_reduce(const double* __restrict__ per_traj, int n_obs, int n_traj, double* mean, double* m2) {
+__global__ void k_obs_reduce(const double* __restrict__ per_traj, int n_obs, int stride, int n_traj, double* mean,
+                             double* m2) {
   __shared__ double sn[256], sm[256], sq[256];
   const int o = blockIdx.x, tid = threadIdx.x;
   double n = 0, mu = 0, q = 0;
   for (int t = tid; t < n_traj; t += 256) {
-    double x = per_traj[(long long)t * n_obs + o];
+    double x = per_traj[(long long)t * stride + o];
     n += 1;
     double d = x - mu;
     mu += d / n;
@@ -227,8 +228,9 @@ __global__ void k_obs_reduce(const double* __restrict__ per_traj, int n_obs, int
   }
 }
 
-hipError_t obs_reduce(const double* per_traj, int n_obs, int n_traj, double* mean, double* m2, hipStream_t st) {
-  hipLaunchKernelGGL(k_obs_reduce, dim3(n_obs), dim3(256), 0, st, per_traj, n_obs, n_traj, mean, m2);
+hipError_t obs_reduce(const double* per_traj, int n_obs, int stride, int n_traj, double* mean, double* m2,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_obs_reduce, dim3(n_obs), dim3(256), 0, st, per_traj, n_obs, stride, n_traj, mean, m2);
   return hipGetLastError();
 }
 

@@ -1747,7 +1747,7 @@ int expect_uniform(mpsb_batch* h, double* mean, double* m2, double* per_traj, in
   h->prof.on = prof_on;
   if (r) return r;
   if (stride > nobs) HIPCHK(fill_nan(obs, stride, nobs, T, h->st));
-  if (mean) HIPCHK(obs_reduce(obs, nobs, T, mean, m2, h->st));
+  if (mean) HIPCHK(obs_reduce(obs, nobs, stride, T, mean, m2, h->st));
   return MPSB_OK;
 }
 }  // namespace
@@ -1761,13 +1761,40 @@ int expect(mpsb_handle h, double* mean, double* m2, double* per_traj) {
     if (!mean && !per_traj) return fail(MPSB_EINVAL, "no output");
     return expect_uniform(h, mean, m2, per_traj, 2 * h->L.n - 1);
   }
-  if (mean) return fail(MPSB_ENOTSUP, "a mixed batch reports per-trajectory observables only (mean = m2 = NULL)");
-  if (!per_traj) return fail(MPSB_EINVAL, "null per_traj");
-  const int stride = 2 * h->rec_stride - 1;
+  if (!mean && !per_traj) return fail(MPSB_EINVAL, "no output");
+  const int Wd = h->rec_stride, stride = 2 * Wd - 1;
+  // trajectory mean and M2 in the widest trajectory's layout: each member's own (fixed-order
+  // device reduction, written into the caller's mean / m2 as scratch) merged on the host in
+  // member order with the pairwise update of Chan et al.; a slot counts the trajectories
+  // that have the observable (Z_i: width > i, Z_i Z_(i+1): width > i + 1)
+  std::vector<double> cnt(mean ? stride : 0, 0.0), mu(mean ? stride : 0, 0.0), sq(mean ? stride : 0, 0.0);
+  std::vector<double> mb, qb;
   for (mpsb_batch* b : h->sub) {
     b->st = h->st;
-    int r = expect_uniform(b, nullptr, nullptr, per_traj + (size_t)b->traj_base * stride, stride);
+    int r = expect_uniform(b, mean, m2, per_traj ? per_traj + (size_t)b->traj_base * stride : nullptr, stride);
     if (r) return r;
+    if (!mean) continue;
+    const int nb = b->L.n, nob = 2 * nb - 1;
+    const double tb = (double)b->L.n_traj;
+    mb.resize(nob);
+    qb.resize(nob);
+    HIPCHK(hipMemcpyAsync(mb.data(), mean, sizeof(double) * nob, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipMemcpyAsync(qb.data(), m2, sizeof(double) * nob, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    for (int k = 0; k < nob; ++k) {
+      const int slot = k < nb ? k : Wd + (k - nb);
+      const double na = cnt[slot], nab = na + tb, dlt = mb[k] - mu[slot];
+      mu[slot] += dlt * tb / nab;
+      sq[slot] += qb[k] + dlt * dlt * na * tb / nab;
+      cnt[slot] = nab;
+    }
+  }
+  if (mean) {
+    for (int k = 0; k < stride; ++k)
+      if (cnt[k] == 0) mu[k] = sq[k] = std::nan("");
+    HIPCHK(hipMemcpyAsync(mean, mu.data(), sizeof(double) * stride, hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipMemcpyAsync(m2, sq.data(), sizeof(double) * stride, hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
   }
   return MPSB_OK;
 }

@@ -277,14 +277,13 @@ class Batch:
         return bits
 
     def expect(self, per_traj: bool = True):
-        """(mean, m2, per_traj) of <Z_i> (n) then <Z_i Z_i+1> (n-1), float64 CUDA tensors.
-        A mixed batch returns (None, None, per_traj [n_traj][2W-1], NaN-padded)."""
+        """(mean, m2, per_traj) of <Z_i> (n) then <Z_i Z_i+1> (n-1), float64 CUDA tensors
+        (per_traj None unless asked for).  A mixed batch (widths up to W) uses the widest
+        trajectory's layout: per_traj [n_traj][2W-1] NaN-padded rows, mean / m2 over the
+        trajectories that have each observable (NaN where none has it)."""
         import torch
         nobs = 2 * self.n - 1
-        pt = torch.empty((self.n_traj, nobs), dtype=torch.float64, device="cuda") if (per_traj or self.mixed) else None
-        if self.mixed:
-            _check(lib().expect(self.h, None, None, _ptr(pt)))
-            return None, None, pt
+        pt = torch.empty((self.n_traj, nobs), dtype=torch.float64, device="cuda") if per_traj else None
         mean = torch.empty(nobs, dtype=torch.float64, device="cuda")
         m2 = torch.empty(nobs, dtype=torch.float64, device="cuda")
         _check(lib().expect(self.h, _ptr(mean), _ptr(m2), _ptr(pt)))

@@ -195,3 +195,43 @@ def test_mixed_schedule_timing():
     assert busy.sum() <= 4 * elapsed * 1.05 + 0.5
     print(f"{runs} members, {layers} layers: busy {busy.sum():.2f} ms over {elapsed:.2f} ms elapsed", flush=True)
     assert np.array_equal(np.nan_to_num(pt.cpu().numpy(), nan=7.0), np.nan_to_num(plain["per_traj"], nan=7.0))
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_mixed_batch_mean_and_m2(prec):
+    """expect on a mixed batch: mean and M2 in the widest trajectory's layout over the
+    trajectories that have each observable (<Z_i>: width > i, <Z_i Z_(i+1)>: width > i + 1),
+    against a two-pass NumPy mean / M2 of the per-trajectory rows (each row in its own width's
+    layout); a second call (without rows, after the first sweep has moved the centres, so the
+    state is in another gauge) agrees to rounding."""
+    from paper_2508_05745_amd import mpsb as M
+    mc = I.mixed_brickwork(40, seed=11, widths=(5, 10), depths=(3, 7), chis=(4, 8, 16), pool_size=64)
+    b = M.Batch(mc.n_traj, mc.widths, mc.chis, prec, 23)
+    b.set_circuit(mc, M.OPTIMAL)
+    for l in range(mc.depth):
+        b.apply_layer(l)
+    mean, m2, pt = b.expect()
+    mean2, m22, _ = b.expect(per_traj=False)
+    b.sync()
+    b.close()
+    mean, m2, pt = mean.cpu().numpy(), m2.cpu().numpy(), pt.cpu().numpy()
+    tol = 1e-12 if prec == 1 else 1e-5
+    fin = np.isfinite(mean)
+    assert np.array_equal(fin, np.isfinite(mean2.cpu().numpy()))
+    assert np.abs(mean[fin] - mean2.cpu().numpy()[fin]).max() < tol
+    assert np.abs(m2[fin] - m22.cpu().numpy()[fin]).max() < tol * mc.n_traj
+    W = mc.n
+    for k in range(2 * W - 1):
+        vals = []
+        for t in range(mc.n_traj):
+            n = int(mc.widths[t])
+            if k < W and k < n:
+                vals.append(pt[t, k])
+            elif k >= W and k - W < n - 1:
+                vals.append(pt[t, n + k - W])
+        if not vals:
+            assert np.isnan(mean[k]) and np.isnan(m2[k]), k
+            continue
+        v = np.array(vals)
+        assert abs(mean[k] - v.mean()) < 1e-13, k
+        assert abs(m2[k] - ((v - v.mean()) ** 2).sum()) < 1e-12 * max(1.0, len(v)), k
