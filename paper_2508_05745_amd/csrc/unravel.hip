@@ -31,7 +31,11 @@ __device__ inline double cabs_(cd a) { return sqrt(norm2(a)); }
 // cyclic Jacobi eigen-decomposition of a real symmetric n x n matrix (n <= NMAX), in place:
 // on exit a holds the eigenvalues on its diagonal, v the eigenvectors (columns).  The sweeps run
 // on local copies with every index fixed at compile time (pairs and rows unrolled over NMAX,
-// n as a guard), so that the matrices stay in registers rather than in per-lane scratch.
+// n as a guard), so that the matrices stay in registers rather than in per-lane scratch.  A
+// pair is rotated only while its off-diagonal entry is not negligible against its diagonal
+// entries (|a_pq| > eps (|a_pp| + |a_qq|) / 2), and the iteration stops after a sweep without a
+// rotation (a test on the summed off-diagonal mass alone can stall above its threshold at
+// rounding level and run every sweep).
 template <int NMAX>
 __device__ void jacobi_sym(int n, double (&a_io)[NMAX][NMAX], double (&v_io)[NMAX][NMAX]) {
   double a[NMAX][NMAX], v[NMAX][NMAX];
@@ -52,12 +56,14 @@ __device__ void jacobi_sym(int n, double (&a_io)[NMAX][NMAX], double (&v_io)[NMA
         if (i != j) off += a[i][j] * a[i][j];
       }
     if (off <= 1e-34 * tot || off == 0.0) break;
+    bool rotated = false;
 #pragma unroll
     for (int p = 0; p < NMAX - 1; ++p)
 #pragma unroll
       for (int q = p + 1; q < NMAX; ++q) {
         const double apq = a[p][q];
-        if (q < n && apq != 0.0) {
+        if (q < n && fabs(apq) > DBL_EPSILON * 0.5 * (fabs(a[p][p]) + fabs(a[q][q])) && fabs(apq) > 1e-300) {
+          rotated = true;
           double zeta = (a[q][q] - a[p][p]) / (2.0 * apq);
           double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
@@ -81,6 +87,7 @@ __device__ void jacobi_sym(int n, double (&a_io)[NMAX][NMAX], double (&v_io)[NMA
           }
         }
       }
+    if (!rotated) break;
   }
 #pragma unroll
   for (int i = 0; i < NMAX; ++i)
@@ -161,8 +168,10 @@ __device__ void optimal_mixing(const cd (&rho)[2][2], const cd (&K)[4][2][2], in
           be += norm2(ph[c][j]);
           ga = ga + cmulc(ph[c][i], ph[c][j]);
         }
+        // columns orthogonal to working precision: no rotation (a relative 1e-17 test below the
+        // rounding level of the products would keep every sweep rotating)
         double g = cabs_(ga);
-        if (g <= 1e-17 * sqrt(al * be) || g == 0.0) continue;
+        if (g <= 2.0 * DBL_EPSILON * sqrt(al * be) || g == 0.0) continue;
         rotated = true;
         cd eph = {ga.re / g, -ga.im / g};   // e^{-i phi}
         double zeta = (be - al) / (2.0 * g);
