@@ -99,14 +99,6 @@ __device__ void jacobi_sym(int n, double (&a_io)[NMAX][NMAX], double (&v_io)[NMA
       }
 }
 
-__device__ inline int first_argmax_c(const cd* a, int n, int stride) {
-  double mx = 0;
-  for (int i = 0; i < n; ++i) mx = fmax(mx, cabs_(a[i * stride]));
-  for (int i = 0; i < n; ++i)
-    if (cabs_(a[i * stride]) >= mx * (1.0 - 1e-12)) return i;
-  return 0;
-}
-
 __device__ inline cd yy_flip(const cd (&v)[4], int i) {
   // (Y x Y) v*:  [ -v3*, v2*, v1*, -v0* ]
   switch (i) {
@@ -189,21 +181,34 @@ __device__ void optimal_mixing(const cd (&rho)[2][2], const cd (&K)[4][2][2], in
       }
     if (!rotated) break;
   }
-  double sig[4];
+  // singular values in descending order: the exchange sort of the indices, on register copies
+  double sv[4];
   int ord[4];
+#pragma unroll
   for (int i = 0; i < 4; ++i) {
     double s2 = 0;
+#pragma unroll
     for (int c = 0; c < 4; ++c) s2 += norm2(ph[c][i]);
-    sig[i] = (i < r) ? sqrt(s2) : -1.0;
+    sv[i] = (i < r) ? sqrt(s2) : -1.0;
     ord[i] = i;
   }
+#pragma unroll
   for (int i = 0; i < 4; ++i)
+#pragma unroll
     for (int j = i + 1; j < 4; ++j)
-      if (sig[ord[j]] > sig[ord[i]]) { int t = ord[i]; ord[i] = ord[j]; ord[j] = t; }
-  const double smax = sig[ord[0]];
+      if (sv[j] > sv[i]) {
+        const double tv = sv[i];
+        sv[i] = sv[j];
+        sv[j] = tv;
+        const int ti = ord[i];
+        ord[i] = ord[j];
+        ord[j] = ti;
+      }
+  const double smax = sv[0];
   int rank = 0;
-  for (int i = 0; i < r; ++i)
-    if (sig[ord[i]] > 1e-12 * smax) rank++;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (i < r && sv[i] > 1e-12 * smax) rank++;
   cd v[4][4];    // [component][k], k < rank
   cd Vs[4][4];   // sorted V columns
 #pragma unroll
@@ -220,100 +225,168 @@ __device__ void optimal_mixing(const cd (&rho)[2][2], const cd (&K)[4][2][2], in
       v[c][k] = (k < rank) ? pv : cz();
       Vs[c][k] = vv;
     }
-  // tau = v^dag v~  (rank x rank)
+  // From here on every array index is fixed at compile time (loops over the padded size 4
+  // or 8 with the rank as a guard, gathers by selects), so that the arrays stay in registers
+  // instead of per-lane scratch memory.
+  // tau = v^dag v~ (zero outside its rank x rank block)
   cd tau[4][4];
-  for (int a = 0; a < rank; ++a)
-    for (int b = 0; b < rank; ++b) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
       cd vb[4] = {v[0][b], v[1][b], v[2][b], v[3][b]};
       cd acc = cz();
+#pragma unroll
       for (int c = 0; c < 4; ++c) acc = acc + cmulc(v[c][a], yy_flip(vb, c));
-      tau[a][b] = acc;
+      tau[a][b] = (a < rank && b < rank) ? acc : cz();
     }
-  for (int a = 0; a < rank; ++a)
-    for (int b = a + 1; b < rank; ++b) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a + 1; b < 4; ++b) {
       cd m = {0.5 * (tau[a][b].re + tau[b][a].re), 0.5 * (tau[a][b].im + tau[b][a].im)};
       tau[a][b] = m;
       tau[b][a] = m;
     }
-  // Takagi via the real embedding
+  // Takagi via the real embedding [[A, B], [B, -A]] of tau = A + iB in fixed blocks of 4 (the
+  // rows and columns of the padding beyond the rank are zero and never rotated, so the
+  // embedding of the rank block keeps its eigenpairs and the padding adds exact unit vectors)
   double E[8][8], Q[8][8];
-  const int m2 = 2 * rank;
-  for (int a = 0; a < rank; ++a)
-    for (int b = 0; b < rank; ++b) {
-      E[a][b] = tau[a][b].re;
-      E[a][rank + b] = tau[a][b].im;
-      E[rank + a][b] = tau[a][b].im;
-      E[rank + a][rank + b] = -tau[a][b].re;
-    }
-  jacobi_sym<8>(m2, E, Q);
-  int eo[8];
-  for (int i = 0; i < m2; ++i) eo[i] = i;
-  for (int i = 0; i < m2; ++i)
-    for (int j = i + 1; j < m2; ++j)
-      if (E[eo[j]][eo[j]] > E[eo[i]][eo[i]]) { int t = eo[i]; eo[i] = eo[j]; eo[j] = t; }
-  double emax = 0;
-  for (int i = 0; i < m2; ++i) emax = fmax(emax, fabs(E[i][i]));
-  cd UT[4][4];   // [row][col]
+#pragma unroll
   for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) UT[a][b] = cz();
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      E[a][b] = tau[a][b].re;
+      E[a][4 + b] = tau[a][b].im;
+      E[4 + a][b] = tau[a][b].im;
+      E[4 + a][4 + b] = -tau[a][b].re;
+    }
+  jacobi_sym<8>(8, E, Q);
+  double ev8[8];
+  double emax = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    ev8[i] = E[i][i];
+    emax = fmax(emax, fabs(ev8[i]));
+  }
+  // columns of U_T: the positive eigenvalues in descending order (ties: lower index), at most
+  // rank of them, each eigenvector [a; b] giving the Takagi vector a + ib (unit norm)
+  cd UT[4][4];
   double lam[4] = {0, 0, 0, 0};
   int kpos = 0;
-  for (int i = 0; i < rank; ++i) {
-    int idx = eo[i];
-    if (!(E[idx][idx] > 1e-12 * emax)) break;
+  unsigned taken = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int idx = -1;
+    double best = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (!((taken >> i) & 1u) && (idx < 0 || ev8[i] > best)) {
+        idx = i;
+        best = ev8[i];
+      }
+    const bool use = kpos == k && k < rank && best > 1e-12 * emax;
+    double qr[4], qi[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) qr[a] = qi[a] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i == idx) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          qr[a] = Q[a][i];
+          qi[a] = Q[4 + a][i];
+        }
+      }
     double nn = 0;
-    for (int a = 0; a < rank; ++a) nn += Q[a][idx] * Q[a][idx] + Q[rank + a][idx] * Q[rank + a][idx];
-    nn = 1.0 / sqrt(nn);
-    for (int a = 0; a < rank; ++a) UT[a][kpos] = cd{Q[a][idx] * nn, Q[rank + a][idx] * nn};
-    lam[kpos] = E[idx][idx];
-    kpos++;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (a < rank) nn += qr[a] * qr[a] + qi[a] * qi[a];
+    nn = nn > 0 ? 1.0 / sqrt(nn) : 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) UT[a][k] = (use && a < rank) ? cd{qr[a] * nn, qi[a] * nn} : cz();
+    lam[k] = use ? best : 0.0;
+    if (use) {
+      kpos = k + 1;
+      taken |= 1u << idx;
+    }
   }
-  // null directions: from eigenvectors of the embedding with ~0 eigenvalue, pivoted
-  // complex Gram-Schmidt against the chosen columns
-  while (kpos < rank) {
+  // null directions (tau singular on the rank block): eigenvectors of the embedding with ~0
+  // eigenvalue, complex Gram-Schmidt against the chosen columns, the largest residual taken
+  bool nostop = true;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (!(nostop && k == kpos && k < rank)) continue;
     double best = -1;
-    cd cand[4];
-    for (int i = 0; i < m2; ++i) {
-      int idx = eo[i];
-      if (E[idx][idx] > 1e-12 * emax || E[idx][idx] < -1e-12 * emax) continue;
+    cd cand[4] = {cz(), cz(), cz(), cz()};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (ev8[i] > 1e-12 * emax || ev8[i] < -1e-12 * emax) continue;
       cd u[4];
-      for (int a = 0; a < rank; ++a) u[a] = cd{Q[a][idx], Q[rank + a][idx]};
-      for (int k = 0; k < kpos; ++k) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) u[a] = a < rank ? cd{Q[a][i], Q[4 + a][i]} : cz();
+#pragma unroll
+      for (int kk = 0; kk < k; ++kk) {
         cd pr = cz();
-        for (int a = 0; a < rank; ++a) pr = pr + cmulc(UT[a][k], u[a]);
-        for (int a = 0; a < rank; ++a) u[a] = u[a] - pr * UT[a][k];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) pr = pr + cmulc(UT[a][kk], u[a]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) u[a] = u[a] - pr * UT[a][kk];
       }
       double nn = 0;
-      for (int a = 0; a < rank; ++a) nn += norm2(u[a]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) nn += norm2(u[a]);
       if (nn > best) {
         best = nn;
-        for (int a = 0; a < rank; ++a) cand[a] = u[a];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) cand[a] = u[a];
       }
     }
-    if (best <= 1e-20) break;
-    double inv = 1.0 / sqrt(best);
-    for (int a = 0; a < rank; ++a) UT[a][kpos] = inv * cand[a];
-    lam[kpos] = 0.0;
-    kpos++;
+    if (best <= 1e-20) {
+      nostop = false;
+      continue;
+    }
+    const double inv = 1.0 / sqrt(best);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) UT[a][k] = inv * cand[a];
+    lam[k] = 0.0;
+    kpos = k + 1;
   }
-  // x = v U_T with the sign / phase pins
+  // x = v U_T with the sign / phase pins: the first entry of largest modulus of column k made
+  // real positive (sigma > 0: sign only; sigma = 0: its phase)
   cd x[4][4];
+#pragma unroll
   for (int k = 0; k < 4; ++k)
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
       cd acc = cz();
-      if (k < kpos)
-        for (int a = 0; a < rank; ++a) cfma(acc, v[c][a], UT[a][k]);
-      x[c][k] = acc;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a < rank) cfma(acc, v[c][a], UT[a][k]);
+      x[c][k] = k < kpos ? acc : cz();
     }
-  for (int k = 0; k < kpos; ++k) {
-    int i = first_argmax_c(&x[0][k], 4, 4);
-    cd e = x[i][k];
-    double ae = cabs_(e);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k >= kpos) continue;
+    double mx = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) mx = fmax(mx, cabs_(x[c][k]));
+    int i = -1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (i < 0 && cabs_(x[c][k]) >= mx * (1.0 - 1e-12)) i = c;
+    cd e = x[0][k];
+#pragma unroll
+    for (int c = 1; c < 4; ++c)
+      if (c == i) e = x[c][k];
+    const double ae = cabs_(e);
     if (ae == 0.0) continue;
     cd f;
     if (lam[k] > 0.0) f = (e.re < 0.0 || (e.re == 0.0 && e.im < 0.0)) ? cd{-1.0, 0.0} : cd{1.0, 0.0};
     else f = cd{e.re / ae, -e.im / ae};
-    for (int a = 0; a < rank; ++a) UT[a][k] = UT[a][k] * f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) UT[a][k] = UT[a][k] * f;
+#pragma unroll
     for (int c = 0; c < 4; ++c) x[c][k] = x[c][k] * f;
   }
   const double cdiff = lam[0] - lam[1] - lam[2] - lam[3];
@@ -324,45 +397,85 @@ __device__ void optimal_mixing(const cd (&rho)[2][2], const cd (&K)[4][2][2], in
   if (cdiff > 0.0) {
     const cd u2[4] = {{1, 0}, {0, -1}, {0, -1}, {0, -1}};
     cd y[4][4];
+#pragma unroll
     for (int c = 0; c < 4; ++c)
+#pragma unroll
       for (int k = 0; k < 4; ++k) y[c][k] = x[c][k] * u2[k];
     double MR[4][4], QR[4][4];
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
       for (int b = 0; b < 4; ++b) {
         cd yb[4] = {y[0][b], y[1][b], y[2][b], y[3][b]};
         cd s1 = cz(), s2 = cz();
+#pragma unroll
         for (int c = 0; c < 4; ++c) {
           s1 = s1 + cmulc(y[c][a], yy_flip(yb, c));
           s2 = s2 + cmulc(y[c][a], y[c][b]);
         }
         MR[a][b] = s1.re - conc * s2.re;
       }
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
       for (int b = a + 1; b < 4; ++b) {
         double m = 0.5 * (MR[a][b] + MR[b][a]);
         MR[a][b] = MR[b][a] = m;
       }
     jacobi_sym<4>(4, MR, QR);
-    int qo[4] = {0, 1, 2, 3};
-    for (int i = 0; i < 4; ++i)
-      for (int j = i + 1; j < 4; ++j)
-        if (MR[qo[j]][qo[j]] < MR[qo[i]][qo[i]]) { int t = qo[i]; qo[i] = qo[j]; qo[j] = t; }
-    double Qs[4][4];
-    for (int k = 0; k < 4; ++k) {
-      int col = qo[k];
-      double mx = 0;
-      for (int a = 0; a < 4; ++a) mx = fmax(mx, fabs(QR[a][col]));
-      int ia = 0;
-      for (int a = 0; a < 4; ++a)
-        if (fabs(QR[a][col]) >= mx * (1.0 - 1e-12)) { ia = a; break; }
-      double sg = QR[ia][col] < 0 ? -1.0 : 1.0;
-      for (int a = 0; a < 4; ++a) Qs[a][k] = sg * QR[a][col];
+    // eigenvalues ascending: the exchange sort of the indices, on register copies
+    double qv[4];
+    int qo[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      qv[i] = MR[i][i];
+      qo[i] = i;
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 4; ++j)
+        if (qv[j] < qv[i]) {
+          const double tv = qv[i];
+          qv[i] = qv[j];
+          qv[j] = tv;
+          const int ti = qo[i];
+          qo[i] = qo[j];
+          qo[j] = ti;
+        }
+    double Qs[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double col[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (qo[k] == t) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a) col[a] = QR[a][t];
+        }
+      double mx = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) mx = fmax(mx, fabs(col[a]));
+      double lead = col[0];
+      bool found = false;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (!found && fabs(col[a]) >= mx * (1.0 - 1e-12)) {
+          lead = col[a];
+          found = true;
+        }
+      const double sg = lead < 0 ? -1.0 : 1.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) Qs[a][k] = sg * col[a];
+    }
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
       for (int cc = 0; cc < 4; ++cc) {
-        double s = 0;
-        for (int b = 0; b < 4; ++b) s += Qs[a][b] * H4[cc][b];
-        Em[a][cc] = u2[a] * cd{s, 0.0};
+        double sum = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) sum += Qs[a][b] * H4[cc][b];
+        Em[a][cc] = u2[a] * cd{sum, 0.0};
       }
   } else {
     double l1 = lam[0], l2 = lam[1], l3 = lam[2], l4 = lam[3];
@@ -370,30 +483,38 @@ __device__ void optimal_mixing(const cd (&rho)[2][2], const cd (&K)[4][2][2], in
     if (l1 - l4 <= 1e-15 * fmax(l1, 1e-300)) {
       th[0] = 0; th[1] = M_PI / 4; th[2] = M_PI / 2; th[3] = 3 * M_PI / 4;
     } else {
-      double base = l1 - l4, s = 0.5 * (base + l2 + l3);
-      double area2 = fmax(0.0, s * (s - base) * (s - l2) * (s - l3));
+      double base = l1 - l4, sp = 0.5 * (base + l2 + l3);
+      double area2 = fmax(0.0, sp * (sp - base) * (sp - l2) * (sp - l3));
       double hh = 2.0 / base * sqrt(area2);
       double t2 = (l2 > 0) ? M_PI - asin(fmin(1.0, hh / l2)) : M_PI;
       double cr = (l4 - l1) - l2 * cos(t2), ci = -l2 * sin(t2);
       double t3 = (cr != 0.0 || ci != 0.0) ? atan2(ci, cr) : 0.0;
       th[0] = 0; th[1] = 0.5 * t2; th[2] = 0.5 * t3; th[3] = M_PI / 2;
     }
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
       for (int cc = 0; cc < 4; ++cc) Em[a][cc] = cd{cos(th[a]) * H4[a][cc], sin(th[a]) * H4[a][cc]};
   }
   // W = Vs[:, :rank] U_T E[:rank] + Vs[:, rank:r] E[rank:r]
+#pragma unroll
   for (int i = 0; i < 4; ++i)
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
       cd acc = cz();
-      if (i < r) {
-        for (int a = 0; a < rank; ++a) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (a < rank) {
           cd ue = cz();
-          for (int k = 0; k < rank; ++k) cfma(ue, UT[a][k], Em[k][j]);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (k < rank) cfma(ue, UT[a][k], Em[k][j]);
           cfma(acc, Vs[i][a], ue);
+        } else if (a < r) {
+          cfma(acc, Vs[i][a], Em[a][j]);
         }
-        for (int a = rank; a < r; ++a) cfma(acc, Vs[i][a], Em[a][j]);
       }
-      out.W[i][j] = acc;
+      out.W[i][j] = i < r ? acc : cz();
     }
   out.conc = conc;
   out.separable = cdiff > 0.0 ? 0 : 1;
