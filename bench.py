@@ -450,9 +450,9 @@ SCHED_LAYERS = (8, 11)
 def schedule_report(mc, first, count, stream, busy, elapsed, layers):
     """Per-chi-class rates and stream utilisation from the member schedule of timed layers.
     A member's gate-steps are the real gates (not the identity padding past a trajectory's own
-    depth) of its trajectories in those layers.  rate of a chi class = its trajectory gate-steps / its members' summed busy time (the rate
-    of the class on the stream slots it occupied); utilisation = summed busy time / (streams x
-    elapsed)."""
+    depth) of its trajectories in those layers.  The rate of a chi class is its trajectory
+    gate-steps over its members' summed busy time (the rate of the class on the stream slots it
+    occupied); utilisation = summed busy time / (streams x elapsed)."""
     lo, hi = SCHED_LAYERS
     ns = min(4, len(first))
     per = {}
@@ -466,7 +466,8 @@ def schedule_report(mc, first, count, stream, busy, elapsed, layers):
         d[2] += 1
         total += g
     return {
-        "layers": [lo, hi], "members": int(len(first)), "streams": ns, "assignment": "round-robin over the members sorted by (chi, width)",
+        "layers": [lo, hi], "layers_timed": int(layers), "members": int(len(first)), "streams": ns,
+        "assignment": "round-robin over the members sorted by (chi, width)",
         "elapsed_ms": elapsed, "busy_ms": float(np.sum(busy)),
         "utilisation_busy_over_streams_x_elapsed": float(np.sum(busy) / (ns * elapsed)) if elapsed > 0 else None,
         "rate_all": total / (elapsed * 1e-3) if elapsed > 0 else None,

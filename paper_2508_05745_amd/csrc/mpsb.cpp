@@ -1146,7 +1146,6 @@ void sched_collect(mpsb_batch* h) {
   h->sched_used = 0;
 }
 
-
 // Enqueues one layer of every member batch on stream S (members of a mixed batch on the
 // private streams, forked from and joined back into S), then advances the layer counter.
 int enqueue_layer(mpsb_batch* h, int layer, hipStream_t S, double* discarded, int32_t* branch, double* w_record,
@@ -1161,6 +1160,10 @@ int enqueue_layer(mpsb_batch* h, int layer, hipStream_t S, double* discarded, in
     b->ent_rows = h->entropy ? h->entropy + (size_t)b->traj_base * dstr : nullptr;
   };
   const bool timed = h->sched_on && !capturing;
+  // timed layers run directly on the caller's stream, into which every earlier layer's streams
+  // are joined: the pending records are complete once it is synchronised, so the event pool is
+  // emptied here (never inside a layer) when it has grown large
+  if (timed && h->sched_used > 8192) sched_collect(h);
   if (h->sub.empty()) {
     hipStream_t keep = h->st;
     h->st = S;
