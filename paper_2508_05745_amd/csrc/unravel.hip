@@ -674,9 +674,9 @@ constexpr int EV_SPREAD = 8;
 __global__ __launch_bounds__(64) void k_gate_events(EventArgs ea, const double* __restrict__ partial, int n_tiles, int q, int has_s, int has_t,
                               double* __restrict__ kops, int* __restrict__ status) {
   // EV_SPREAD trajectories per wave (one lane each, the other lanes idle): the per-lane work
-  // is long and latency-bound (its small eigensolvers index their arrays at run time, so the
-  // arrays live in scratch), so spreading the waves over all CUs shortens the launch; 8 per
-  // wave measured fastest (16 leaves half the CUs idle, 4 and 2 add waves without gain)
+  // is a long dependent chain (the small eigensolvers of two noise events) with a large
+  // register footprint, so spreading the waves over all CUs shortens the launch; 8 per wave
+  // measured fastest (16 leaves half the CUs idle, 4 and 2 add waves without gain)
   if (threadIdx.x % (64 / EV_SPREAD)) return;
   int traj = blockIdx.x * EV_SPREAD + threadIdx.x / (64 / EV_SPREAD);
   if (traj >= ea.n_traj) return;
