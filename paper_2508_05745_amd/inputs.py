@@ -63,6 +63,15 @@ def amplitude_damping(gamma: float) -> np.ndarray:
     return np.stack([k0, k1])
 
 
+def random_channel(r: int, seed: int) -> np.ndarray:
+    """A seeded random single-qubit channel with r Kraus operators: the r 2 x 2 blocks of a
+    random 2r x 2 isometry (QR of a complex Gaussian matrix), so that sum K^dag K = I."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((2 * r, 2)) + 1j * rng.standard_normal((2 * r, 2))
+    q, _ = np.linalg.qr(z)
+    return q.reshape(r, 2, 2).astype(np.complex128)
+
+
 def compose(first: np.ndarray, second: np.ndarray) -> np.ndarray:
     """Kraus set of ``second o first``: all products K2_j K1_i (j major)."""
     return np.stack([k2 @ k1 for k2 in second for k1 in first])

@@ -20,10 +20,12 @@ CHANNELS = {
 }
 
 
-@pytest.mark.parametrize("name", sorted(CHANNELS))
+@pytest.mark.parametrize("name", sorted(CHANNELS) + ["random_r2", "random_r3", "random_r4"])
 def test_unravel_opt_matches_oracle(name):
+    """The standard channels (degenerate spectra) and seeded random channels of 2, 3 and 4
+    Kraus operators (generic spectra), on random mixed and pure states and on I/2."""
     from paper_2508_05745_amd import mpsb as M
-    k = CHANNELS[name]
+    k = CHANNELS[name] if name in CHANNELS else I.random_channel(int(name[-1]), 5000 + int(name[-1]))
     B = 300
     rho = np.stack([I.random_density_matrices(1, 1000 + t, rank=1 if t % 11 == 0 else 2)[0]
                     for t in range(B)])

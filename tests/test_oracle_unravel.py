@@ -157,7 +157,9 @@ def test_dephasing_worked_example_mixing_convention():
 
 @pytest.mark.parametrize("chan", [I.depolarizing(0.02), I.amplitude_damping(0.3),
                                   I.dephasing(0.2), I.depolarizing(0.8),
-                                  I.compose(I.amplitude_damping(0.05), I.dephasing(0.05))])
+                                  I.compose(I.amplitude_damping(0.05), I.dephasing(0.05)),
+                                  I.random_channel(2, 5002), I.random_channel(3, 5003),
+                                  I.random_channel(4, 5004)])
 def test_random_states_reach_eof(chan):
     """On random single-qubit reduced states: E_av of the returned decomposition equals
     the Hill-Wootters EoF (via the Takagi lambdas) to 1e-12, the concurrence agrees with
@@ -176,17 +178,29 @@ def test_random_states_reach_eof(chan):
         assert np.allclose(p, out["p"], atol=1e-14)
 
 
-def test_brute_force_never_below_eof():
+@pytest.mark.parametrize("chan", [I.depolarizing(0.1), I.random_channel(3, 5003)])
+def test_brute_force_never_below_eof(chan):
     """Random unitary mixings never beat the returned optimum."""
     rng = np.random.default_rng(5)
-    chan = I.depolarizing(0.1)
+    r = len(chan)
     for t in range(5):
         rho = I.random_density_matrices(1, 100 + t)[0]
         eof = U.optimal_mixing(rho, chan)["eof"]
         for _ in range(400):
-            u = I.haar_unitary(rng, 4)
+            u = I.haar_unitary(rng, r)
             _, eav = U.average_entanglement(rho, U.mixed_kraus(chan, u.T))
             assert eav >= eof - 1e-12
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_random_channel_is_a_complete_kraus_set(r):
+    """The seeded random channel generator: r Kraus operators with sum K^dag K = I, the same
+    operators for the same seed, other operators for another seed."""
+    k = I.random_channel(r, 17)
+    assert k.shape == (r, 2, 2)
+    assert np.abs(sum(x.conj().T @ x for x in k) - np.eye(2)).max() < 1e-14
+    assert np.array_equal(k, I.random_channel(r, 17))
+    assert not np.allclose(k, I.random_channel(r, 18))
 
 
 def test_bell_depolarizing_u_theta_phi_grid_never_below_eof():
