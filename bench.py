@@ -47,8 +47,9 @@ if ROOT not in sys.path:
 PROF_NAMES = ["theta", "events", "kraus_pair", "gram", "tridiag", "tri_eig", "hop_eig", "backtransform",
               "recompose", "hop", "idle", "expect", "tridiag_s", "tridiag_l", "backtransform_l"]
 # kernel instance timed by each single-instance class
-KERNEL = {"theta": "k_theta<float> / k_theta_l (autotuned per shape)", "tridiag": "k_tridiag<256, 6, 2, 512, 4>", "tridiag_s": "k_tridiag<128, 8, 2, 512, 4>",
-          "tridiag_l": "k_tridiag<512, 4, 2, 512, 1>", "backtransform": "k_bt_tfac + k_bt_panel<256, 512>",
+KERNEL = {"theta": "k_theta<float> / k_theta_l (autotuned per shape)", "tridiag": "k_tridiag<256, 6, 2, 512, 4, true>",
+          "tridiag_s": "k_tridiag<128, 8, 2, 512, 4, false>",
+          "tridiag_l": "k_tridiag<512, 4, 2, 512, 1, true>", "backtransform": "k_bt_tfac + k_bt_panel<256, 512>",
           "backtransform_l": "k_bt_tfac + k_bt_panel<512, 512>", "tri_eig": "k_tri_eig"}
 TRIDIAG = {"tridiag_s": (0, 128), "tridiag": (129, 256), "tridiag_l": (257, 512)}
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}

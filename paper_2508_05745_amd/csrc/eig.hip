@@ -86,19 +86,35 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// q += V_r conj(W_c) + W_r conj(V_c), one complex element of a rank-2 update (fixed fma order)
+__device__ inline void rank2_acc(c64d& q, c64d vr, c64d wr, c64d vc, c64d wc) {
+  q.re = fma(vr.re, wc.re, q.re);
+  q.re = fma(vr.im, wc.im, q.re);
+  q.im = fma(vr.im, wc.re, q.im);
+  q.im = fma(-vr.re, wc.im, q.im);
+  q.re = fma(wr.re, vc.re, q.re);
+  q.re = fma(wr.im, vc.im, q.re);
+  q.im = fma(wr.im, vc.re, q.im);
+  q.im = fma(-wr.re, vc.im, q.im);
+}
+
 // ---------------------------------------------------------------------------- E1
 // Blocked Householder tridiagonalisation reading and writing only the lower triangle.
 // Panels of NB columns are reduced with the trailing matrix kept in the deferred form
 // A - 2 (V W^dag + W V^dag); each column needs one pass over the lower triangle of the
 // trailing matrix (the matrix-vector product), and the panel's rank-2NB update is applied
-// once at the end of the panel.  The panel vectors live in LDS (column-major by vector, so
+// once at the end of the panel, in the same pass as the next panel's first matrix-vector
+// product (so a panel of NB columns reads the trailing triangle NB times and writes it
+// once).  The panel vectors live in LDS (column-major by vector, so
 // that lanes read consecutive rows).  u_j is kept in column j below the diagonal.
 // One workgroup per matrix runs a chain of dependent steps per column, so the time per
 // matrix is set by latency rather than by HBM bandwidth: the row sums of the matrix-vector
 // product are reduced on the VALU (permlane swaps and DPP, no LDS round trips), column slots
 // past the trailing triangle are skipped, and WPE > 1 trades registers per wave for more
-// waves per SIMD (two 512-thread workgroups per CU for n <= 256).
-template <int NMAX, int NB, int RB, int NT, int WPE = 1>
+// waves per SIMD (two 512-thread workgroups per CU for n <= 256).  The n <= 128 instance
+// keeps the update as a pass of its own (FUSE = false): the fused pass's registers would cost
+// it a third workgroup per CU (measured 8% slower).
+template <int NMAX, int NB, int RB, int NT, int WPE = 1, bool FUSE = true>
 __global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ Ag, long long sA, double* __restrict__ ws,
                                                 long long sW, const int* __restrict__ active) {
   if (active && !active[blockIdx.x]) return;
@@ -123,11 +139,173 @@ __global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ A
   t = block_sum<NT>(t, red);
   if (tid == 0) tr[0] = t;
 
+  // The matrix-vector product below acts on column j, with m = n - j - 1 rows under the
+  // diagonal; u at the lane's columns is held in registers across a pass when there are at
+  // most 4 slots, read from LDS otherwise (register budget of the n <= 512 instance).
+  int j = 0, m = 0;
+  constexpr bool UK_REG = SLOTS <= 4 && NT <= 256;
+  c64d colacc[SLOTS], ukv[UK_REG ? SLOTS : 1];
+  auto start_product = [&]() {
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int kk = lane + 64 * s;
+      colacc[s] = c64d{0, 0};
+      if constexpr (UK_REG) ukv[s] = su[kk < m ? kk : 0];
+    }
+  };
+  // Row blocks of RB rows, NT / 64 * RB apart for a wave.  Slots past a block's last row
+  // hold no element of the lower triangle and are skipped (wave-uniform), so the work
+  // follows the triangle rather than NMAX.
+  auto load_block = [&](c64d (&buf)[RB][SLOTS], int ib) {
+    const int ns = (min(ib + RB, m) - 1) / 64 + 1;
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int i = ib + rr;
+      const c64d* row = A + (long long)(j + 1 + i) * n + (j + 1);
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        const int kk = lane + 64 * s;
+        buf[rr][s] = (s < ns && i < m && kk <= i) ? row[kk] : c64d{0, 0};
+      }
+    }
+  };
+  // p = (lower-stored Hermitian A22) u on a block of rows: row parts by the wave (the RB rows'
+  // sums into sp), column parts accumulated in registers (lane owns columns lane + 64 s).
+  // One element a = A[i][kk] (kk = lane + 64 s, zero outside the triangle):
+  auto mul_elem = [&](const c64d a, const c64d ui, int i, int s, double& pr, double& pim) {
+    const int kk = lane + 64 * s;
+    c64d uk;
+    if constexpr (UK_REG) uk = ukv[s];
+    else uk = su[kk < m ? kk : 0];
+    pr = fma(a.re, uk.re, pr);
+    pr = fma(-a.im, uk.im, pr);
+    pim = fma(a.re, uk.im, pim);
+    pim = fma(a.im, uk.re, pim);
+    // strictly lower elements also act on row kk through A[kk][i] = conj(A[i][kk])
+    const double cr = kk < i ? a.re : 0.0, ci = kk < i ? a.im : 0.0;
+    colacc[s].re = fma(cr, ui.re, colacc[s].re);
+    colacc[s].re = fma(ci, ui.im, colacc[s].re);
+    colacc[s].im = fma(cr, ui.im, colacc[s].im);
+    colacc[s].im = fma(-ci, ui.re, colacc[s].im);
+  };
+  // the row sums rs (re and im of each row of the block) over the wave, into sp: a
+  // reduce-scatter butterfly over the 2 RB sums, each exchange halving the values a lane
+  // carries (lanes 32..63, then odd rows, then lanes 8..15 of a row take the upper half), so
+  // lane group g = lane / (32 / RB) ends with the full sum of value g
+  auto store_rows = [&](double (&rs)[2 * RB], int ib) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      swap_halves(rs[q], rs[q + RB]);
+      rs[q] += rs[q + RB];
+    }
+#pragma unroll
+    for (int q = 0; q < RB / 2; ++q) {
+      swap_rows(rs[q], rs[q + RB / 2]);
+      rs[q] += rs[q + RB / 2];
+    }
+    if constexpr (RB == 4) {
+      const bool up = (lane & 8) != 0;
+      const double send = up ? rs[0] : rs[1];
+      rs[0] = (up ? rs[1] : rs[0]) + dpp_f64<0x128>(send);
+    } else {
+      rs[0] += dpp_f64<0x128>(rs[0]);
+    }
+    rs[0] = oct_sum(rs[0]);
+    if ((lane & (32 / RB - 1)) == 0) {
+      const int g = lane / (32 / RB);
+      if (ib + (g >> 1) < m) ((double*)&sp[ib + (g >> 1)])[g & 1] = rs[0];
+    }
+  };
+  auto mul_block = [&](const c64d (&buf)[RB][SLOTS], int ib) {
+    const int ns = (min(ib + RB, m) - 1) / 64 + 1;
+    double rs[2 * RB];
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int i = ib + rr;
+      const c64d ui = i < m ? su[i] : c64d{0, 0};
+      double pr = 0, pim = 0;
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s)
+        if (s < ns) mul_elem(buf[rr][s], ui, i, s, pr, pim);
+      rs[2 * rr] = pr;
+      rs[2 * rr + 1] = pim;
+    }
+    store_rows(rs, ib);
+  };
+  // the column parts of the waves into part[]: waves NPART.. add theirs in a second step
+  auto store_parts = [&]() {
+    if (wv < NPART) {
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        const int kk = lane + 64 * s;
+        if (kk < m) part[wv][kk] = colacc[s];
+      }
+    }
+  };
+  // Householder reflector of column j from its corrected part below the diagonal in su:
+  // u = (x + alpha e^{i arg x0} e_1) / |..| into su and column j of A, the subdiagonal
+  // element of T into ec[j]
+  auto reflect = [&]() {
+    double s2 = 0;
+    for (int i = tid; i < m; i += NT) s2 += norm2(su[i]);
+    s2 = block_sum<NT>(s2, red);
+    const double alpha = sqrt(s2);
+    const c64d x0 = su[0];
+    const double ax0 = sqrt(norm2(x0));
+    const bool skip = !(alpha > 1e-300);
+    const c64d ph = ax0 > 0 ? c64d{x0.re / ax0, x0.im / ax0} : c64d{1.0, 0.0};
+    const double vn = skip ? 1.0 : sqrt(2.0 * alpha * (alpha + ax0));
+    __syncthreads();
+    for (int i = tid; i < m; i += NT) {
+      c64d xi = su[i];
+      if (i == 0) xi = xi + alpha * ph;
+      c64d u = skip ? c64d{0, 0} : c64d{xi.re / vn, xi.im / vn};
+      su[i] = u;
+      A[(long long)(j + 1 + i) * n + j] = u;
+    }
+    if (tid == 0) ec[j] = skip ? x0 : c64d{-ph.re * alpha, -ph.im * alpha};
+  };
+  // w_k = p - (u^dag p) u with p = A22 u - 2 (V (W^dag u) + W (V^dag u)) over the panel's k
+  // earlier vectors (cdot holds their dot products with u), after the parts are stored
+  auto finish = [&](int k) {
+    if constexpr (NT / 64 > NPART) {
+      static_assert(NT / 64 <= 2 * NPART, "at most two waves per part row");
+      if (wv >= NPART) {
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+          const int kk = lane + 64 * s;
+          if (kk < m) part[wv - NPART][kk] = part[wv - NPART][kk] + colacc[s];
+        }
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < m; i += NT) {
+      c64d p = sp[i];
+#pragma unroll
+      for (int w = 0; w < NPART; ++w) p = p + part[w][i];
+      const int r = j + 1 + i;
+      for (int kk = 0; kk < k; ++kk) {
+        c64d corr = Vt[kk][r] * cdot[2 * kk + 1] + Wt[kk][r] * cdot[2 * kk];
+        p = p - 2.0 * corr;
+      }
+      sp[i] = p;
+    }
+    __syncthreads();
+    double kq = 0;
+    for (int i = tid; i < m; i += NT) kq += su[i].re * sp[i].re + su[i].im * sp[i].im;
+    kq = block_sum<NT>(kq, red);
+    for (int r = tid; r <= j; r += NT) Wt[k][r] = c64d{0, 0};
+    for (int i = tid; i < m; i += NT) Wt[k][j + 1 + i] = sp[i] - kq * su[i];
+    __syncthreads();
+  };
+
+  // first: the panel's column 0 was already reduced by the previous panel's fused pass
+  bool first_done = false;
   for (int j0 = 0; j0 + 2 < n; j0 += NB) {
     const int jb = min(NB, n - 2 - j0);
-    for (int k = 0; k < jb; ++k) {
-      const int j = j0 + k;
-      const int m = n - j - 1;
+    for (int k = first_done ? 1 : 0; k < jb; ++k) {
+      j = j0 + k;
+      m = n - j - 1;
       // corrected column j (rows j..n-1) -> su (rows j+1..) and the diagonal
       for (int r = j + tid; r < n; r += NT) {
         c64d a = A[(long long)r * n + j];
@@ -139,125 +317,17 @@ __global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ A
         else su[r - j - 1] = a;
       }
       __syncthreads();
-      double s2 = 0;
-      for (int i = tid; i < m; i += NT) s2 += norm2(su[i]);
-      s2 = block_sum<NT>(s2, red);
-      const double alpha = sqrt(s2);
-      const c64d x0 = su[0];
-      const double ax0 = sqrt(norm2(x0));
-      const bool skip = !(alpha > 1e-300);
-      const c64d ph = ax0 > 0 ? c64d{x0.re / ax0, x0.im / ax0} : c64d{1.0, 0.0};
-      const double vn = skip ? 1.0 : sqrt(2.0 * alpha * (alpha + ax0));
-      __syncthreads();
-      for (int i = tid; i < m; i += NT) {
-        c64d xi = su[i];
-        if (i == 0) xi = xi + alpha * ph;
-        c64d u = skip ? c64d{0, 0} : c64d{xi.re / vn, xi.im / vn};
-        su[i] = u;
-        A[(long long)(j + 1 + i) * n + j] = u;
-      }
+      reflect();
       for (int r = tid; r <= j; r += NT) Vt[k][r] = c64d{0, 0};
-      if (tid == 0) ec[j] = skip ? x0 : c64d{-ph.re * alpha, -ph.im * alpha};
       __syncthreads();
       for (int i = tid; i < m; i += NT) Vt[k][j + 1 + i] = su[i];
-      // p = (lower-stored Hermitian A22) u: row parts by waves (RB rows at a time, loads
-      // issued together), column parts accumulated in registers (lane owns columns
-      // lane + 64 s)
-      // u at the lane's columns: held in registers across the pass when there are at most 4
-      // slots, read from LDS otherwise (register budget of the n <= 512 instance)
-      constexpr bool UK_REG = SLOTS <= 4 && NT <= 256;
-      c64d colacc[SLOTS], ukv[UK_REG ? SLOTS : 1];
-#pragma unroll
-      for (int s = 0; s < SLOTS; ++s) {
-        const int kk = lane + 64 * s;
-        colacc[s] = c64d{0, 0};
-        if constexpr (UK_REG) ukv[s] = su[kk < m ? kk : 0];
-      }
-      // Row blocks of RB rows, NT / 64 * RB apart for a wave.  Slots past a block's last row
-      // hold no element of the lower triangle and are skipped (wave-uniform), so the work
-      // follows the triangle rather than NMAX.
-      auto load_block = [&](c64d (&buf)[RB][SLOTS], int ib) {
-        const int ns = (min(ib + RB, m) - 1) / 64 + 1;
-#pragma unroll
-        for (int rr = 0; rr < RB; ++rr) {
-          const int i = ib + rr;
-          const c64d* row = A + (long long)(j + 1 + i) * n + (j + 1);
-#pragma unroll
-          for (int s = 0; s < SLOTS; ++s) {
-            const int kk = lane + 64 * s;
-            buf[rr][s] = (s < ns && i < m && kk <= i) ? row[kk] : c64d{0, 0};
-          }
-        }
-      };
-      auto mul_block = [&](const c64d (&buf)[RB][SLOTS], int ib) {
-        const int ns = (min(ib + RB, m) - 1) / 64 + 1;
-        double rs[2 * RB];   // row sums: re and im of each row of the block
-#pragma unroll
-        for (int rr = 0; rr < RB; ++rr) {
-          const int i = ib + rr;
-          const c64d ui = i < m ? su[i] : c64d{0, 0};
-          double pr = 0, pim = 0;
-#pragma unroll
-          for (int s = 0; s < SLOTS; ++s) {
-            if (s < ns) {
-              const int kk = lane + 64 * s;
-              const c64d a = buf[rr][s];
-              c64d uk;
-              if constexpr (UK_REG) uk = ukv[s];
-              else uk = su[kk < m ? kk : 0];
-              pr = fma(a.re, uk.re, pr);
-              pr = fma(-a.im, uk.im, pr);
-              pim = fma(a.re, uk.im, pim);
-              pim = fma(a.im, uk.re, pim);
-              // strictly lower elements also act on row kk through A[kk][i] = conj(A[i][kk])
-              const double cr = kk < i ? a.re : 0.0, ci = kk < i ? a.im : 0.0;
-              colacc[s].re = fma(cr, ui.re, colacc[s].re);
-              colacc[s].re = fma(ci, ui.im, colacc[s].re);
-              colacc[s].im = fma(cr, ui.im, colacc[s].im);
-              colacc[s].im = fma(-ci, ui.re, colacc[s].im);
-            }
-          }
-          rs[2 * rr] = pr;
-          rs[2 * rr + 1] = pim;
-        }
-        // reduce-scatter butterfly over the 2 RB sums: each exchange halves the values a lane
-        // carries (lanes 32..63, then odd rows, then lanes 8..15 of a row take the upper
-        // half), so lane group g = lane / (32 / RB) ends with the full sum of value g
-#pragma unroll
-        for (int q = 0; q < RB; ++q) {
-          swap_halves(rs[q], rs[q + RB]);
-          rs[q] += rs[q + RB];
-        }
-#pragma unroll
-        for (int q = 0; q < RB / 2; ++q) {
-          swap_rows(rs[q], rs[q + RB / 2]);
-          rs[q] += rs[q + RB / 2];
-        }
-        if constexpr (RB == 4) {
-          const bool up = (lane & 8) != 0;
-          const double send = up ? rs[0] : rs[1];
-          rs[0] = (up ? rs[1] : rs[0]) + dpp_f64<0x128>(send);
-        } else {
-          rs[0] += dpp_f64<0x128>(rs[0]);
-        }
-        rs[0] = oct_sum(rs[0]);
-        if ((lane & (32 / RB - 1)) == 0) {
-          const int g = lane / (32 / RB);
-          if (ib + (g >> 1) < m) ((double*)&sp[ib + (g >> 1)])[g & 1] = rs[0];
-        }
-      };
+      start_product();
       for (int i0 = wv * RB; i0 < m; i0 += (NT / 64) * RB) {
         c64d av[RB][SLOTS];
         load_block(av, i0);
         mul_block(av, i0);
       }
-      if (wv < NPART) {
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-          const int kk = lane + 64 * s;
-          if (kk < m) part[wv][kk] = colacc[s];
-        }
-      }
+      store_parts();
       // dot products of the panel vectors with u (rows j+1..n-1)
       for (int dd = wv; dd < 2 * k; dd += NT / 64) {
         const int kk = dd >> 1;
@@ -274,40 +344,89 @@ __global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ A
         if (lane == 0) cdot[dd] = c64d{cr, ci};   // even: V^dag u, odd: W^dag u
       }
       __syncthreads();
-      if constexpr (NT / 64 > NPART) {
-        static_assert(NT / 64 <= 2 * NPART, "at most two waves per part row");
-        if (wv >= NPART) {
-#pragma unroll
-          for (int s = 0; s < SLOTS; ++s) {
-            const int kk = lane + 64 * s;
-            if (kk < m) part[wv - NPART][kk] = part[wv - NPART][kk] + colacc[s];
-          }
-        }
-        __syncthreads();
-      }
-      for (int i = tid; i < m; i += NT) {
-        c64d p = sp[i];
-#pragma unroll
-        for (int w = 0; w < NPART; ++w) p = p + part[w][i];
-        const int r = j + 1 + i;
-        for (int kk = 0; kk < k; ++kk) {
-          c64d corr = Vt[kk][r] * cdot[2 * kk + 1] + Wt[kk][r] * cdot[2 * kk];
-          p = p - 2.0 * corr;
-        }
-        sp[i] = p;
-      }
-      __syncthreads();
-      double kq = 0;
-      for (int i = tid; i < m; i += NT) kq += su[i].re * sp[i].re + su[i].im * sp[i].im;
-      kq = block_sum<NT>(kq, red);
-      for (int r = tid; r <= j; r += NT) Wt[k][r] = c64d{0, 0};
-      for (int i = tid; i < m; i += NT) Wt[k][j + 1 + i] = sp[i] - kq * su[i];
-      __syncthreads();
+      finish(k);
     }
     // trailing update of the lower triangle, rows/cols >= t0:
-    // A[r][c] -= 2 sum_k (V[r][k] conj(W[c][k]) + W[r][k] conj(V[c][k])), RB rows per wave and
-    // SLOTS columns per lane register-blocked
+    // A[r][c] -= 2 sum_k (V[r][k] conj(W[c][k]) + W[r][k] conj(V[c][k]))
     const int t0 = j0 + jb;
+    if (FUSE && t0 + 2 < n) {
+      // The next panel's first column is reduced here, fused with this update: column t0 of
+      // the updated matrix first (with the update's own arithmetic), its reflector, then one
+      // pass over the rows and columns past t0 that applies the update and accumulates the
+      // reflector's matrix-vector product from the updated values in registers.  This saves
+      // one read of the trailing triangle per panel; the results equal those of a separate
+      // update followed by the product, bit for bit.
+      j = t0;
+      m = n - t0 - 1;
+      for (int r = t0 + tid; r < n; r += NT) {
+        c64d acc{0, 0};
+        for (int kk = 0; kk < jb; ++kk) rank2_acc(acc, Vt[kk][r], Wt[kk][r], Vt[kk][t0], Wt[kk][t0]);
+        const c64d xo = A[(long long)r * n + t0];
+        const c64d a{fma(-2.0, acc.re, xo.re), fma(-2.0, acc.im, xo.im)};
+        if (r == t0) d[t0] = a.re;
+        else su[r - t0 - 1] = a;
+      }
+      __syncthreads();
+      reflect();
+      __syncthreads();
+      start_product();
+      for (int i0 = wv * RB; i0 < m; i0 += (NT / 64) * RB) {
+        const int ns = (min(i0 + RB, m) - 1) / 64 + 1;
+        double rs[2 * RB];
+        c64d ui[RB];
+        int rw[RB];
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+          const int i = i0 + rr;
+          ui[rr] = i < m ? su[i] : c64d{0, 0};
+          rw[rr] = min(t0 + 1 + i, n - 1);
+          rs[2 * rr] = 0;
+          rs[2 * rr + 1] = 0;
+        }
+        // slot by slot: the update of the RB rows' elements in this slot, then their
+        // contributions to the product (row sums and column parts in the same order as a
+        // separate product over the stored values)
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+          if (s < ns) {
+            const int kk = lane + 64 * s;
+            const int c = min(t0 + 1 + kk, n - 1);
+            c64d acc[RB];
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) acc[rr] = c64d{0, 0};
+            for (int q = 0; q < jb; ++q) {
+              const c64d vc = Vt[q][c], wc = Wt[q][c];
+#pragma unroll
+              for (int rr = 0; rr < RB; ++rr) rank2_acc(acc[rr], Vt[q][rw[rr]], Wt[q][rw[rr]], vc, wc);
+            }
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+              const int i = i0 + rr;
+              c64d a{0, 0};
+              if (i < m && kk <= i) {
+                c64d* x = A + (long long)(t0 + 1 + i) * n + (t0 + 1 + kk);
+                const c64d xo = *x;
+                a = c64d{fma(-2.0, acc[rr].re, xo.re), fma(-2.0, acc[rr].im, xo.im)};
+                *x = a;
+              }
+              mul_elem(a, ui[rr], i, s, rs[2 * rr], rs[2 * rr + 1]);
+            }
+          }
+        }
+        store_rows(rs, i0);
+      }
+      store_parts();
+      __syncthreads();
+      // the finished panel's vectors are no longer read: slot 0 takes the new reflector
+      for (int r = tid; r <= t0; r += NT) Vt[0][r] = c64d{0, 0};
+      for (int i = tid; i < m; i += NT) Vt[0][t0 + 1 + i] = su[i];
+      finish(0);
+      first_done = true;
+      continue;
+    }
+    first_done = false;
+    // the separate update (the last panel's, or every panel's without FUSE): rows/cols >= t0,
+    // RB rows per wave and SLOTS columns per lane register-blocked
     // rows per wave in the trailing update: RB, except for the small instance under a tight
     // register budget, where one row per wave leaves room to load ahead (measured faster)
     constexpr int RBT = (WPE > 1 && NMAX <= 128) ? 1 : RB;
@@ -337,24 +456,13 @@ __global__ __launch_bounds__(NT, WPE) void k_tridiag(int n, c64d* __restrict__ A
           vr[rr] = Vt[kk][r];
           wr[rr] = Wt[kk][r];
         }
-        // acc += V[r] conj(W[c]) + W[r] conj(V[c]), slot by slot
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           if (s < ns) {
             const int c = min(t0 + lane + 64 * s, n - 1);
             const c64d vc = Vt[kk][c], wc = Wt[kk][c];
 #pragma unroll
-            for (int rr = 0; rr < RBT; ++rr) {
-              c64d& q = acc[rr][s];
-              q.re = fma(vr[rr].re, wc.re, q.re);
-              q.re = fma(vr[rr].im, wc.im, q.re);
-              q.im = fma(vr[rr].im, wc.re, q.im);
-              q.im = fma(-vr[rr].re, wc.im, q.im);
-              q.re = fma(wr[rr].re, vc.re, q.re);
-              q.re = fma(wr[rr].im, vc.im, q.re);
-              q.im = fma(wr[rr].im, vc.re, q.im);
-              q.im = fma(-wr[rr].re, vc.im, q.im);
-            }
+            for (int rr = 0; rr < RBT; ++rr) rank2_acc(acc[rr][s], vr[rr], wr[rr], vc, wc);
           }
         }
       }
@@ -1266,7 +1374,7 @@ hipError_t heev_phase(int phase, int n, int keep, double zero_tol, void* A, long
   (void)sG;
   switch (phase) {
     case 0:
-      if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 8, 2, 512, 4>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW, active);
+      if (n <= 128) hipLaunchKernelGGL((k_tridiag<128, 8, 2, 512, 4, false>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW, active);
       else if (n <= 256) hipLaunchKernelGGL((k_tridiag<256, 6, 2, 512, 4>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW, active);
       else hipLaunchKernelGGL((k_tridiag<512, 4, 2, 512>), dim3(batch), dim3(512), 0, st, n, (c64d*)A, sA, ws, sW, active);
       break;
