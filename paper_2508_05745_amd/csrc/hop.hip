@@ -36,7 +36,7 @@ __global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int o
                                                  cplx<T>* __restrict__ Rout, long long sR, double tol) {
   __shared__ c64d R[NMAX * (NMAX + 1) / 2];
   __shared__ double piv[NMAX], ipiv[NMAX];   // pivots R[c][c] and their inverses (0 if dropped)
-  __shared__ c64d tcol[NMAX];                 // a column of R while it is inverted
+  __shared__ c64d tcol[NMAX];                 // a column of each diagonal block of R while it is inverted
   __shared__ double red[HT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const c64d* E = Eg + blockIdx.x * sE;
@@ -67,23 +67,22 @@ __global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int o
       const double p = R[pk(c, c, n)].re;
       const bool keep = p > cut && p > 0.0;
       const double r = keep ? sqrt(p) : 0.0;
-      __syncthreads();   // everyone has read the pivot before row c is rewritten
-      for (int k = c + tid; k < n; k += HT) {
+      // row c past the diagonal; the pivot itself is overwritten after the next barrier, once
+      // every thread has read it (nothing below reads it)
+      for (int k = c + 1 + tid; k < n; k += HT) {
         c64d v = R[pk(c, k, n)];
-        R[pk(c, k, n)] = keep ? (k == c ? c64d{r, 0.0} : c64d{v.re / r, v.im / r}) : c64d{0, 0};
+        R[pk(c, k, n)] = keep ? c64d{v.re / r, v.im / r} : c64d{0, 0};
       }
       if (tid == 0) {
         piv[c] = r;
         ipiv[c] = keep ? 1.0 / r : 0.0;
       }
       __syncthreads();
-      // rows c+1 .. c0+cb-1 of the panel: E[i][k] -= conj(R[c][i]) R[c][k], i <= k
+      if (tid == 0) R[pk(c, c, n)] = c64d{r, 0.0};
+      // rows c+1 .. c0+cb-1 of the panel, a wave per row: E[i][k] -= conj(R[c][i]) R[c][k], k >= i
       if (keep) {
-        const int rows = c0 + cb - (c + 1), m = n - (c + 1);
-        for (int e = tid; e < rows * m; e += HT) {
-          const int i = c + 1 + e / m, k = c + 1 + e % m;
-          if (k >= i) R[pk(i, k, n)] = R[pk(i, k, n)] - cmulc(R[pk(c, i, n)], R[pk(c, k, n)]);
-        }
+        for (int i = c + 1 + wv; i < c0 + cb; i += HT / 64)
+          for (int k = i + lane; k < n; k += 64) R[pk(i, k, n)] = R[pk(i, k, n)] - cmulc(R[pk(c, i, n)], R[pk(c, k, n)]);
       }
     }
     __syncthreads();
@@ -132,47 +131,118 @@ __global__ __launch_bounds__(HT) void k_hop_chol(int n, int left_to_right, int o
       c64d v = k >= i ? R[pk(i, k, n)] : c64d{0, 0};
       Ro[(long long)i * n + k] = cplx<T>{(T)v.re, (T)v.im};
     }
-  // R^{-1} in place (upper triangle, packed), column by column: column j of the inverse is
-  // -(1 / R[j][j]) Rinv[0:j, 0:j] R[0:j, j]; a dropped pivot gives a zero row and column, so
-  // the products below leave those directions out exactly as the substitution would
+  // R^{-1} in place (upper triangle, packed), by 16 x 16 blocks.  For R = [[A, B], [0, C]] the
+  // inverse is [[A^-1, -(A^-1 B) C^-1], [0, C^-1]]: the diagonal blocks are inverted together,
+  // column by column (column jj of a block's inverse is -(1 / R[j][j]) X[., 0:jj] R[0:jj, jj]
+  // within the block), then block column J above the diagonal becomes -(X[0:a, 0:a] R[0:a, J])
+  // X_JJ with a = 16 J, for J = 1, 2, ... in turn.  A dropped pivot (1 / R[j][j] taken as 0)
+  // gives a zero row and column, so the products below leave those directions out exactly as
+  // the substitution would.
   __syncthreads();   // R has been written out
-  // four lanes per row i (a DPP quad), each with two independent accumulation chains
-  static_assert(HT >= 4 * NMAX, "four lanes per row of the inverse");
-  for (int j = 0; j < n; ++j) {
-    for (int i = tid; i < j; i += HT) tcol[i] = R[pk(i, j, n)];
-    __syncthreads();
-    const double dj = ipiv[j];
-    const int i = tid >> 2, part = tid & 3;
-    double yr0 = 0.0, yi0 = 0.0, yr1 = 0.0, yi1 = 0.0;
-    if (i < j) {
-      const int base = pk(i, i, n) - i;   // Rinv[i][l] = R[base + l], l >= i
-      int l = i + part;
-      for (; l + 4 < j; l += 8) {
-        const c64d a0 = R[base + l], x0 = tcol[l], a1 = R[base + l + 4], x1 = tcol[l + 4];
-        yr0 = fma(a0.re, x0.re, yr0);
-        yr0 = fma(-a0.im, x0.im, yr0);
-        yi0 = fma(a0.re, x0.im, yi0);
-        yi0 = fma(a0.im, x0.re, yi0);
-        yr1 = fma(a1.re, x1.re, yr1);
-        yr1 = fma(-a1.im, x1.im, yr1);
-        yi1 = fma(a1.re, x1.im, yi1);
-        yi1 = fma(a1.im, x1.re, yi1);
+  const int nbk = (n + 15) / 16;
+  static_assert(HT >= 16 * (NMAX / 16), "a thread per row of every diagonal block");
+  {
+    const int b = tid >> 4, ii = tid & 15, r0 = 16 * b;
+    const int bs = b < nbk ? min(16, n - r0) : 0;
+    for (int jj = 0; jj < 16; ++jj) {
+      if (ii < jj && jj < bs) tcol[r0 + ii] = R[pk(r0 + ii, r0 + jj, n)];
+      __syncthreads();
+      if (jj < bs) {
+        const int i = r0 + ii, j = r0 + jj;
+        const double dj = ipiv[j];
+        if (ii < jj) {
+          double yr0 = 0.0, yi0 = 0.0, yr1 = 0.0, yi1 = 0.0;
+          int l = ii;
+          for (; l + 1 < jj; l += 2) {
+            const c64d a0 = R[pk(i, r0 + l, n)], x0 = tcol[r0 + l], a1 = R[pk(i, r0 + l + 1, n)], x1 = tcol[r0 + l + 1];
+            yr0 = fma(a0.re, x0.re, yr0);
+            yr0 = fma(-a0.im, x0.im, yr0);
+            yi0 = fma(a0.re, x0.im, yi0);
+            yi0 = fma(a0.im, x0.re, yi0);
+            yr1 = fma(a1.re, x1.re, yr1);
+            yr1 = fma(-a1.im, x1.im, yr1);
+            yi1 = fma(a1.re, x1.im, yi1);
+            yi1 = fma(a1.im, x1.re, yi1);
+          }
+          if (l < jj) {
+            const c64d a0 = R[pk(i, r0 + l, n)], x0 = tcol[r0 + l];
+            yr0 = fma(a0.re, x0.re, yr0);
+            yr0 = fma(-a0.im, x0.im, yr0);
+            yi0 = fma(a0.re, x0.im, yi0);
+            yi0 = fma(a0.im, x0.re, yi0);
+          }
+          R[pk(i, j, n)] = c64d{-dj * (yr0 + yr1), -dj * (yi0 + yi1)};
+        } else if (ii == jj) {
+          R[pk(j, j, n)] = c64d{dj, 0.0};
+        }
       }
-      if (l < j) {
-        const c64d a0 = R[base + l], x0 = tcol[l];
-        yr0 = fma(a0.re, x0.re, yr0);
-        yr0 = fma(-a0.im, x0.im, yr0);
-        yi0 = fma(a0.re, x0.im, yi0);
-        yi0 = fma(a0.im, x0.re, yi0);
-      }
+      __syncthreads();
     }
-    double yr = yr0 + yr1, yi = yi0 + yi1;
-    yr += quad_xor<0xB1>(yr);
-    yi += quad_xor<0xB1>(yi);
-    yr += quad_xor<0x4E>(yr);
-    yi += quad_xor<0x4E>(yi);
-    if (i < j && part == 0) R[pk(i, j, n)] = c64d{-dj * yr, -dj * yi};
-    if (tid == 0) R[pk(j, j, n)] = c64d{dj, 0.0};
+  }
+  // block columns J >= 1: element (i, jj) of the a x 16 block above the diagonal in thread
+  // (16 i + jj) mod HT, at most four per thread (a <= NMAX - 16)
+  constexpr int PER = ((NMAX - 16) * 16 + HT - 1) / HT;
+  for (int J = 1; J < nbk; ++J) {
+    const int a = 16 * J, cw = min(16, n - a);
+    c64d yv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + HT * q, i = e >> 4, jj = e & 15;
+      double yr0 = 0.0, yi0 = 0.0, yr1 = 0.0, yi1 = 0.0;
+      if (i < a && jj < cw) {
+        // Y[i][jj] = sum_{l = i}^{a-1} X[i][l] R[l][a + jj]
+        const int base = pk(i, i, n) - i;   // X[i][l] = R[base + l], l >= i
+        int l = i;
+        for (; l + 1 < a; l += 2) {
+          const c64d x0 = R[base + l], r0v = R[pk(l, a + jj, n)], x1 = R[base + l + 1], r1v = R[pk(l + 1, a + jj, n)];
+          yr0 = fma(x0.re, r0v.re, yr0);
+          yr0 = fma(-x0.im, r0v.im, yr0);
+          yi0 = fma(x0.re, r0v.im, yi0);
+          yi0 = fma(x0.im, r0v.re, yi0);
+          yr1 = fma(x1.re, r1v.re, yr1);
+          yr1 = fma(-x1.im, r1v.im, yr1);
+          yi1 = fma(x1.re, r1v.im, yi1);
+          yi1 = fma(x1.im, r1v.re, yi1);
+        }
+        if (l < a) {
+          const c64d x0 = R[base + l], r0v = R[pk(l, a + jj, n)];
+          yr0 = fma(x0.re, r0v.re, yr0);
+          yr0 = fma(-x0.im, r0v.im, yr0);
+          yi0 = fma(x0.re, r0v.im, yi0);
+          yi0 = fma(x0.im, r0v.re, yi0);
+        }
+      }
+      yv[q] = c64d{yr0 + yr1, yi0 + yi1};
+    }
+    __syncthreads();   // block column J of R has been read
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + HT * q, i = e >> 4, jj = e & 15;
+      if (i < a && jj < cw) R[pk(i, a + jj, n)] = yv[q];
+    }
+    __syncthreads();
+    // X[i][a + jj] = -sum_{m <= jj} Y[i][m] X_JJ[m][jj]
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + HT * q, i = e >> 4, jj = e & 15;
+      double xr = 0.0, xi = 0.0;
+      if (i < a && jj < cw) {
+        for (int m = 0; m <= jj; ++m) {
+          const c64d y = R[pk(i, a + m, n)], z = R[pk(a + m, a + jj, n)];
+          xr = fma(y.re, z.re, xr);
+          xr = fma(-y.im, z.im, xr);
+          xi = fma(y.re, z.im, xi);
+          xi = fma(y.im, z.re, xi);
+        }
+      }
+      yv[q] = c64d{-xr, -xi};
+    }
+    __syncthreads();   // Y has been read
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + HT * q, i = e >> 4, jj = e & 15;
+      if (i < a && jj < cw) R[pk(i, a + jj, n)] = yv[q];
+    }
     __syncthreads();
   }
   // Q = C R^{-1} (L->R, C: other x n, row-major) or Q = R^{-dag} C (R->L, C: n x other), in
